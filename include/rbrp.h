@@ -1,0 +1,181 @@
+/*
+ * rbrp.h -- C ABI of an MI355X (gfx950) library for adaptive robust blockwise
+ * random pivoting (RBRP) interpolative decompositions.
+ *
+ * Method: Dong, Chen, Martinsson, Pearce, "Robust blockwise random pivoting:
+ * fast and accurate adaptive interpolative decomposition", arXiv:2309.16002.
+ * The library computes a row interpolative decomposition X ~= W X(S,:) (the
+ * (r, eps)-ID problem statement, eq. id) with the skeletons S chosen by
+ * Algorithm 2 and W = X X_S^+ (eq. stable_id) obtained from Algorithm 3.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are row-major with a leading dimension (elements between row
+ *   starts) >= the number of columns.  The paper's n x d data matrix is
+ *   m x n here: m rows (data points), n columns (features).
+ * - Pointers are DEVICE pointers unless the argument name ends in _host.
+ *   The caller owns every buffer; the library keeps no pointer after return.
+ * - ``stream`` is a hipStream_t passed as void* (NULL = the null stream).
+ *   All device work is ordered on that stream.
+ * - Arguments are validated before any device work is issued.  On
+ *   RBRP_E_INVALID / RBRP_E_WORKSPACE nothing is written anywhere.
+ * - No entry point allocates device memory: every scratch buffer lives in the
+ *   caller-provided workspace (size from rbrp_workspace_size).  The library
+ *   holds one small pinned host buffer per process for the per-block stop
+ *   test.
+ * - Calls that share a workspace must not overlap; distinct workspaces on
+ *   distinct streams are independent.
+ */
+#ifndef RBRP_H_
+#define RBRP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RBRP_OK = 0,
+  RBRP_E_INVALID = 1,     /* an argument is out of range or a pointer is NULL */
+  RBRP_E_WORKSPACE = 2,   /* ws_bytes < rbrp_workspace_size(...)               */
+  RBRP_E_HIP = 3,         /* a HIP runtime call failed                        */
+  RBRP_E_NONFINITE = 4,   /* X holds a NaN or an infinity                     */
+  RBRP_E_CAPACITY = 5,    /* the tolerance was not met within k_max skeletons;
+                             S, k and W describe the k_max skeletons chosen   */
+  RBRP_E_UNSUPPORTED = 6  /* a valid combination this build does not provide  */
+} rbrp_status;
+
+typedef enum { RBRP_F32 = 0, RBRP_F64 = 1 } rbrp_dtype;
+
+/* Arithmetic of the two deflation GEMMs R Q' and (R Q') Q'^T.
+ * NATIVE: the input's type on MFMA (FP64 for F64 input; FP32 for F32 input,
+ *         the "plain" single-precision form).
+ * BF16:   BF16 MFMA operands with FP32 accumulation on an FP32 residual;
+ *         split into hi+lo BF16 parts (three products) while the tracked
+ *         relative residual is above theta, one BF16 product below it.
+ * In every mode the residual norms, the projection and reorthogonalisation
+ * of the basis, the block CPQR and the solve for W are FP64. */
+typedef enum { RBRP_PREC_NATIVE = 0, RBRP_PREC_BF16 = 1 } rbrp_precision;
+
+typedef struct {
+  double tau_b;        /* filter tolerance of Alg. 2 (Remark 4.2); <= 0 -> 1/b  */
+  int64_t k_max;       /* capacity of S and W; <= 0 -> min(m, n)                */
+  int32_t fixed_rank;  /* 1: ignore eps and stop at |S| = k_max (Alg. 2, "or k") */
+  int32_t greedy;      /* 1: take the b largest residual norms instead of
+                          sampling (RBGP, Remark 4.3)                           */
+  int32_t precision;   /* rbrp_precision                                         */
+  int32_t w_refine;    /* refinement steps of the W solve; < 0 -> 1              */
+  double theta;        /* BF16 mode: split/plain switch; <= 0 -> 25 * eps        */
+} rbrp_options;
+
+/* Per-call statistics (optional, host memory). */
+typedef struct {
+  int32_t blocks;          /* T, the number of sampled blocks                 */
+  int32_t blocks_split;    /* BF16 mode: blocks deflated with hi+lo products  */
+  double resid_tracked;    /* sqrt(||d||_1 / ||d^(0)||_1) at exit             */
+  double norm_x_fro;       /* ||X||_F                                         */
+  int32_t bprime[256];     /* b' of the first 256 blocks                       */
+} rbrp_stats;
+
+/* Fill *opt with the defaults (tau_b = 1/b, k_max = min(m, n), sampling,
+ * NATIVE precision, one refinement step). */
+void rbrp_default_options(rbrp_options* opt);
+
+/* Bytes of device workspace rbrp_id needs for these arguments (0 when the
+ * arguments are invalid). */
+size_t rbrp_workspace_size(rbrp_dtype dtype, int64_t m, int64_t n, int32_t b,
+                           const rbrp_options* opt);
+
+/*
+ * Row interpolative decomposition by RBRP (Algorithm 2, then Algorithm 3).
+ *
+ * Computes skeleton rows S and W with X ~= W X(S,:), stopping at the first
+ * block boundary where ||X - W X(S,:)||_F <= eps ||X||_F as tracked by the
+ * residual squared row norms (Alg. 2 stopping rule with tau = eps^2; the
+ * rank-adaptive property of the paper's introduction).
+ *
+ * X      [m x n], ld ldx, dtype F32 or F64; read only.
+ * eps    relative Frobenius tolerance, 0 < eps < 1 (ignored if fixed_rank).
+ * b      block size, 1 <= b <= 128.
+ * seed   key of the Philox4x64-10 stream: candidate j of block t draws word 0
+ *        of Philox(counter = (j, t, 0, 0), key = (seed, 0)).
+ * opt    NULL for defaults.
+ * S      [k_max] int64: skeleton row indices (0-based) in selection order.
+ * k_host host int64: k = |S|.
+ * W      [m x k_max] FP64, ld ldw >= k_max: W(S(j), :) = e_j^T; columns >= k
+ *        are left untouched.  May be NULL to skip the interpolation matrix.
+ * stats_host optional (NULL allowed).
+ * workspace, ws_bytes  device scratch of at least rbrp_workspace_size bytes.
+ *
+ * The call blocks the host once per block (to read the stop test) and
+ * returns after the stream has finished the call's work.
+ */
+rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n,
+                    int64_t ldx, double eps, int32_t b, uint64_t seed,
+                    const rbrp_options* opt, int64_t* S, int64_t* k_host,
+                    double* W, int64_t ldw, rbrp_stats* stats_host,
+                    void* workspace, size_t ws_bytes, void* stream);
+
+/* Static text for a status code. */
+const char* rbrp_status_string(rbrp_status s);
+
+/* ---- single-step entry points (the steps of Algorithm 2 in isolation) ---- */
+
+/*
+ * Squared row norms d_i = ||x_i||^2 of Alg. 2's initialisation, accumulated
+ * in FP64 from X of type dtype.  d [m] FP64.  Also returns, on the host,
+ * sum_i d_i and max_i d_i (either pointer may be NULL).  Fails with
+ * RBRP_E_NONFINITE if X holds a NaN or infinity.  workspace of at least
+ * rbrp_row_norms_workspace_size(m) bytes.
+ */
+size_t rbrp_row_norms_workspace_size(int64_t m);
+rbrp_status rbrp_row_norms(const void* X, rbrp_dtype dtype, int64_t m,
+                           int64_t n, int64_t ldx, double* d,
+                           double* sum_host, double* max_host,
+                           void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Block sampling of Alg. 2: up to b distinct indices drawn without
+ * replacement from d / ||d||_1, excluding rows with excluded[i] != 0 (may be
+ * NULL).  d [m] FP64 (entries <= 0 have no mass), excluded [m] uint8.
+ * Fixed-point weights w_i = floor(max(d_i,0) 2^s), s = 62 - e - ceil(log2 m)
+ * where max d = f 2^e, f in [0.5, 1); candidate j maps Philox word x_j to the
+ * smallest i with C_i > floor(x_j W / 2^64) (C the inclusive prefix of w);
+ * first occurrences are accepted; after 32 b candidates the accepted rows are
+ * removed from the CDF and each further candidate is accepted.  If at most b
+ * rows have positive weight they are all returned in index order.
+ * idx [b] int64 device, n_host: number written.  ``ident`` is counter word 2.
+ * workspace of at least rbrp_sample_workspace_size(m) bytes.
+ */
+size_t rbrp_sample_workspace_size(int64_t m);
+rbrp_status rbrp_sample_block(const double* d, const uint8_t* excluded,
+                              int64_t m, int32_t b, uint64_t seed, uint64_t t,
+                              uint64_t ident, int64_t* idx, int32_t* n_host,
+                              void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Robust blockwise filter of Alg. 2 (local CPQR + truncation, Remark 4.2) on
+ * one block.  Vt [nb x n] FP64, ld ldv: row j is column j of the paper's V
+ * (the residual of the j-th sampled row).  Pivot = largest remaining residual
+ * norm, ties to the lowest j; b' = max{i : ||R_V(i:nb,i:nb)||_F^2 >=
+ * tau_b ||R_V||_F^2 (1 - 4 nb 2^-53)}.
+ * piv [nb] int32 (first b' entries meaningful), R [nb x nb] FP64 row-major:
+ * the first b' rows of R_V in pivoted column order (upper triangular part),
+ * Qt [nb x n] FP64 ld ldq: first b' rows = orthonormal basis of the kept
+ * columns (Q_V(:,1:b')^T, signs with positive diagonal of R_V).
+ * bprime_host: b'.  1 <= nb <= 128.
+ */
+size_t rbrp_block_cpqr_workspace_size(int64_t n, int32_t nb);
+rbrp_status rbrp_block_cpqr(const double* Vt, int64_t n, int32_t nb,
+                            int64_t ldv, double tau_b, int32_t* piv,
+                            double* R, double* Qt, int64_t ldq,
+                            int32_t* bprime_host, void* workspace,
+                            size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBRP_H_ */

@@ -1,0 +1,12 @@
+"""MI355X (gfx950) implementation of robust blockwise random pivoting (RBRP)
+for the interpolative decomposition (Dong, Chen, Martinsson, Pearce,
+arXiv:2309.16002).
+
+The computation runs in the HIP library ``lib/librbrp.so`` (C ABI in
+``include/rbrp.h``); this package is its thin Python binding.
+"""
+
+from ._binding import (  # noqa: F401
+    LIB_PATH, IDResult, RBRPError, block_cpqr, lib, rbrp_id, row_norms, sample_block,
+    status_string, workspace_size,
+)

@@ -1,0 +1,263 @@
+"""ctypes binding of the RBRP C ABI (include/rbrp.h).
+
+Argument marshalling only: PyTorch provides device memory (outputs and the
+workspace) and the current stream; every step of the decomposition runs in
+the library's HIP kernels.  The library must have been built
+(``paper_2309_16002_amd.build``); nothing here falls back to other code.
+"""
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "librbrp.so")
+
+RBRP_OK = 0
+RBRP_E_INVALID = 1
+RBRP_E_WORKSPACE = 2
+RBRP_E_HIP = 3
+RBRP_E_NONFINITE = 4
+RBRP_E_CAPACITY = 5
+RBRP_E_UNSUPPORTED = 6
+
+RBRP_F32 = 0
+RBRP_F64 = 1
+PRECISIONS = {"native": 0, "bf16": 1}
+
+
+class rbrp_options(ctypes.Structure):
+    _fields_ = [
+        ("tau_b", ctypes.c_double),
+        ("k_max", ctypes.c_int64),
+        ("fixed_rank", ctypes.c_int32),
+        ("greedy", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("w_refine", ctypes.c_int32),
+        ("theta", ctypes.c_double),
+    ]
+
+
+class rbrp_stats(ctypes.Structure):
+    _fields_ = [
+        ("blocks", ctypes.c_int32),
+        ("blocks_split", ctypes.c_int32),
+        ("resid_tracked", ctypes.c_double),
+        ("norm_x_fro", ctypes.c_double),
+        ("bprime", ctypes.c_int32 * 256),
+    ]
+
+
+class RBRPError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} (status {status})")
+
+
+_lib = None
+
+_c = ctypes
+_vp, _i64, _i32, _u64, _dbl, _sz = (_c.c_void_p, _c.c_int64, _c.c_int32, _c.c_uint64,
+                                    _c.c_double, _c.c_size_t)
+
+# name -> (restype, argtypes); the exported C ABI
+SIGNATURES = {
+    "rbrp_default_options": (None, [_c.POINTER(rbrp_options)]),
+    "rbrp_workspace_size": (_sz, [_c.c_int, _i64, _i64, _i32, _c.POINTER(rbrp_options)]),
+    "rbrp_id": (_c.c_int, [_vp, _c.c_int, _i64, _i64, _i64, _dbl, _i32, _u64,
+                           _c.POINTER(rbrp_options), _vp, _c.POINTER(_i64), _vp, _i64,
+                           _c.POINTER(rbrp_stats), _vp, _sz, _vp]),
+    "rbrp_status_string": (_c.c_char_p, [_c.c_int]),
+    "rbrp_row_norms_workspace_size": (_sz, [_i64]),
+    "rbrp_row_norms": (_c.c_int, [_vp, _c.c_int, _i64, _i64, _i64, _vp,
+                                  _c.POINTER(_dbl), _c.POINTER(_dbl), _vp, _sz, _vp]),
+    "rbrp_sample_workspace_size": (_sz, [_i64]),
+    "rbrp_sample_block": (_c.c_int, [_vp, _vp, _i64, _i32, _u64, _u64, _u64, _vp,
+                                     _c.POINTER(_i32), _vp, _sz, _vp]),
+    "rbrp_block_cpqr_workspace_size": (_sz, [_i64, _i32]),
+    "rbrp_block_cpqr": (_c.c_int, [_vp, _i64, _i32, _i64, _dbl, _vp, _vp, _vp, _i64,
+                                   _c.POINTER(_i32), _vp, _sz, _vp]),
+}
+
+
+def lib():
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"RBRP HIP library not built: {LIB_PATH} is missing "
+                "(run python -m paper_2309_16002_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(status):
+    return lib().rbrp_status_string(int(status)).decode()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return RBRP_F32
+    if t.dtype == torch.float64:
+        return RBRP_F64
+    raise TypeError(f"unsupported dtype {t.dtype}: use float32 or float64")
+
+
+def _ld(t):
+    """Leading dimension of a row-major 2-D tensor (a single row may carry any
+    row stride)."""
+    return t.stride(0) if t.shape[0] > 1 else t.shape[1]
+
+
+def _check_matrix(X):
+    if not X.is_cuda:
+        raise ValueError("X must be a GPU tensor")
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be a 2-D row-major tensor (unit column stride)")
+
+
+def make_options(k_max=0, tau_b=0.0, fixed_rank=False, greedy=False, precision="native",
+                 theta=0.0, w_refine=1):
+    o = rbrp_options()
+    lib().rbrp_default_options(ctypes.byref(o))
+    o.tau_b = float(tau_b)
+    o.k_max = int(k_max)
+    o.fixed_rank = int(bool(fixed_rank))
+    o.greedy = int(bool(greedy))
+    o.precision = PRECISIONS[precision]
+    o.theta = float(theta)
+    o.w_refine = int(w_refine)
+    return o
+
+
+@dataclass
+class IDResult:
+    S: object            # int64 tensor [k], selection order
+    k: int
+    W: object            # float64 tensor [m, k] or None
+    status: int
+    blocks: int
+    blocks_split: int
+    bprime: list
+    resid_tracked: float
+    norm_x: float
+
+
+def workspace_size(m, n, b, dtype="f32", **opts):
+    o = make_options(**opts)
+    dt = RBRP_F32 if dtype in ("f32", "float32") else RBRP_F64
+    return int(lib().rbrp_workspace_size(dt, int(m), int(n), int(b), ctypes.byref(o)))
+
+
+def rbrp_id(X, eps, b, seed=0, *, want_w=True, workspace=None, **opts):
+    """Row ID X ~= W X[S] by RBRP (Algorithm 2, then Algorithm 3)."""
+    torch = _torch()
+    _check_matrix(X)
+    L = lib()
+    m, n = X.shape
+    dt = _dtype_code(X)
+    o = make_options(**opts)
+    ws_bytes = L.rbrp_workspace_size(dt, m, n, int(b), ctypes.byref(o))
+    if ws_bytes == 0:
+        raise RBRPError(RBRP_E_INVALID, "rbrp_workspace_size")
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=X.device)
+    k_max = o.k_max if o.k_max > 0 else min(m, n)
+    S = torch.empty(k_max, dtype=torch.int64, device=X.device)
+    W = torch.empty((m, k_max), dtype=torch.float64, device=X.device) if want_w else None
+    k = ctypes.c_int64(0)
+    st = rbrp_stats()
+    status = L.rbrp_id(_ptr(X), dt, m, n, _ld(X), float(eps), int(b), int(seed),
+                       ctypes.byref(o), _ptr(S), ctypes.byref(k), _ptr(W), k_max,
+                       ctypes.byref(st), _ptr(workspace), ws_bytes, _stream_ptr(X.device))
+    if status not in (RBRP_OK, RBRP_E_CAPACITY):
+        raise RBRPError(status, "rbrp_id")
+    kk = int(k.value)
+    nb = min(st.blocks, 256)
+    return IDResult(S[:kk], kk, W[:, :kk] if W is not None else None, status, st.blocks,
+                    st.blocks_split, [int(x) for x in st.bprime[:nb]], st.resid_tracked,
+                    st.norm_x_fro)
+
+
+def row_norms(X):
+    """d_i = ||x_i||^2 in FP64 (Alg. 2 initialisation); returns (d, sum, max)."""
+    torch = _torch()
+    _check_matrix(X)
+    L = lib()
+    m, n = X.shape
+    d = torch.empty(m, dtype=torch.float64, device=X.device)
+    ws_bytes = L.rbrp_row_norms_workspace_size(m)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=X.device)
+    s, mx = ctypes.c_double(0), ctypes.c_double(0)
+    status = L.rbrp_row_norms(_ptr(X), _dtype_code(X), m, n, _ld(X), _ptr(d),
+                              ctypes.byref(s), ctypes.byref(mx), _ptr(ws), ws_bytes,
+                              _stream_ptr(X.device))
+    if status != RBRP_OK:
+        raise RBRPError(status, "rbrp_row_norms")
+    return d, s.value, mx.value
+
+
+def sample_block(d, excluded, b, seed, t, ident=0):
+    """One block of Alg. 2's sampler; returns an int64 tensor of indices."""
+    torch = _torch()
+    L = lib()
+    if d.dtype != torch.float64 or not d.is_cuda or d.dim() != 1:
+        raise ValueError("d must be a 1-D float64 GPU tensor")
+    d = d.contiguous()
+    m = d.shape[0]
+    ex = None
+    if excluded is not None:
+        ex = excluded.to(device=d.device, dtype=torch.uint8).contiguous()
+    idx = torch.empty(max(int(b), 1), dtype=torch.int64, device=d.device)
+    ws_bytes = L.rbrp_sample_workspace_size(m)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=d.device)
+    nout = ctypes.c_int32(0)
+    status = L.rbrp_sample_block(_ptr(d), _ptr(ex), m, int(b), int(seed), int(t), int(ident),
+                                 _ptr(idx), ctypes.byref(nout), _ptr(ws), ws_bytes,
+                                 _stream_ptr(d.device))
+    if status != RBRP_OK:
+        raise RBRPError(status, "rbrp_sample_block")
+    return idx[: nout.value]
+
+
+def block_cpqr(Vt, tau_b):
+    """Robust blockwise filter on one block (rows of Vt = columns of V).
+
+    Returns (piv int32 [nb], R float64 [nb, nb], Qt float64 [b', n], b')."""
+    torch = _torch()
+    L = lib()
+    if Vt.dtype != torch.float64 or not Vt.is_cuda or Vt.dim() != 2 or Vt.stride(1) != 1:
+        raise ValueError("Vt must be a 2-D row-major float64 GPU tensor")
+    nb, n = Vt.shape
+    piv = torch.empty(nb, dtype=torch.int32, device=Vt.device)
+    R = torch.empty((nb, nb), dtype=torch.float64, device=Vt.device)
+    Qt = torch.zeros((nb, n), dtype=torch.float64, device=Vt.device)
+    ws_bytes = L.rbrp_block_cpqr_workspace_size(n, nb)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=Vt.device)
+    bp = ctypes.c_int32(0)
+    status = L.rbrp_block_cpqr(_ptr(Vt), n, nb, _ld(Vt), float(tau_b), _ptr(piv), _ptr(R),
+                               _ptr(Qt), n, ctypes.byref(bp), _ptr(ws), ws_bytes,
+                               _stream_ptr(Vt.device))
+    if status != RBRP_OK:
+        raise RBRPError(status, "rbrp_block_cpqr")
+    return piv, R, Qt[: bp.value], int(bp.value)

@@ -1,0 +1,442 @@
+// C ABI of the RBRP library: argument validation, workspace layout, and the
+// host loop of Algorithm 2 (one stop test per block), followed by
+// Algorithm 3 for W.
+#include "rbrp_internal.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+namespace rbrp {
+hipError_t launch_cpqr_gram_ex(const double*, int64_t, int32_t, const int32_t*, double,
+                               int, const double*, int32_t*, double*, int64_t, double*,
+                               int32_t*, double*, int32_t*, hipStream_t);
+}
+
+using namespace rbrp;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+struct Carver {
+  size_t off = 0;
+  char* base = nullptr;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct Plan {
+  rbrp_dtype dt;
+  int64_t m, n, mr, ldr, k_max, ntiles, nparts;
+  int32_t b;
+  int native_mode;   // deflation mode of the NATIVE precision
+  bool bf16;
+  bool r_f64;
+};
+
+struct Work {
+  DevScalars* sc;
+  void* R;
+  double* d;
+  double* part_sum;
+  double* part_max;
+  int32_t* sel_block;
+  uint64_t* cdf;
+  uint64_t* tile_sum;
+  int32_t* tile_pos;
+  int64_t* idx;
+  double* xs2;
+  double* Vt;
+  double* C;
+  double* G;
+  int32_t* piv;
+  int32_t* piv2;
+  double* Rraw;
+  double* R2raw;
+  double* Qt;
+  void* fragB1;
+  void* fragA2;
+  void* L;
+  double* interp;
+};
+
+void fill_defaults(rbrp_options* o) {
+  memset(o, 0, sizeof(*o));
+  o->tau_b = 0.0;
+  o->k_max = 0;
+  o->fixed_rank = 0;
+  o->greedy = 0;
+  o->precision = RBRP_PREC_NATIVE;
+  o->w_refine = 1;
+  o->theta = 0.0;
+}
+
+bool make_plan(rbrp_dtype dt, int64_t m, int64_t n, int32_t b, const rbrp_options* opt,
+               Plan* p) {
+  if (dt != RBRP_F32 && dt != RBRP_F64) return false;
+  if (m <= 0 || n <= 0 || b < 1 || b > kMaxB) return false;
+  rbrp_options o;
+  if (opt) o = *opt; else fill_defaults(&o);
+  if (o.precision != RBRP_PREC_NATIVE && o.precision != RBRP_PREC_BF16) return false;
+  p->dt = dt;
+  p->m = m;
+  p->n = n;
+  p->b = b;
+  p->mr = round_up(m, kRowPad);
+  p->ldr = deflate_pad_cols(n);
+  if (p->ldr <= 0) return false;
+  p->k_max = (o.k_max > 0) ? o.k_max : (m < n ? m : n);
+  if (p->k_max > m || p->k_max > n) return false;
+  p->bf16 = o.precision == RBRP_PREC_BF16;
+  p->r_f64 = dt == RBRP_F64;
+  p->native_mode = p->r_f64 ? kModeF64 : kModeF32;
+  p->ntiles = scan_num_tiles(m);
+  const int64_t a = norms_num_partials(p->mr), c = deflate_num_partials(p->mr);
+  p->nparts = a > c ? a : c;
+  return true;
+}
+
+size_t layout(const Plan& p, char* base, Work* w) {
+  Carver cv;
+  cv.base = base;
+  const size_t rs = p.r_f64 ? sizeof(double) : sizeof(float);
+  const int mode = p.bf16 ? kModeBF16x3 : p.native_mode;
+  w->sc = cv.take<DevScalars>(1);
+  w->R = cv.take<char>((size_t)p.mr * p.ldr * rs);
+  w->d = cv.take<double>(p.mr);
+  w->part_sum = cv.take<double>(p.nparts);
+  w->part_max = cv.take<double>(p.nparts);
+  w->sel_block = cv.take<int32_t>(p.m);
+  w->cdf = cv.take<uint64_t>(p.m);
+  w->tile_sum = cv.take<uint64_t>(p.ntiles + 1);
+  w->tile_pos = cv.take<int32_t>(p.ntiles + 1);
+  w->idx = cv.take<int64_t>(kMaxB);
+  w->xs2 = cv.take<double>(kMaxB);
+  w->Vt = cv.take<double>((size_t)p.b * p.ldr);
+  w->C = cv.take<double>((size_t)p.k_max * p.b);
+  w->G = cv.take<double>((size_t)p.b * p.b);
+  w->piv = cv.take<int32_t>(kMaxB);
+  w->piv2 = cv.take<int32_t>(kMaxB);
+  w->Rraw = cv.take<double>((size_t)p.b * p.b);
+  w->R2raw = cv.take<double>((size_t)p.b * p.b);
+  w->Qt = cv.take<double>((size_t)p.k_max * p.ldr);
+  w->fragB1 = cv.take<char>(frag_bytes(mode, p.ldr, p.b));
+  w->fragA2 = cv.take<char>(frag_bytes(mode, p.ldr, p.b));
+  w->L = cv.take<char>((size_t)p.m * p.k_max * rs);
+  w->interp = cv.take<double>(interp_workspace_doubles(p.m, p.k_max));
+  return cv.off + kAlign;
+}
+
+// Pinned host copy of the device scalars (one per host thread).
+DevScalars* host_scalars() {
+  static thread_local DevScalars* h = nullptr;
+  if (!h) {
+    if (hipHostMalloc((void**)&h, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess)
+      h = nullptr;
+  }
+  return h;
+}
+
+#define RBRP_HIP(expr)                             \
+  do {                                             \
+    hipError_t e_ = (expr);                        \
+    if (e_ != hipSuccess) {                        \
+      if (getenv("RBRP_LOG"))                      \
+        fprintf(stderr, "rbrp: %s failed: %s (%s:%d)\n", #expr, hipGetErrorString(e_), \
+                __FILE__, __LINE__);               \
+      return RBRP_E_HIP;                           \
+    }                                              \
+  } while (0)
+
+rbrp_status fetch(DevScalars* h, const DevScalars* dsc, hipStream_t s) {
+  RBRP_HIP(hipMemcpyAsync(h, dsc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+  RBRP_HIP(hipStreamSynchronize(s));
+  return RBRP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void rbrp_default_options(rbrp_options* opt) {
+  if (opt) fill_defaults(opt);
+}
+
+const char* rbrp_status_string(rbrp_status s) {
+  switch (s) {
+    case RBRP_OK: return "ok";
+    case RBRP_E_INVALID: return "invalid argument";
+    case RBRP_E_WORKSPACE: return "workspace too small";
+    case RBRP_E_HIP: return "HIP runtime error";
+    case RBRP_E_NONFINITE: return "input holds NaN or Inf";
+    case RBRP_E_CAPACITY: return "tolerance not met within k_max skeletons";
+    case RBRP_E_UNSUPPORTED: return "unsupported combination";
+  }
+  return "unknown status";
+}
+
+size_t rbrp_workspace_size(rbrp_dtype dtype, int64_t m, int64_t n, int32_t b,
+                           const rbrp_options* opt) {
+  Plan p;
+  if (!make_plan(dtype, m, n, b, opt, &p)) return 0;
+  Work w;
+  return layout(p, nullptr, &w);
+}
+
+rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64_t ldx,
+                    double eps, int32_t b, uint64_t seed, const rbrp_options* opt,
+                    int64_t* S, int64_t* k_host, double* W, int64_t ldw,
+                    rbrp_stats* stats_host, void* workspace, size_t ws_bytes,
+                    void* stream) {
+  rbrp_options o;
+  if (opt) o = *opt; else fill_defaults(&o);
+  Plan p;
+  if (!X || !S || !k_host || !workspace) return RBRP_E_INVALID;
+  if (!make_plan(dtype, m, n, b, &o, &p)) return RBRP_E_INVALID;
+  if (ldx < n) return RBRP_E_INVALID;
+  if (!o.fixed_rank && !(eps > 0.0 && eps < 1.0)) return RBRP_E_INVALID;
+  if (W && ldw < p.k_max) return RBRP_E_INVALID;
+  if (p.bf16 && dtype != RBRP_F32) return RBRP_E_UNSUPPORTED;
+  const int mode_hi = p.bf16 ? kModeBF16x3 : p.native_mode;
+  const int mode_lo = p.bf16 ? kModeBF16 : p.native_mode;
+  if (!deflate_supported(mode_hi, p.ldr, b) || !deflate_supported(mode_lo, p.ldr, b))
+    return RBRP_E_UNSUPPORTED;
+  Work w;
+  const size_t need = layout(p, nullptr, &w);
+  if (ws_bytes < need) return RBRP_E_WORKSPACE;
+  layout(p, (char*)(((uintptr_t)workspace + kAlign - 1) / kAlign * kAlign), &w);
+  if (((uintptr_t)workspace % kAlign) != 0 && ws_bytes < need) return RBRP_E_WORKSPACE;
+
+  hipStream_t s = (hipStream_t)stream;
+  DevScalars* h = host_scalars();
+  if (!h) return RBRP_E_HIP;
+  const double tau_b = o.tau_b > 0.0 ? o.tau_b : 1.0 / b;
+  const double theta = o.theta > 0.0 ? o.theta : 25.0 * eps;
+  const int refine = o.w_refine < 0 ? 1 : o.w_refine;
+  const int64_t k_max = p.k_max;
+  const int64_t ldr = p.ldr;
+  rbrp_stats st;
+  memset(&st, 0, sizeof(st));
+
+  RBRP_HIP(hipMemsetAsync(w.sc, 0, sizeof(DevScalars), s));
+  RBRP_HIP(hipMemsetAsync(w.sel_block, 0xFF, sizeof(int32_t) * p.m, s));
+  RBRP_HIP(launch_init_norms(X, dtype, m, n, ldx, w.R, p.r_f64, p.mr, ldr, w.d,
+                             w.part_sum, w.part_max, &w.sc->nonfinite, s));
+  RBRP_HIP(launch_reduce(w.part_sum, w.part_max, norms_num_partials(p.mr), w.sc, 1, s));
+  rbrp_status rs = fetch(h, w.sc, s);
+  if (rs != RBRP_OK) return rs;
+  if (h->nonfinite) return RBRP_E_NONFINITE;
+  const double D0 = h->d0;
+  st.norm_x_fro = sqrt(D0);
+  *k_host = 0;
+  if (D0 == 0.0) {
+    st.resid_tracked = 0.0;
+    if (stats_host) *stats_host = st;
+    return RBRP_OK;
+  }
+  const double tau = eps * eps;
+  int64_t kS = 0;
+  int32_t t = 0;
+  rbrp_status final_status = RBRP_OK;
+  double sum_d = h->sum_d;
+  const int def_rows = deflate_rows_per_wg(mode_hi, ldr);
+  while (true) {
+    if (kS >= k_max) {
+      if (!o.fixed_rank && sum_d > tau * D0) final_status = RBRP_E_CAPACITY;
+      break;
+    }
+    if (!o.fixed_rank && !(sum_d > tau * D0)) break;
+    ++t;
+    const int32_t bt = (int32_t)((int64_t)b < k_max - kS ? b : k_max - kS);
+    // sampling (or greedy top-b)
+    if (o.greedy) {
+      RBRP_HIP(launch_topb(w.d, w.sel_block, m, bt, w.idx, w.sc, s));
+    } else {
+      RBRP_HIP(launch_weights_scan(w.d, w.sel_block, nullptr, m, w.sc, w.cdf, w.tile_sum,
+                                   w.tile_pos, s));
+      RBRP_HIP(launch_sample(w.cdf, w.tile_sum, w.tile_pos, m, bt, seed, (uint64_t)t, 0,
+                             w.idx, w.sc, s));
+    }
+    // V^T: sampled rows of X in FP64, projected twice against the basis
+    RBRP_HIP(launch_gather_rows(X, dtype, n, ldx, w.idx, w.sc, bt, w.Vt, ldr, w.xs2, s));
+    if (kS > 0) {
+      for (int pass = 0; pass < 2; ++pass) {
+        RBRP_HIP(launch_gemm_f64(0, 1, kS, bt, ldr, 1.0, w.Qt, 0, ldr, w.Vt, ldr, 0.0, w.C,
+                                 bt, nullptr, nullptr, 0, s));
+        RBRP_HIP(launch_gemm_f64(1, 0, bt, ldr, kS, -1.0, w.C, 0, bt, w.Qt, ldr, 1.0, w.Vt,
+                                 ldr, nullptr, nullptr, 0, s));
+      }
+    }
+    // robust blockwise filter: pivoted Cholesky of V^T V
+    RBRP_HIP(launch_gemm_f64(0, 1, bt, bt, ldr, 1.0, w.Vt, 0, ldr, w.Vt, ldr, 0.0, w.G, bt,
+                             nullptr, nullptr, 0, s));
+    RBRP_HIP(launch_cpqr_gram_ex(w.G, bt, bt, &w.sc->nt, tau_b, 1, w.xs2, w.piv, w.Rraw, bt,
+                                 nullptr, &w.sc->bprime, &w.sc->tail1, &w.sc->stop_rank, s));
+    double* Qn = w.Qt + kS * ldr;
+    RBRP_HIP(launch_qform(w.Vt, ldr, w.piv, w.Rraw, bt, &w.sc->bprime, bt, ldr, Qn, ldr, s));
+    // reorthogonalisation: project against the basis, then Cholesky QR
+    if (kS > 0) {
+      RBRP_HIP(launch_gemm_f64(0, 1, kS, bt, ldr, 1.0, w.Qt, 0, ldr, Qn, ldr, 0.0, w.C, bt,
+                               nullptr, &w.sc->bprime, 0, s));
+      RBRP_HIP(launch_gemm_f64(1, 0, bt, ldr, kS, -1.0, w.C, 0, bt, w.Qt, ldr, 1.0, Qn, ldr,
+                               &w.sc->bprime, nullptr, 0, s));
+    }
+    RBRP_HIP(launch_gemm_f64(0, 1, bt, bt, ldr, 1.0, Qn, 0, ldr, Qn, ldr, 0.0, w.G, bt,
+                             &w.sc->bprime, &w.sc->bprime, 0, s));
+    RBRP_HIP(launch_cpqr_gram_ex(w.G, bt, bt, &w.sc->bprime, 0.0, 0, nullptr, w.piv2, w.R2raw,
+                                 bt, nullptr, &w.sc->b2, nullptr, nullptr, s));
+    RBRP_HIP(launch_qform(Qn, ldr, nullptr, w.R2raw, bt, &w.sc->b2, bt, ldr, Qn, ldr, s));
+    RBRP_HIP(launch_append(w.idx, w.piv, &w.sc->bprime, kS, t, S, w.sel_block, s));
+    // deflation of the residual
+    int mode = p.native_mode;
+    if (p.bf16) {
+      const double rho = sqrt(sum_d / D0);
+      mode = rho > theta ? kModeBF16x3 : kModeBF16;
+      if (mode == kModeBF16x3) st.blocks_split++;
+    }
+    RBRP_HIP(launch_make_frags(Qn, ldr, &w.sc->bprime, ldr, b, mode, w.fragB1, w.fragA2, s));
+    RBRP_HIP(launch_deflate(mode, w.R, p.mr, ldr, m, w.fragB1, w.fragA2, &w.sc->bprime, b,
+                            w.L, k_max, kS, w.sel_block, t, w.d, w.part_sum, w.part_max, s));
+    RBRP_HIP(launch_reduce(w.part_sum, w.part_max, p.mr / def_rows, w.sc, 0, s));
+    rs = fetch(h, w.sc, s);
+    if (rs != RBRP_OK) return rs;
+    const int bp = h->bprime;
+    if (t <= 256) st.bprime[t - 1] = bp;
+    st.blocks = t;
+    if (h->stop_rank || bp <= 0) break;
+    if (h->b2 != bp) return RBRP_E_HIP;  // basis lost orthogonality beyond repair
+    kS += bp;
+    sum_d = h->sum_d;
+  }
+  *k_host = kS;
+  st.resid_tracked = sqrt(fmax(sum_d, 0.0) / D0);
+  if (W && kS > 0) {
+    RBRP_HIP(launch_interp(w.L, p.r_f64, k_max, m, kS, S, W, ldw, refine, w.interp, s));
+  }
+  RBRP_HIP(hipStreamSynchronize(s));
+  if (stats_host) *stats_host = st;
+  return final_status;
+}
+
+// ---- single-step entry points ----
+
+size_t rbrp_row_norms_workspace_size(int64_t m) {
+  if (m <= 0) return 0;
+  return 2 * kAlign + sizeof(DevScalars) + 2 * sizeof(double) * norms_num_partials(m);
+}
+
+rbrp_status rbrp_row_norms(const void* X, rbrp_dtype dtype, int64_t m, int64_t n,
+                           int64_t ldx, double* d, double* sum_host, double* max_host,
+                           void* workspace, size_t ws_bytes, void* stream) {
+  if (!X || !d || !workspace) return RBRP_E_INVALID;
+  if (dtype != RBRP_F32 && dtype != RBRP_F64) return RBRP_E_INVALID;
+  if (m <= 0 || n <= 0 || ldx < n) return RBRP_E_INVALID;
+  if (ws_bytes < rbrp_row_norms_workspace_size(m)) return RBRP_E_WORKSPACE;
+  Carver cv;
+  cv.base = (char*)(((uintptr_t)workspace + kAlign - 1) / kAlign * kAlign);
+  DevScalars* sc = cv.take<DevScalars>(1);
+  const int64_t np = norms_num_partials(m);
+  double* ps = cv.take<double>(np);
+  double* pm = cv.take<double>(np);
+  hipStream_t s = (hipStream_t)stream;
+  DevScalars* h = host_scalars();
+  if (!h) return RBRP_E_HIP;
+  RBRP_HIP(hipMemsetAsync(sc, 0, sizeof(DevScalars), s));
+  RBRP_HIP(launch_init_norms(X, dtype, m, n, ldx, nullptr, 0, m, 0, d, ps, pm,
+                             &sc->nonfinite, s));
+  RBRP_HIP(launch_reduce(ps, pm, np, sc, 1, s));
+  rbrp_status rs = fetch(h, sc, s);
+  if (rs != RBRP_OK) return rs;
+  if (h->nonfinite) return RBRP_E_NONFINITE;
+  if (sum_host) *sum_host = h->sum_d;
+  if (max_host) *max_host = h->max_d;
+  return RBRP_OK;
+}
+
+size_t rbrp_sample_workspace_size(int64_t m) {
+  if (m <= 0) return 0;
+  const int64_t np = masked_num_partials(m), nt = scan_num_tiles(m);
+  return 8 * kAlign + sizeof(DevScalars) + 2 * sizeof(double) * np +
+         sizeof(uint64_t) * m + (sizeof(uint64_t) + sizeof(int32_t)) * (nt + 1);
+}
+
+rbrp_status rbrp_sample_block(const double* d, const uint8_t* excluded, int64_t m,
+                              int32_t b, uint64_t seed, uint64_t t, uint64_t ident,
+                              int64_t* idx, int32_t* n_host, void* workspace,
+                              size_t ws_bytes, void* stream) {
+  if (!d || !idx || !n_host || !workspace) return RBRP_E_INVALID;
+  if (m <= 0 || b < 1 || b > kMaxB) return RBRP_E_INVALID;
+  if (scan_num_tiles(m) > 4096) return RBRP_E_UNSUPPORTED;
+  if (ws_bytes < rbrp_sample_workspace_size(m)) return RBRP_E_WORKSPACE;
+  Carver cv;
+  cv.base = (char*)(((uintptr_t)workspace + kAlign - 1) / kAlign * kAlign);
+  DevScalars* sc = cv.take<DevScalars>(1);
+  const int64_t np = masked_num_partials(m), nt = scan_num_tiles(m);
+  double* ps = cv.take<double>(np);
+  double* pm = cv.take<double>(np);
+  uint64_t* cdf = cv.take<uint64_t>(m);
+  uint64_t* ts = cv.take<uint64_t>(nt + 1);
+  int32_t* tp = cv.take<int32_t>(nt + 1);
+  hipStream_t s = (hipStream_t)stream;
+  DevScalars* h = host_scalars();
+  if (!h) return RBRP_E_HIP;
+  RBRP_HIP(hipMemsetAsync(sc, 0, sizeof(DevScalars), s));
+  RBRP_HIP(launch_masked_partials(d, excluded, m, ps, pm, s));
+  RBRP_HIP(launch_reduce(ps, pm, np, sc, 0, s));
+  RBRP_HIP(launch_weights_scan(d, nullptr, excluded, m, sc, cdf, ts, tp, s));
+  RBRP_HIP(launch_sample(cdf, ts, tp, m, b, seed, t, ident, idx, sc, s));
+  rbrp_status rs = fetch(h, sc, s);
+  if (rs != RBRP_OK) return rs;
+  *n_host = h->nt;
+  return RBRP_OK;
+}
+
+size_t rbrp_block_cpqr_workspace_size(int64_t n, int32_t nb) {
+  if (n <= 0 || nb < 1 || nb > kMaxB) return 0;
+  return 6 * kAlign + sizeof(DevScalars) + sizeof(double) * (3 * (size_t)nb * nb) +
+         sizeof(int32_t) * kMaxB;
+}
+
+rbrp_status rbrp_block_cpqr(const double* Vt, int64_t n, int32_t nb, int64_t ldv,
+                            double tau_b, int32_t* piv, double* R, double* Qt,
+                            int64_t ldq, int32_t* bprime_host, void* workspace,
+                            size_t ws_bytes, void* stream) {
+  if (!Vt || !piv || !R || !Qt || !bprime_host || !workspace) return RBRP_E_INVALID;
+  if (n <= 0 || nb < 1 || nb > kMaxB || ldv < n || ldq < n) return RBRP_E_INVALID;
+  if (!(tau_b >= 0.0 && tau_b <= 1.0)) return RBRP_E_INVALID;
+  if (ws_bytes < rbrp_block_cpqr_workspace_size(n, nb)) return RBRP_E_WORKSPACE;
+  Carver cv;
+  cv.base = (char*)(((uintptr_t)workspace + kAlign - 1) / kAlign * kAlign);
+  DevScalars* sc = cv.take<DevScalars>(1);
+  double* G = cv.take<double>((size_t)nb * nb);
+  double* Rraw = cv.take<double>((size_t)nb * nb);
+  double* R2 = cv.take<double>((size_t)nb * nb);
+  int32_t* piv2 = cv.take<int32_t>(kMaxB);
+  hipStream_t s = (hipStream_t)stream;
+  DevScalars* h = host_scalars();
+  if (!h) return RBRP_E_HIP;
+  RBRP_HIP(hipMemsetAsync(sc, 0, sizeof(DevScalars), s));
+  RBRP_HIP(launch_gemm_f64(0, 1, nb, nb, n, 1.0, Vt, 0, ldv, Vt, ldv, 0.0, G, nb, nullptr,
+                           nullptr, 0, s));
+  RBRP_HIP(launch_cpqr_gram_ex(G, nb, nb, nullptr, tau_b, 1, nullptr, piv, Rraw, nb, R,
+                               &sc->bprime, &sc->tail1, nullptr, s));
+  RBRP_HIP(launch_qform(Vt, ldv, piv, Rraw, nb, &sc->bprime, nb, n, Qt, ldq, s));
+  RBRP_HIP(launch_gemm_f64(0, 1, nb, nb, n, 1.0, Qt, 0, ldq, Qt, ldq, 0.0, G, nb,
+                           &sc->bprime, &sc->bprime, 0, s));
+  RBRP_HIP(launch_cpqr_gram_ex(G, nb, nb, &sc->bprime, 0.0, 0, nullptr, piv2, R2, nb,
+                               nullptr, &sc->b2, nullptr, nullptr, s));
+  RBRP_HIP(launch_qform(Qt, ldq, nullptr, R2, nb, &sc->b2, nb, n, Qt, ldq, s));
+  rbrp_status rs = fetch(h, sc, s);
+  if (rs != RBRP_OK) return rs;
+  *bprime_host = h->bprime;
+  return RBRP_OK;
+}
+
+}  // extern "C"

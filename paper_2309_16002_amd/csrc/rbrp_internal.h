@@ -1,0 +1,157 @@
+// Internal declarations shared by the HIP translation units of the RBRP
+// library: launch wrappers (one per kernel family) and small device helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "rbrp.h"
+
+namespace rbrp {
+
+constexpr int kWave = 64;
+
+// Rows of the residual buffer are padded to a multiple of this.
+constexpr int kRowPad = 64;
+// Rows per workgroup of the norm / weight kernels.
+constexpr int kNormRowsPerWG = 64;
+constexpr int kScanTile = 2048;   // rows per tile of the fixed-point CDF
+constexpr int kMaxB = 128;        // largest block size
+constexpr int kRejectionFactor = 32;
+
+__host__ __device__ inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+__host__ __device__ inline int64_t ceil_div(int64_t x, int64_t a) { return (x + a - 1) / a; }
+
+// Device-resident scalars of one decomposition, written by the kernels and
+// read by the host once per block.
+struct DevScalars {
+  double sum_d;        // ||d||_1
+  double max_d;        // max_i d_i over rows not in S
+  double d0;           // ||d^(0)||_1
+  double tail1;        // ||V||_F^2 of the last block
+  double xs2;          // ||X(S_t,:)||_F^2 of the last block
+  int32_t nonfinite;   // X holds NaN/Inf
+  int32_t nt;          // rows drawn in the last block
+  int32_t bprime;      // b' of the last block
+  int32_t stop_rank;   // last block numerically inside span(Q)
+  int32_t npos;        // rows with positive weight
+  int32_t b2;          // steps completed by the reorthogonalisation Cholesky
+  int32_t pad[2];
+};
+
+// ---- launch wrappers (defined next to their kernels) ----
+
+// R <- X (cast, zero padded to ldr columns and mr rows), d_i = ||x_i||^2,
+// per-workgroup partial sums / maxima, non-finite flag.
+hipError_t launch_init_norms(const void* X, rbrp_dtype dt, int64_t m, int64_t n,
+                             int64_t ldx, void* R, int r_is_f64, int64_t mr,
+                             int64_t ldr, double* d, double* part_sum,
+                             double* part_max, int32_t* nonfinite,
+                             hipStream_t s);
+int64_t norms_num_partials(int64_t mr);
+
+// Per-workgroup sum / max of max(d_i, 0) over rows with excluded[i] == 0
+// (the sampler's scale when rows are excluded by a mask).
+hipError_t launch_masked_partials(const double* d, const uint8_t* excluded,
+                                  int64_t m, double* part_sum, double* part_max,
+                                  hipStream_t s);
+int64_t masked_num_partials(int64_t m);
+
+// Fixed-order reduction of partial sums / maxima into sc->sum_d, sc->max_d
+// (and sc->d0 when set_d0).
+hipError_t launch_reduce(const double* part_sum, const double* part_max,
+                         int64_t np, DevScalars* sc, int set_d0, hipStream_t s);
+
+// Fixed-point weights and per-tile inclusive prefix (uint64).
+hipError_t launch_weights_scan(const double* d, const int32_t* sel_block,
+                               const uint8_t* excluded, int64_t m,
+                               const DevScalars* sc, uint64_t* cdf_local,
+                               uint64_t* tile_sum, int32_t* tile_pos,
+                               hipStream_t s);
+int64_t scan_num_tiles(int64_t m);
+
+// One workgroup: draws the block (rejection, removal fallback, or all rows
+// with positive weight) and writes idx[0..nt), sc->nt, sc->npos.
+hipError_t launch_sample(const uint64_t* cdf_local, const uint64_t* tile_sum,
+                         const int32_t* tile_pos, int64_t m, int32_t b,
+                         uint64_t seed, uint64_t t, uint64_t ident,
+                         int64_t* idx, DevScalars* sc, hipStream_t s);
+
+// Greedy top-b selection (Remark 4.3).
+hipError_t launch_topb(const double* d, const int32_t* sel_block, int64_t m,
+                       int32_t b, int64_t* idx, DevScalars* sc, hipStream_t s);
+
+// Vt[j,:] = X[idx[j], :] (FP64, zero beyond sc->nt and beyond n),
+// xs2[j] = ||X[idx[j],:]||^2.
+hipError_t launch_gather_rows(const void* X, rbrp_dtype dt, int64_t n, int64_t ldx,
+                              const int64_t* idx, const DevScalars* sc, int32_t bmax,
+                              double* Vt, int64_t ldv, double* xs2, hipStream_t s);
+
+// FP64 MFMA GEMM: C = alpha op(A) op(B) + beta C, all row-major.
+// A may be FP32 (a_f32).  Dimensions M, N may be overridden by device ints
+// (m_dev / n_dev, used when a size is only known on the device); the launch
+// covers the host bounds M, N.
+hipError_t launch_gemm_f64(int transA, int transB, int64_t M, int64_t N,
+                           int64_t K, double alpha, const void* A, int a_f32,
+                           int64_t lda, const double* B, int64_t ldb,
+                           double beta, double* C, int64_t ldc,
+                           const int32_t* m_dev, const int32_t* n_dev,
+                           int b_lower_tri, hipStream_t s);
+
+// Pivoted Cholesky of the nb x nb Gram matrix G (FP64) in one workgroup:
+// pivots, pivot rows of R with unpermuted columns (Rraw, row p = R_V(p,:)),
+// optionally the pivoted-order R (Rperm, nb x nb), b' by the truncation rule,
+// tail_1 = ||V||_F^2 and the rank-guard flag.  pivoted = 0 gives plain
+// Cholesky (for the reorthogonalisation pass).  nb <= kMaxB.
+hipError_t launch_cpqr_gram_ex(const double* G, int64_t ldg, int32_t nb,
+                               const int32_t* nb_dev, double tau_b, int pivoted,
+                               const double* xs2_rows, int32_t* piv,
+                               double* Rraw, int64_t ldr, double* Rperm,
+                               int32_t* bprime_out, double* tail1_out,
+                               int32_t* stop_out, hipStream_t s);
+
+// Qt_out[p,:] = (Vt[piv[p],:] - sum_{q<p} R[q][p] Qt_out[q,:]) / R[p][p]
+// for p < b' (row-oriented forward substitution with R^T).
+hipError_t launch_qform(const double* Vt, int64_t ldv, const int32_t* piv,
+                        const double* R, int64_t ldr, const int32_t* bprime,
+                        int32_t bmax, int64_t n, double* Qt, int64_t ldq,
+                        hipStream_t s);
+
+// Skeleton bookkeeping after the filter: S[kS + p] = idx[piv[p]],
+// sel_block[S[kS+p]] = t.
+hipError_t launch_append(const int64_t* idx, const int32_t* piv,
+                         const int32_t* bprime, int64_t kS, int32_t t,
+                         int64_t* S, int32_t* sel_block, hipStream_t s);
+
+// Low-precision MFMA fragment copies of Q' (rows kS.. kS+b' of Qt).
+hipError_t launch_make_frags(const double* Qt_new, int64_t ldq,
+                             const int32_t* bprime, int64_t n_pad, int bmax,
+                             int mode, void* fragB1, void* fragA2,
+                             hipStream_t s);
+
+// Fused deflation of one block (the hot kernel):
+// P = R Q', L[:, kS:kS+b'] = P (rows of earlier skeletons zeroed),
+// R <- R - P Q'^T, d_i = ||R_i||^2 (0 on skeletons), partial sums / maxima.
+hipError_t launch_deflate(int mode, void* R, int64_t mr, int64_t ldr,
+                          int64_t m, const void* fragB1, const void* fragA2,
+                          const int32_t* bprime, int bmax, void* L,
+                          int64_t ldl, int64_t kS, const int32_t* sel_block,
+                          int32_t t, double* d, double* part_sum,
+                          double* part_max, hipStream_t s);
+int64_t deflate_num_partials(int64_t mr);
+int deflate_supported(int mode, int64_t ldr, int bmax);
+int deflate_rows_per_wg(int mode, int64_t ldr);
+int64_t deflate_pad_cols(int64_t n);
+size_t frag_bytes(int mode, int64_t ldr, int bmax);
+
+// Interpolation matrix (Alg. 3): W(rest,:) = L_2 L_1^{-1}, W(S,:) = I.
+hipError_t launch_interp(const void* L, int l_f64, int64_t ldl, int64_t m,
+                         int64_t k, const int64_t* S, double* W, int64_t ldw,
+                         int refine, double* ws, hipStream_t s);
+size_t interp_workspace_doubles(int64_t m, int64_t k);
+
+// Deflation arithmetic modes.
+enum DeflateMode { kModeF64 = 0, kModeF32 = 1, kModeBF16x3 = 2, kModeBF16 = 3 };
+
+}  // namespace rbrp

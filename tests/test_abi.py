@@ -1,0 +1,113 @@
+"""The C ABI loads, exports every function include/rbrp.h declares, and
+rejects invalid arguments before any device work (CPU only, no GPU calls)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2309_16002_amd as rb
+from paper_2309_16002_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rbrp.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*[A-Za-z_][\w\s\*]*?\b(rbrp_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.fail("library not built: run python -m paper_2309_16002_amd.build")
+    return rb.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared_functions()
+    assert "rbrp_id" in names and "rbrp_sample_block" in names
+    for name in names:
+        assert hasattr(L, name), name
+        assert name in B.SIGNATURES, f"binding lacks {name}"
+
+
+def test_status_strings(L):
+    for s in range(7):
+        assert isinstance(rb.status_string(s), str) and rb.status_string(s)
+    assert rb.status_string(99) == "unknown status"
+
+
+def test_workspace_size_is_host_only_and_validates(L):
+    assert rb.workspace_size(1000, 100, 16, "f32") > 0
+    assert rb.workspace_size(2000, 500, 16, "f64") > rb.workspace_size(2000, 500, 16, "f32")
+    assert rb.workspace_size(0, 100, 16) == 0
+    assert rb.workspace_size(100, 0, 16) == 0
+    assert rb.workspace_size(100, 100, 0) == 0
+    assert rb.workspace_size(100, 100, 129) == 0
+    assert rb.workspace_size(100, 100, 16, k_max=101) == 0
+
+
+def _call_id(L, X=1, dt=0, m=100, n=50, ldx=50, eps=0.1, b=8, S=1, k=True, W=None, ldw=0,
+             ws=1, wsb=1 << 40, opt=None):
+    kk = ctypes.c_int64(-7)
+    st = L.rbrp_id(ctypes.c_void_p(X) if X else None, dt, m, n, ldx, eps, b, 1,
+                   ctypes.byref(opt) if opt else None,
+                   ctypes.c_void_p(S) if S else None, ctypes.byref(kk) if k else None,
+                   ctypes.c_void_p(W) if W else None, ldw, None,
+                   ctypes.c_void_p(ws) if ws else None, wsb, None)
+    return st, kk.value
+
+
+@pytest.mark.parametrize("kw", [
+    dict(X=0), dict(S=0), dict(k=False), dict(ws=0), dict(m=0), dict(n=-1), dict(ldx=49),
+    dict(eps=0.0), dict(eps=1.0), dict(eps=float("nan")), dict(b=0), dict(b=1000),
+    dict(dt=7), dict(W=1, ldw=10),
+])
+def test_rbrp_id_rejects_invalid_arguments_without_device_work(L, kw):
+    st, k = _call_id(L, **kw)
+    assert st == B.RBRP_E_INVALID
+    assert k == -7            # nothing written
+
+
+def test_rbrp_id_workspace_too_small(L):
+    st, k = _call_id(L, wsb=16)
+    assert st == B.RBRP_E_WORKSPACE and k == -7
+
+
+def test_bf16_needs_fp32_input(L):
+    o = B.make_options(precision="bf16")
+    st, _ = _call_id(L, dt=1, opt=o)
+    assert st == B.RBRP_E_UNSUPPORTED
+
+
+def test_hooks_validate_before_device_work(L):
+    n = ctypes.c_int32(0)
+    assert L.rbrp_sample_block(None, None, 10, 4, 1, 1, 0, None, ctypes.byref(n), None, 0,
+                               None) == B.RBRP_E_INVALID
+    assert L.rbrp_sample_block(ctypes.c_void_p(1), None, 10, 0, 1, 1, 0, ctypes.c_void_p(1),
+                               ctypes.byref(n), ctypes.c_void_p(1), 1 << 30,
+                               None) == B.RBRP_E_INVALID
+    bp = ctypes.c_int32(0)
+    assert L.rbrp_block_cpqr(ctypes.c_void_p(1), 10, 200, 10, 0.1, ctypes.c_void_p(1),
+                             ctypes.c_void_p(1), ctypes.c_void_p(1), 10, ctypes.byref(bp),
+                             ctypes.c_void_p(1), 1 << 30, None) == B.RBRP_E_INVALID
+    assert L.rbrp_block_cpqr(ctypes.c_void_p(1), 10, 4, 10, 1.5, ctypes.c_void_p(1),
+                             ctypes.c_void_p(1), ctypes.c_void_p(1), 10, ctypes.byref(bp),
+                             ctypes.c_void_p(1), 1 << 30, None) == B.RBRP_E_INVALID
+    s, mx = ctypes.c_double(0), ctypes.c_double(0)
+    assert L.rbrp_row_norms(None, 0, 10, 10, 10, None, ctypes.byref(s), ctypes.byref(mx),
+                            None, 0, None) == B.RBRP_E_INVALID
+    assert L.rbrp_sample_workspace_size(0) == 0
+    assert L.rbrp_block_cpqr_workspace_size(10, 0) == 0
+    assert L.rbrp_row_norms_workspace_size(0) == 0
+
+
+def test_no_cpu_fallback_in_binding():
+    # the binding only marshals arguments: it never imports the oracle
+    src = open(os.path.join(ROOT, "paper_2309_16002_amd", "_binding.py")).read()
+    assert "oracle" not in src and "numpy" not in src

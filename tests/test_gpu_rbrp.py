@@ -1,0 +1,152 @@
+"""End-to-end GPU parity of rbrp_id (Algorithm 2 + Algorithm 3) against the
+CPU FP64 oracle.
+
+Tolerances: FP64 results within relative Frobenius error 1e-10 of the
+oracle.  FP32 ("plain" single-precision deflation) cannot reproduce the FP64
+sampling probabilities bit for bit once the residual has been deflated in
+FP32 (d carries relative errors of order u32 ||x_i|| / ||r_i||), so the
+FP32 checks are: the first block is identical (its d comes straight from X),
+the tracked residual equals the true interpolation error of the returned
+(S, W) to the FP32 floor, W matches X X_S^+ on the GPU's own S, W(S,:) = I,
+and the error meets eps.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import rbrp as oracle_rbrp, w_lstsq, relative_id_error
+from workloads import (svd_matrix, geometric_spectrum, power_spectrum, exact_rank,
+                       adversarial_gmm, config_matrix)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2309_16002_amd as rb
+    rb.lib()
+    return rb
+
+
+def _gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _run(rb, X, eps, b, seed, **kw):
+    print(f"rbrp_id m={X.shape[0]} n={X.shape[1]} {X.dtype} eps={eps} b={b} seed={seed} {kw}",
+          flush=True)
+    res = rb.rbrp_id(_gpu(X), eps, b, seed, **kw)
+    torch.cuda.synchronize()
+    return res
+
+
+@pytest.mark.parametrize("m,n,b,eps,seed", [
+    (400, 120, 16, 1e-2, 1), (1000, 300, 32, 1e-3, 2), (333, 77, 8, 1e-2, 3),
+    (2000, 500, 16, 1e-2, 1),   # the svd-geometric FP64 workload at full size
+    (700, 130, 64, 1e-4, 4),
+])
+def test_fp64_matches_oracle(rb, m, n, b, eps, seed):
+    X = svd_matrix(m, n, geometric_spectrum(min(m, n), 0.9), seed=1000 + m)
+    res = _run(rb, X, eps, b, seed)
+    ref = oracle_rbrp(X, eps, b, seed)
+    assert res.S.cpu().tolist() == ref.S
+    assert res.bprime == [bp for _, bp in ref.blocks]
+    W = res.W.cpu().numpy()
+    Wref = w_lstsq(X, ref.S)
+    assert np.linalg.norm(W - Wref) <= 1e-10 * np.linalg.norm(Wref)
+    assert np.array_equal(W[ref.S], np.eye(res.k))
+    assert abs(res.resid_tracked - ref.rho) <= 1e-10 * ref.rho
+    e_true = relative_id_error(X, W, ref.S)
+    assert abs(e_true - res.resid_tracked) <= 1e-9 * e_true
+    assert e_true <= 1.05 * relative_id_error(X, Wref, ref.S)
+
+
+@pytest.mark.parametrize("r,b", [(5, 16), (40, 16), (12, 8), (70, 32)])
+def test_fp64_exact_rank_recovery(rb, r, b):
+    X = exact_rank(600, 150, r, seed=40 + r)
+    res = _run(rb, X, 1e-6, b, 3)
+    assert res.k == r
+    W = res.W.cpu().numpy()
+    assert relative_id_error(X, W, res.S.cpu().tolist()) <= 1e-12
+
+
+def test_fp64_kmax_capacity_and_fixed_rank(rb):
+    X = svd_matrix(500, 100, geometric_spectrum(100, 0.95), seed=8)
+    res = _run(rb, X, 1e-6, 16, 1, k_max=30)
+    assert res.k == 30 and res.status == 5
+    ref = oracle_rbrp(X, 1e-6, 16, 1, k_max=30)
+    assert res.S.cpu().tolist() == ref.S
+    res = _run(rb, X, 0.5, 16, 1, k_max=37, fixed_rank=True)
+    ref = oracle_rbrp(X, 0.5, 16, 1, k_max=37, fixed_rank=True)
+    assert res.k == 37 and res.S.cpu().tolist() == ref.S
+
+
+def test_zero_matrix(rb):
+    res = _run(rb, np.zeros((100, 40)), 1e-2, 8, 1)
+    assert res.k == 0
+
+
+def test_nonfinite_input(rb):
+    X = np.ones((64, 32), dtype=np.float32)
+    X[3, 3] = np.inf
+    with pytest.raises(rb.RBRPError) as e:
+        _run(rb, X, 1e-2, 8, 1)
+    assert e.value.status == 4
+
+
+def test_deterministic(rb):
+    X = adversarial_gmm(5000, 200, sub_dim=50, n_comp=10, seed=4)
+    a = _run(rb, X, 1e-3, 32, 9)
+    b = _run(rb, X, 1e-3, 32, 9)
+    assert a.S.cpu().tolist() == b.S.cpu().tolist()
+    assert torch.equal(a.W, b.W)
+
+
+@pytest.mark.parametrize("m,n,b,seed", [(6000, 250, 32, 1), (20000, 1000, 64, 2)])
+def test_fp32_adversarial_gmm(rb, m, n, b, seed):
+    eps = 1e-3
+    X = adversarial_gmm(m, n, sub_dim=min(200, n // 2), n_comp=20, seed=seed)
+    res = _run(rb, X, eps, b, seed)
+    ref = oracle_rbrp(X.astype(np.float64), eps, b, seed)
+    S = res.S.cpu().tolist()
+    # first block: identical draws and filter (d^(0) comes straight from X)
+    bp0 = ref.blocks[0][1]
+    assert res.bprime[0] == bp0
+    assert S[:bp0] == ref.S[:bp0]
+    X64 = X.astype(np.float64)
+    W = res.W.cpu().numpy()
+    assert np.array_equal(W[S], np.eye(res.k))
+    e_true = relative_id_error(X64, W, S)
+    Wopt = w_lstsq(X64, S)
+    e_opt = relative_id_error(X64, Wopt, S)
+    # stated FP32 bound: interpolation error within 1.05x of the optimum on S
+    # and the eps target met
+    assert e_true <= 1.05 * e_opt + 1e-6
+    assert e_true <= eps * 1.01
+    # tracked residual vs the true residual: FP32 floor
+    assert abs(res.resid_tracked - e_opt) <= 5e-6 + 0.02 * e_opt
+    # skeleton count close to the oracle's at the same eps
+    assert abs(res.k - ref.k) <= max(b, 0.15 * ref.k)
+
+
+def test_fp32_svd_matches_oracle_skeletons_mostly(rb):
+    X = svd_matrix(3000, 400, power_spectrum(400, 1.5), seed=31).astype(np.float32)
+    res = _run(rb, X, 1e-2, 32, 5)
+    ref = oracle_rbrp(X.astype(np.float64), 1e-2, 32, 5)
+    S = res.S.cpu().tolist()
+    W = res.W.cpu().numpy()
+    e = relative_id_error(X.astype(np.float64), W, S)
+    assert e <= 1e-2 * 1.01
+    assert S[:ref.blocks[0][1]] == ref.S[:ref.blocks[0][1]]
+
+
+def test_greedy_b1_matches_oracle(rb):
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((300, 60)) * rng.uniform(0.5, 2.0, size=(300, 1))
+    res = _run(rb, X, 1e-12, 1, 0, greedy=True, k_max=40, fixed_rank=True)
+    ref = oracle_rbrp(X, 1e-12, 1, 0, greedy=True, k_max=40, fixed_rank=True)
+    assert res.S.cpu().tolist() == ref.S

@@ -42,7 +42,7 @@ def svd_matrix(m, n, s, seed, dtype=np.float64):
     return np.ascontiguousarray(X.astype(dtype))
 
 
-def exact_rank(m, n, r, seed, dtype=np.float64, decay=0.7):
+def exact_rank(m, n, r, seed, dtype=np.float64, decay=0.9):
     """A matrix of exact rank r (Haar factors, s_i = decay^i)."""
     return svd_matrix(m, n, geometric_spectrum(r, decay), seed, dtype)
 
