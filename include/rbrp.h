@@ -68,6 +68,9 @@ typedef struct {
   int32_t precision;   /* rbrp_precision                                         */
   int32_t w_refine;    /* refinement steps of the W solve; < 0 -> 1              */
   double theta;        /* BF16 mode: split/plain switch; <= 0 -> 25 * eps        */
+  int32_t profile;     /* 1: time the phases with HIP events on ``stream`` and
+                          report them in rbrp_stats                             */
+  int32_t reserved0;
 } rbrp_options;
 
 /* Per-call statistics (optional, host memory). */
@@ -76,6 +79,15 @@ typedef struct {
   int32_t blocks_split;    /* BF16 mode: blocks deflated with hi+lo products  */
   double resid_tracked;    /* sqrt(||d||_1 / ||d^(0)||_1) at exit             */
   double norm_x_fro;       /* ||X||_F                                         */
+  /* filled when rbrp_options.profile = 1 (milliseconds, HIP events) */
+  double ms_init;          /* copy X -> residual, initial norms               */
+  double ms_select;        /* weights, CDF and sampling, all blocks           */
+  double ms_filter;        /* gather, projection, block CPQR, basis, all blocks */
+  double ms_deflate;       /* the fused deflation kernel, all blocks          */
+  double ms_interp;        /* W from L (Algorithm 3)                          */
+  double deflate_flops;    /* algorithmic flops of the deflations: sum 4 m n b' */
+  int32_t deflate_launches;
+  int32_t reserved0;
   int32_t bprime[256];     /* b' of the first 256 blocks                       */
 } rbrp_stats;
 

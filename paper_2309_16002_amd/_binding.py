@@ -34,6 +34,8 @@ class rbrp_options(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("w_refine", ctypes.c_int32),
         ("theta", ctypes.c_double),
+        ("profile", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
     ]
 
 
@@ -43,6 +45,14 @@ class rbrp_stats(ctypes.Structure):
         ("blocks_split", ctypes.c_int32),
         ("resid_tracked", ctypes.c_double),
         ("norm_x_fro", ctypes.c_double),
+        ("ms_init", ctypes.c_double),
+        ("ms_select", ctypes.c_double),
+        ("ms_filter", ctypes.c_double),
+        ("ms_deflate", ctypes.c_double),
+        ("ms_interp", ctypes.c_double),
+        ("deflate_flops", ctypes.c_double),
+        ("deflate_launches", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
         ("bprime", ctypes.c_int32 * 256),
     ]
 
@@ -137,7 +147,7 @@ def _check_matrix(X):
 
 
 def make_options(k_max=0, tau_b=0.0, fixed_rank=False, greedy=False, precision="native",
-                 theta=0.0, w_refine=1):
+                 theta=0.0, w_refine=1, profile=False):
     o = rbrp_options()
     lib().rbrp_default_options(ctypes.byref(o))
     o.tau_b = float(tau_b)
@@ -147,6 +157,7 @@ def make_options(k_max=0, tau_b=0.0, fixed_rank=False, greedy=False, precision="
     o.precision = PRECISIONS[precision]
     o.theta = float(theta)
     o.w_refine = int(w_refine)
+    o.profile = int(bool(profile))
     return o
 
 
@@ -161,6 +172,7 @@ class IDResult:
     bprime: list
     resid_tracked: float
     norm_x: float
+    profile: dict = None
 
 
 def workspace_size(m, n, b, dtype="f32", **opts):
@@ -169,8 +181,12 @@ def workspace_size(m, n, b, dtype="f32", **opts):
     return int(lib().rbrp_workspace_size(dt, int(m), int(n), int(b), ctypes.byref(o)))
 
 
-def rbrp_id(X, eps, b, seed=0, *, want_w=True, workspace=None, **opts):
-    """Row ID X ~= W X[S] by RBRP (Algorithm 2, then Algorithm 3)."""
+def rbrp_id(X, eps, b, seed=0, *, want_w=True, workspace=None, out_S=None, out_W=None,
+            **opts):
+    """Row ID X ~= W X[S] by RBRP (Algorithm 2, then Algorithm 3).
+
+    ``workspace``, ``out_S`` (int64 [k_max]) and ``out_W`` (float64 [m, k_max],
+    row-major) may be passed in to reuse device buffers across calls."""
     torch = _torch()
     _check_matrix(X)
     L = lib()
@@ -183,20 +199,34 @@ def rbrp_id(X, eps, b, seed=0, *, want_w=True, workspace=None, **opts):
     if workspace is None or workspace.numel() < ws_bytes:
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=X.device)
     k_max = o.k_max if o.k_max > 0 else min(m, n)
-    S = torch.empty(k_max, dtype=torch.int64, device=X.device)
-    W = torch.empty((m, k_max), dtype=torch.float64, device=X.device) if want_w else None
+    S = out_S if out_S is not None else torch.empty(k_max, dtype=torch.int64, device=X.device)
+    if S.numel() < k_max or S.dtype != torch.int64 or not S.is_contiguous():
+        raise ValueError("out_S must be a contiguous int64 tensor of at least k_max entries")
+    W = None
+    if want_w:
+        W = out_W if out_W is not None else torch.empty((m, k_max), dtype=torch.float64,
+                                                        device=X.device)
+        if (W.dtype != torch.float64 or W.dim() != 2 or W.shape[0] != m
+                or W.shape[1] < k_max or W.stride(1) != 1):
+            raise ValueError("out_W must be a row-major float64 [m, >= k_max] tensor")
     k = ctypes.c_int64(0)
     st = rbrp_stats()
     status = L.rbrp_id(_ptr(X), dt, m, n, _ld(X), float(eps), int(b), int(seed),
-                       ctypes.byref(o), _ptr(S), ctypes.byref(k), _ptr(W), k_max,
+                       ctypes.byref(o), _ptr(S), ctypes.byref(k), _ptr(W),
+                       W.stride(0) if W is not None else k_max,
                        ctypes.byref(st), _ptr(workspace), ws_bytes, _stream_ptr(X.device))
     if status not in (RBRP_OK, RBRP_E_CAPACITY):
         raise RBRPError(status, "rbrp_id")
     kk = int(k.value)
     nb = min(st.blocks, 256)
+    prof = None
+    if o.profile:
+        prof = dict(ms_init=st.ms_init, ms_select=st.ms_select, ms_filter=st.ms_filter,
+                    ms_deflate=st.ms_deflate, ms_interp=st.ms_interp,
+                    deflate_flops=st.deflate_flops, deflate_launches=st.deflate_launches)
     return IDResult(S[:kk], kk, W[:, :kk] if W is not None else None, status, st.blocks,
                     st.blocks_split, [int(x) for x in st.bprime[:nb]], st.resid_tracked,
-                    st.norm_x_fro)
+                    st.norm_x_fro, prof)
 
 
 def row_norms(X):

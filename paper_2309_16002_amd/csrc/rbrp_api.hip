@@ -155,6 +155,46 @@ DevScalars* host_scalars() {
     }                                              \
   } while (0)
 
+// Phase timing with HIP events recorded on the caller's stream.
+struct Profiler {
+  bool on = false;
+  hipStream_t s = nullptr;
+  struct Span { hipEvent_t a, b; int phase; };
+  Span spans[1100];
+  int n = 0;
+  hipEvent_t cur_a = nullptr;
+  int cur_phase = -1;
+  ~Profiler() {
+    for (int i = 0; i < n; ++i) {
+      hipEventDestroy(spans[i].a);
+      hipEventDestroy(spans[i].b);
+    }
+  }
+  void begin(int phase) {
+    if (!on || n >= 1100) return;
+    Span& sp = spans[n];
+    if (hipEventCreate(&sp.a) != hipSuccess) { on = false; return; }
+    if (hipEventCreate(&sp.b) != hipSuccess) { hipEventDestroy(sp.a); on = false; return; }
+    sp.phase = phase;
+    hipEventRecord(sp.a, s);
+  }
+  void end() {
+    if (!on || n >= 1100) return;
+    hipEventRecord(spans[n].b, s);
+    ++n;
+  }
+  // phases: 0 init, 1 select, 2 filter, 3 deflate, 4 interp
+  void collect(double* ms5, int* ndeflate) {
+    for (int i = 0; i < 5; ++i) ms5[i] = 0.0;
+    *ndeflate = 0;
+    for (int i = 0; i < n; ++i) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, spans[i].a, spans[i].b) == hipSuccess) ms5[spans[i].phase] += t;
+      if (spans[i].phase == 3) ++*ndeflate;
+    }
+  }
+};
+
 rbrp_status fetch(DevScalars* h, const DevScalars* dsc, hipStream_t s) {
   RBRP_HIP(hipMemcpyAsync(h, dsc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
   RBRP_HIP(hipStreamSynchronize(s));
@@ -224,12 +264,18 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
   const int64_t ldr = p.ldr;
   rbrp_stats st;
   memset(&st, 0, sizeof(st));
+  Profiler prof;
+  prof.on = o.profile != 0;
+  prof.s = s;
+  double flops = 0.0;
 
   RBRP_HIP(hipMemsetAsync(w.sc, 0, sizeof(DevScalars), s));
   RBRP_HIP(hipMemsetAsync(w.sel_block, 0xFF, sizeof(int32_t) * p.m, s));
+  prof.begin(0);
   RBRP_HIP(launch_init_norms(X, dtype, m, n, ldx, w.R, p.r_f64, p.mr, ldr, w.d,
                              w.part_sum, w.part_max, &w.sc->nonfinite, s));
   RBRP_HIP(launch_reduce(w.part_sum, w.part_max, norms_num_partials(p.mr), w.sc, 1, s));
+  prof.end();
   rbrp_status rs = fetch(h, w.sc, s);
   if (rs != RBRP_OK) return rs;
   if (h->nonfinite) return RBRP_E_NONFINITE;
@@ -256,6 +302,7 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     ++t;
     const int32_t bt = (int32_t)((int64_t)b < k_max - kS ? b : k_max - kS);
     // sampling (or greedy top-b)
+    prof.begin(1);
     if (o.greedy) {
       RBRP_HIP(launch_topb(w.d, w.sel_block, m, bt, w.idx, w.sc, s));
     } else {
@@ -264,7 +311,9 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
       RBRP_HIP(launch_sample(w.cdf, w.tile_sum, w.tile_pos, m, bt, seed, (uint64_t)t, 0,
                              w.idx, w.sc, s));
     }
+    prof.end();
     // V^T: sampled rows of X in FP64, projected twice against the basis
+    prof.begin(2);
     RBRP_HIP(launch_gather_rows(X, dtype, n, ldx, w.idx, w.sc, bt, w.Vt, ldr, w.xs2, s));
     if (kS > 0) {
       for (int pass = 0; pass < 2; ++pass) {
@@ -302,12 +351,16 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
       if (mode == kModeBF16x3) st.blocks_split++;
     }
     RBRP_HIP(launch_make_frags(Qn, ldr, &w.sc->bprime, ldr, b, mode, w.fragB1, w.fragA2, s));
+    prof.end();
+    prof.begin(3);
     RBRP_HIP(launch_deflate(mode, w.R, p.mr, ldr, m, w.fragB1, w.fragA2, &w.sc->bprime, b,
                             w.L, k_max, kS, w.sel_block, t, w.d, w.part_sum, w.part_max, s));
+    prof.end();
     RBRP_HIP(launch_reduce(w.part_sum, w.part_max, p.mr / def_rows, w.sc, 0, s));
     rs = fetch(h, w.sc, s);
     if (rs != RBRP_OK) return rs;
     const int bp = h->bprime;
+    flops += 4.0 * (double)m * (double)n * (double)(bp > 0 ? bp : 0);
     if (t <= 256) st.bprime[t - 1] = bp;
     st.blocks = t;
     if (h->stop_rank || bp <= 0) break;
@@ -318,9 +371,23 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
   *k_host = kS;
   st.resid_tracked = sqrt(fmax(sum_d, 0.0) / D0);
   if (W && kS > 0) {
+    prof.begin(4);
     RBRP_HIP(launch_interp(w.L, p.r_f64, k_max, m, kS, S, W, ldw, refine, w.interp, s));
+    prof.end();
   }
   RBRP_HIP(hipStreamSynchronize(s));
+  if (prof.on) {
+    double ms5[5];
+    int nd = 0;
+    prof.collect(ms5, &nd);
+    st.ms_init = ms5[0];
+    st.ms_select = ms5[1];
+    st.ms_filter = ms5[2];
+    st.ms_deflate = ms5[3];
+    st.ms_interp = ms5[4];
+    st.deflate_launches = nd;
+    st.deflate_flops = flops;
+  }
   if (stats_host) *stats_host = st;
   return final_status;
 }
