@@ -108,6 +108,9 @@ def main():
     ap.add_argument("--workload", default="adversarial_gmm_fp32", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-repeats", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="only run a plain device-to-device copy of MB megabytes (the "
+                         "reference for HBM byte counters) and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -123,6 +126,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        n_el = args.copy_calibration * 1000000 // 4
+        src = torch.ones(n_el, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n_el * 4}))
+        return
     rb.lib()
     cfg = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")

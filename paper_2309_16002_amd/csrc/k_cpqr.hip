@@ -26,52 +26,57 @@
 
 namespace rbrp {
 
-constexpr int kCpqrThreads = 256;
-
-__global__ __launch_bounds__(kCpqrThreads) void k_cpqr_gram(
+// One thread per column j of the block (nb <= 128, one or two waves).  Thread
+// j keeps the Schur-complement diagonal entry of its column in a register and
+// updates its own column of G (in LDS) at every pivot step, so the only
+// cross-thread traffic per step is the argmax/sum reduction and the pivot row.
+//
+// After pivoting, the kernel also forms M = R11^{-T} (b' x b', lower
+// triangular) by forward substitution over rows, in the same LDS array: the
+// strict upper triangle keeps R11, the strict lower triangle receives M and
+// the two diagonals live in separate vectors.  M is written scattered back to
+// the sampled order, Mout[p][piv[c]] = M[p][c], so that the new basis rows
+// are the plain product Q'^T = Mout V^T.
+__global__ __launch_bounds__(128) void k_cpqr_gram(
     const double* __restrict__ G, int64_t ldg, int32_t nb_host,
     const int32_t* __restrict__ nb_dev, double tau_b, int pivoted,
     const double* __restrict__ xs2_rows, int32_t* __restrict__ piv,
     double* __restrict__ Rraw, int64_t ldr, double* __restrict__ Rperm,
-    int32_t* __restrict__ bprime_out, double* __restrict__ tail1_out,
-    int32_t* __restrict__ stop_out) {
+    double* __restrict__ Mout, int64_t ldm, int32_t* __restrict__ bprime_out,
+    double* __restrict__ tail1_out, int32_t* __restrict__ stop_out,
+    const int32_t* __restrict__ run_flag) {
   extern __shared__ double Gs[];
-  __shared__ double rrow[kMaxB];
-  __shared__ int32_t chosen[kMaxB];
+  if (run_flag && *run_flag == 0) {
+    if (threadIdx.x == 0 && nb_dev) *bprime_out = *nb_dev;
+    return;
+  }
+  __shared__ double rrow[2][kMaxB];
+  __shared__ double rdiag[kMaxB];
+  __shared__ double mdiag[kMaxB];
   __shared__ int32_t pivs[kMaxB];
-  __shared__ double wbest[4];
-  __shared__ int32_t wbi[4];
-  __shared__ double wtail[4];
-  __shared__ int32_t s_piv, s_done, s_bp;
-  __shared__ double s_thr, s_r;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wv = tid >> 6;
+  __shared__ int32_t chosen_s[kMaxB];
+  __shared__ double wbest[2], wtail[2];
+  __shared__ int32_t wbi[2];
+  const int j = threadIdx.x;
+  const int lane = j & 63, wv = j >> 6;
+  const int nwave = blockDim.x >> 6;
   int nb = nb_host;
   if (nb_dev) nb = min(nb, *nb_dev);
   const int ld = nb + 1;
-  for (int e = tid; e < nb * nb; e += kCpqrThreads) {
-    const int i = e / nb, j = e - i * nb;
-    Gs[i * ld + j] = G[(int64_t)i * ldg + j];
-  }
-  for (int j = tid; j < kMaxB; j += kCpqrThreads) chosen[j] = 0;
-  if (tid == 0) {
-    s_done = 0;
-    s_bp = 0;
+  const bool active = j < nb;
+  for (int e = j; e < nb * nb; e += blockDim.x) {
+    const int r = e / nb, c = e - r * nb;
+    Gs[r * ld + c] = G[(int64_t)r * ldg + c];
   }
   __syncthreads();
+  double dj = active ? Gs[j * ld + j] : 0.0;
+  bool chosen = !active;
+  double thr = 0.0;
   int bp = 0;
   for (int p = 0; p <= nb; ++p) {
-    // remaining diagonal: argmax (ties to the lowest column) and sum
-    double best = -INFINITY;
-    int bi = -1;
-    double tail = 0.0;
-    for (int j = tid; j < nb; j += kCpqrThreads) {
-      if (!chosen[j]) {
-        const double v = Gs[j * ld + j];
-        tail += fmax(v, 0.0);
-        if (v > best) { best = v; bi = j; }
-      }
-    }
+    double best = chosen ? -INFINITY : dj;
+    int bi = chosen ? -1 : j;
+    double tail = chosen ? 0.0 : fmax(dj, 0.0);
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
       const double ob = __shfl_xor(best, off, kWave);
@@ -82,94 +87,406 @@ __global__ __launch_bounds__(kCpqrThreads) void k_cpqr_gram(
         bi = oi;
       }
     }
-    if (lane == 0) {
-      wbest[wv] = best;
-      wbi[wv] = bi;
-      wtail[wv] = tail;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double b2 = -INFINITY, t2 = 0.0;
-      int i2 = -1;
-      for (int q = 0; q < 4; ++q) {
-        t2 += wtail[q];
-        if (wbi[q] >= 0 && (i2 < 0 || wbest[q] > b2 || (wbest[q] == b2 && wbi[q] < i2))) {
-          b2 = wbest[q];
-          i2 = wbi[q];
-        }
+    if (nwave > 1) {
+      if (lane == 0) {
+        wbest[wv] = best;
+        wbi[wv] = bi;
+        wtail[wv] = tail;
       }
-      int done = 0;
-      if (p == 0) {
-        if (tail1_out) *tail1_out = t2;
-        s_thr = tau_b * t2 * (1.0 - 4.0 * nb * 1.1102230246251565e-16);
-        if (xs2_rows) {
-          double xs2 = 0.0;
-          for (int q = 0; q < nb; ++q) xs2 += xs2_rows[q];
-          if (!(t2 > 1e-26 * xs2)) {
-            done = 1;
-            if (stop_out) *stop_out = 1;
-          }
-        }
-      }
-      if (pivoted) {
-        if (p == nb || i2 < 0 || !(b2 > 0.0) || (p > 0 && t2 < s_thr)) done = 1;
-      } else {
-        if (p == nb) done = 1;
-        else {
-          i2 = p;
-          b2 = Gs[p * ld + p];
-          if (!(b2 > 0.0)) done = 1;
-        }
-      }
-      s_done = done;
-      if (!done) {
-        s_piv = i2;
-        s_r = sqrt(b2);
-        pivs[p] = i2;
-        chosen[i2] = 1;
-      } else {
-        s_bp = p;
+      __syncthreads();
+      best = wbest[0];
+      bi = wbi[0];
+      tail = wtail[0] + wtail[1];
+      if (wbi[1] >= 0 && (bi < 0 || wbest[1] > best || (wbest[1] == best && wbi[1] < bi))) {
+        best = wbest[1];
+        bi = wbi[1];
       }
     }
-    __syncthreads();
-    if (s_done) {
-      bp = s_bp;
+    // every thread now holds the same best / bi / tail
+    bool done = false;
+    if (p == 0) {
+      if (tail1_out && j == 0) *tail1_out = tail;
+      thr = tau_b * tail * (1.0 - 4.0 * nb * 1.1102230246251565e-16);
+      if (xs2_rows) {
+        double xs2 = 0.0;
+        for (int q = 0; q < nb; ++q) xs2 += xs2_rows[q];
+        if (!(tail > 1e-26 * xs2)) {
+          done = true;
+          if (stop_out && j == 0) *stop_out = 1;
+        }
+      }
+    }
+    int jp = bi;
+    double g = best;
+    if (!pivoted && p < nb) {
+      jp = p;
+      g = Gs[p * ld + p];
+    }
+    if (p == nb || jp < 0 || !(g > 0.0)) done = true;
+    if (pivoted && p > 0 && tail < thr) done = true;
+    if (done) {
+      bp = p;
       break;
     }
-    const int jp = s_piv;
-    const double r = s_r;
-    // pivot row of R (unpermuted columns)
-    for (int j = tid; j < nb; j += kCpqrThreads) {
+    const double r = sqrt(g);
+    const int buf = p & 1;
+    if (active) {
       double v;
       if (j == jp) v = r;
-      else if (chosen[j]) v = 0.0;
+      else if (chosen) v = 0.0;
       else v = Gs[jp * ld + j] / r;
-      rrow[j] = v;
+      rrow[buf][j] = v;
       Rraw[(int64_t)p * ldr + j] = v;
     }
+    if (j == jp) chosen = true;
+    if (j == 0) pivs[p] = jp;
     __syncthreads();
-    // Schur complement update on the remaining columns
-    for (int e = tid; e < nb * nb; e += kCpqrThreads) {
-      const int i = e / nb, j = e - i * nb;
-      if (!chosen[i] && !chosen[j]) Gs[i * ld + j] -= rrow[i] * rrow[j];
+    if (active) {
+      // G[:, j] -= rrow * rrow[j]; the pivot row and chosen columns end at zero
+      const double rj = rrow[buf][j];
+      if (rj != 0.0)
+        for (int i = 0; i < nb; ++i) Gs[i * ld + j] -= rrow[buf][i] * rj;
+      dj = Gs[j * ld + j];
     }
     __syncthreads();
   }
-  // pivot order: the kept pivots, then the rest in increasing column order
-  if (tid == 0) {
+  if (active) chosen_s[j] = chosen ? 1 : 0;
+  __syncthreads();
+  if (j == 0) {
     int q = bp;
-    for (int j = 0; j < nb; ++j)
-      if (!chosen[j]) pivs[q++] = j;
+    for (int c = 0; c < nb; ++c)
+      if (!chosen_s[c]) pivs[q++] = c;
     *bprime_out = bp;
   }
   __syncthreads();
-  for (int j = tid; j < nb; j += kCpqrThreads) piv[j] = pivs[j];
+  if (active) piv[j] = pivs[j];
   if (Rperm) {
-    for (int e = tid; e < nb * nb; e += kCpqrThreads) {
-      const int p = e / nb, q = e - p * nb;
-      Rperm[(int64_t)p * nb + q] = (p < bp && q >= p) ? Rraw[(int64_t)p * ldr + pivs[q]] : 0.0;
+    for (int e = j; e < nb * nb; e += blockDim.x) {
+      const int a = e / nb, c = e - a * nb;
+      Rperm[(int64_t)a * nb + c] = (a < bp && c >= a) ? Rraw[(int64_t)a * ldr + pivs[c]] : 0.0;
     }
   }
+  if (!Mout) return;
+  // R11[a][c] = Rraw[a][piv[c]] for a <= c < bp: strict upper part into Gs,
+  // diagonal into rdiag
+  __syncthreads();
+  for (int e = j; e < bp * bp; e += blockDim.x) {
+    const int a = e / bp, c = e - a * bp;
+    if (c > a) Gs[a * ld + c] = Rraw[(int64_t)a * ldr + pivs[c]];
+    else if (c == a) rdiag[a] = Rraw[(int64_t)a * ldr + pivs[a]];
+  }
+  __syncthreads();
+  // M = R11^{-T}: M[p][c] = (delta_pc - sum_{c <= q < p} R11[q][p] M[q][c]) / R11[p][p]
+  for (int p = 0; p < bp; ++p) {
+    if (j <= p && j < bp) {
+      double v = (j == p) ? 1.0 : 0.0;
+      for (int q = j; q < p; ++q) {
+        const double mq = (q == j) ? mdiag[j] : Gs[q * ld + j];
+        v -= Gs[q * ld + p] * mq;
+      }
+      v /= rdiag[p];
+      if (j == p) mdiag[p] = v;
+      else Gs[p * ld + j] = v;
+    }
+    __syncthreads();
+  }
+  // scatter to the sampled order: Mout[p][pivs[c]] = M[p][c]; the whole
+  // nb_host x nb_host block is cleared first so that rows and columns past b'
+  // are exact zeros for the products that follow
+  for (int e = j; e < nb_host * nb_host; e += blockDim.x) {
+    const int a = e / nb_host, c = e - a * nb_host;
+    Mout[(int64_t)a * ldm + c] = 0.0;
+  }
+  __syncthreads();
+  for (int e = j; e < bp * bp; e += blockDim.x) {
+    const int a = e / bp, c = e - a * bp;
+    if (c <= a) Mout[(int64_t)a * ldm + pivs[c]] = (c == a) ? mdiag[a] : Gs[a * ld + c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pivoted Cholesky of the block's Gram matrix for the filter (256 threads).
+// The Schur complement S (nb x nb) lives in LDS; thread j < nb keeps the
+// diagonal entry S[j][j] in a register.  Per pivot step: a fixed-order
+// argmax / sum over the diagonal (waves 0-1), the pivot row of R written to
+// LDS, and the rank-one update of S spread over all 256 threads (each thread
+// updates nb*nb/256 independent entries, so LDS latency overlaps).
+// Outputs: pivots (kept ones first, the rest in increasing order), b', the
+// pivot rows of R with unpermuted columns (Rraw), R11 in pivoted order
+// (Rp, nb x nb, zero outside the leading b' x b' upper triangle), ||V||_F^2
+// and the rank-guard flag.
+constexpr int kPivThreads = 256;
+
+__global__ __launch_bounds__(kPivThreads) void k_cpqr_piv(
+    const double* __restrict__ G, int64_t ldg, int32_t nb_host,
+    const int32_t* __restrict__ nb_dev, double tau_b,
+    const double* __restrict__ xs2_rows, int32_t* __restrict__ piv,
+    double* __restrict__ Rraw, int64_t ldr, double* __restrict__ Rp, int64_t ldp,
+    int32_t* __restrict__ bprime_out, double* __restrict__ tail1_out,
+    int32_t* __restrict__ stop_out) {
+  extern __shared__ double Ss[];
+  __shared__ double rrow[kMaxB];
+  __shared__ int32_t chosen_s[kMaxB];
+  __shared__ int32_t pivs[kMaxB];
+  __shared__ double wbest[2], wtail[2];
+  __shared__ int32_t wbi[2];
+  __shared__ int32_t s_done;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  int nb = nb_host;
+  if (nb_dev) nb = min(nb, *nb_dev);
+  const int ld = nb + 1;
+  for (int e = tid; e < nb * nb; e += kPivThreads) {
+    const int r = e / nb, c = e - r * nb;
+    Ss[r * ld + c] = G[(int64_t)r * ldg + c];
+  }
+  if (tid < kMaxB) chosen_s[tid] = (tid < nb) ? 0 : 1;
+  __syncthreads();
+  const bool owner = tid < nb;                 // owns diagonal entry tid
+  double dj = owner ? Ss[tid * ld + tid] : 0.0;
+  bool chosen = !owner;
+  double thr = 0.0;
+  int bp = 0;
+  // update assignment: column c = tid % nb (or none), rows r0, r0 + rstep, ...
+  const int nb2 = nb > 0 ? nb : 1;
+  const int ucol = tid % nb2;
+  const int urow0 = tid / nb2;
+  const int rstep = kPivThreads / nb2;
+  for (int p = 0; p <= nb; ++p) {
+    if (wv < 2) {
+      double best = chosen ? -INFINITY : dj;
+      int bi = chosen ? -1 : tid;
+      double tail = chosen ? 0.0 : fmax(dj, 0.0);
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double ob = __shfl_xor(best, off, kWave);
+        const int oi = __shfl_xor(bi, off, kWave);
+        tail += __shfl_xor(tail, off, kWave);
+        if (oi >= 0 && (bi < 0 || ob > best || (ob == best && oi < bi))) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        wbest[wv] = best;
+        wbi[wv] = bi;
+        wtail[wv] = tail;
+      }
+    }
+    __syncthreads();
+    double best = wbest[0];
+    int bi = wbi[0];
+    double tail = wtail[0] + wtail[1];
+    if (wbi[1] >= 0 && (bi < 0 || wbest[1] > best || (wbest[1] == best && wbi[1] < bi))) {
+      best = wbest[1];
+      bi = wbi[1];
+    }
+    bool done = false;
+    if (p == 0) {
+      thr = tau_b * tail * (1.0 - 4.0 * nb * 1.1102230246251565e-16);
+      if (tid == 0 && tail1_out) *tail1_out = tail;
+      if (xs2_rows) {
+        double xs2 = 0.0;
+        for (int q = 0; q < nb; ++q) xs2 += xs2_rows[q];
+        if (!(tail > 1e-26 * xs2)) {
+          done = true;
+          if (stop_out && tid == 0) *stop_out = 1;
+        }
+      }
+    }
+    if (p == nb || bi < 0 || !(best > 0.0)) done = true;
+    if (p > 0 && tail < thr) done = true;
+    if (done) {
+      bp = p;
+      break;
+    }
+    const int jp = bi;
+    const double r = sqrt(best);
+    if (tid < nb) {
+      double v;
+      if (tid == jp) v = r;
+      else if (chosen) v = 0.0;
+      else v = Ss[jp * ld + tid] / r;
+      rrow[tid] = v;
+      Rraw[(int64_t)p * ldr + tid] = v;
+      if (tid == jp) {
+        chosen = true;
+        chosen_s[tid] = 1;
+        pivs[p] = jp;
+      }
+      dj -= v * v;
+    }
+    __syncthreads();
+    // rank-one update of the remaining Schur complement
+    if (urow0 < rstep && tid < rstep * nb) {
+      const double rc = rrow[ucol];
+      if (rc != 0.0) {
+#pragma unroll 8
+        for (int i = urow0; i < nb; i += rstep) Ss[i * ld + ucol] -= rrow[i] * rc;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    int q = bp;
+    for (int c = 0; c < nb; ++c)
+      if (!chosen_s[c]) pivs[q++] = c;
+    *bprime_out = bp;
+  }
+  __syncthreads();
+  if (tid < nb) piv[tid] = pivs[tid];
+  // R11 in pivoted order, zero outside the leading b' x b' upper triangle
+  for (int e = tid; e < nb_host * nb_host; e += kPivThreads) {
+    const int a = e / nb_host, c = e - a * nb_host;
+    double v = 0.0;
+    if (a < bp && c >= a && c < nb) v = Rraw[(int64_t)a * ldr + pivs[c]];
+    Rp[(int64_t)a * ldp + c] = v;
+  }
+}
+
+// Rows of Qtmp: Qtmp[p,:] = (Vt[piv[p],:] - sum_{q<p} R11[q][p] Qtmp[q,:]) /
+// R11[p][p] for p < b' (the orthonormal basis of the kept columns,
+// Q' = V(:, piv(1:b')) R11^{-1}), rows b'..nb_host-1 set to zero.  One thread
+// per column; the column's unknowns are solved in chunks of 64 held in
+// registers (fully unrolled), R11 is read from LDS as broadcasts.
+constexpr int kSolveChunk = 64;
+
+__global__ __launch_bounds__(64) void k_qsolve(const double* __restrict__ Vt, int64_t ldv,
+                                               const int32_t* __restrict__ piv,
+                                               const double* __restrict__ Rp, int64_t ldp,
+                                               const int32_t* __restrict__ bprime,
+                                               int32_t nb_host, int64_t ncols,
+                                               double* __restrict__ Qt, int64_t ldq) {
+  extern __shared__ double Rs[];
+  __shared__ int32_t ps[kMaxB];
+  const int bp = *bprime;
+  for (int e = threadIdx.x; e < bp * bp; e += 64) {
+    const int a = e / bp, c = e - a * bp;
+    Rs[e] = Rp[(int64_t)a * ldp + c];
+  }
+  for (int e = threadIdx.x; e < bp; e += 64) ps[e] = piv[e];
+  __syncthreads();
+  const int64_t c = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (c >= ncols) return;
+  for (int p0 = 0; p0 < nb_host; p0 += kSolveChunk) {
+    double x[kSolveChunk];
+#pragma unroll
+    for (int i = 0; i < kSolveChunk; ++i) {
+      const int p = p0 + i;
+      x[i] = (p < bp) ? Vt[(int64_t)ps[p] * ldv + c] : 0.0;
+    }
+    // contributions of earlier chunks (already stored)
+    for (int q = 0; q < p0 && q < bp; ++q) {
+      const double xq = Qt[(int64_t)q * ldq + c];
+#pragma unroll
+      for (int i = 0; i < kSolveChunk; ++i) {
+        const int p = p0 + i;
+        if (p < bp) x[i] -= Rs[q * bp + p] * xq;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kSolveChunk; ++i) {
+      const int p = p0 + i;
+      if (p < bp) {
+#pragma unroll
+        for (int k = 0; k < i; ++k) x[i] -= Rs[(p0 + k) * bp + p] * x[k];
+        x[i] /= Rs[p * bp + p];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kSolveChunk; ++i) {
+      const int p = p0 + i;
+      if (p < nb_host) Qt[(int64_t)p * ldq + c] = (p < bp) ? x[i] : 0.0;
+    }
+  }
+}
+
+// Re-orthonormalisation factor for Qn = M2 Qtmp from G2 = Qtmp Qtmp^T
+// (b' x b').  With E = G2 - I, the Cholesky factor is R2 = I + U with
+// U = triu(E) - diag(E)/2 + O(|E|^2), so M2 = R2^{-T} = I - tril(E) +
+// diag(E)/2 + O(|E|^2).  When max|E| <= 1e-8 the first-order form is exact to
+// rounding and is written here (flag 0); otherwise flag 1 asks the exact
+// Cholesky path that follows to do the work.
+__global__ __launch_bounds__(256) void k_ortho_first_order(const double* __restrict__ G2,
+                                                           int64_t ldg,
+                                                           const int32_t* __restrict__ bprime,
+                                                           int32_t nb_host,
+                                                           double* __restrict__ M2,
+                                                           int64_t ldm,
+                                                           int32_t* __restrict__ need_exact) {
+  __shared__ double red[256];
+  const int bp = *bprime;
+  double mx = 0.0;
+  for (int e = threadIdx.x; e < bp * bp; e += 256) {
+    const int a = e / bp, c = e - a * bp;
+    const double v = G2[(int64_t)a * ldg + c] - (a == c ? 1.0 : 0.0);
+    mx = fmax(mx, fabs(v));
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  const bool small = red[0] <= 1e-8;
+  if (threadIdx.x == 0) *need_exact = small ? 0 : 1;
+  if (!small) return;
+  for (int e = threadIdx.x; e < nb_host * nb_host; e += 256) {
+    const int a = e / nb_host, c = e - a * nb_host;
+    double v = 0.0;
+    if (a < bp && c < bp) {
+      const double E = G2[(int64_t)a * ldg + c] - (a == c ? 1.0 : 0.0);
+      if (a == c) v = 1.0 - 0.5 * E;
+      else if (c < a) v = -E;
+    }
+    M2[(int64_t)a * ldm + c] = v;
+  }
+}
+
+hipError_t launch_cpqr_piv(const double* G, int64_t ldg, int32_t nb, const int32_t* nb_dev,
+                           double tau_b, const double* xs2_rows, int32_t* piv, double* Rraw,
+                           int64_t ldr, double* Rp, int64_t ldp, int32_t* bprime_out,
+                           double* tail1_out, int32_t* stop_out, hipStream_t s) {
+  if (nb <= 0 || nb > kMaxB) return hipErrorInvalidValue;
+  static bool attr_set = false;
+  const size_t lds = (size_t)kMaxB * (kMaxB + 1) * sizeof(double);
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_cpqr_piv,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_cpqr_piv, dim3(1), dim3(kPivThreads),
+                     (size_t)nb * (nb + 1) * sizeof(double), s, G, ldg, nb, nb_dev, tau_b,
+                     xs2_rows, piv, Rraw, ldr, Rp, ldp, bprime_out, tail1_out, stop_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_qsolve(const double* Vt, int64_t ldv, const int32_t* piv, const double* Rp,
+                         int64_t ldp, const int32_t* bprime, int32_t nb_host, int64_t ncols,
+                         double* Qt, int64_t ldq, hipStream_t s) {
+  if (ncols <= 0) return hipSuccess;
+  if (nb_host <= 0 || nb_host > kMaxB) return hipErrorInvalidValue;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_qsolve,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(kMaxB * kMaxB * sizeof(double)));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_qsolve, dim3((unsigned)ceil_div(ncols, 64)), dim3(64),
+                     (size_t)nb_host * nb_host * sizeof(double), s, Vt, ldv, piv, Rp, ldp,
+                     bprime, nb_host, ncols, Qt, ldq);
+  return hipGetLastError();
+}
+
+hipError_t launch_ortho_first_order(const double* G2, int64_t ldg, const int32_t* bprime,
+                                    int32_t nb_host, double* M2, int64_t ldm,
+                                    int32_t* need_exact, hipStream_t s) {
+  hipLaunchKernelGGL(k_ortho_first_order, dim3(1), dim3(256), 0, s, G2, ldg, bprime, nb_host,
+                     M2, ldm, need_exact);
+  return hipGetLastError();
 }
 
 size_t cpqr_lds_bytes(int32_t nb) { return (size_t)nb * (nb + 1) * sizeof(double); }
@@ -177,9 +494,9 @@ size_t cpqr_lds_bytes(int32_t nb) { return (size_t)nb * (nb + 1) * sizeof(double
 hipError_t launch_cpqr_gram_ex(const double* G, int64_t ldg, int32_t nb,
                                const int32_t* nb_dev, double tau_b, int pivoted,
                                const double* xs2_rows, int32_t* piv,
-                               double* Rraw, int64_t ldr, double* Rperm,
-                               int32_t* bprime_out, double* tail1_out,
-                               int32_t* stop_out, hipStream_t s) {
+                               double* Rraw, int64_t ldr, double* Rperm, double* Mout,
+                               int64_t ldm, int32_t* bprime_out, double* tail1_out,
+                               int32_t* stop_out, hipStream_t s, const int32_t* run_flag) {
   if (nb <= 0 || nb > kMaxB) return hipErrorInvalidValue;
   static bool attr_set = false;
   if (!attr_set) {
@@ -189,9 +506,10 @@ hipError_t launch_cpqr_gram_ex(const double* G, int64_t ldg, int32_t nb,
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_cpqr_gram, dim3(1), dim3(kCpqrThreads), cpqr_lds_bytes(nb), s,
-                     G, ldg, nb, nb_dev, tau_b, pivoted, xs2_rows, piv, Rraw, ldr,
-                     Rperm, bprime_out, tail1_out, stop_out);
+  const int threads = nb <= 64 ? 64 : 128;
+  hipLaunchKernelGGL(k_cpqr_gram, dim3(1), dim3(threads), cpqr_lds_bytes(nb), s, G, ldg, nb,
+                     nb_dev, tau_b, pivoted, xs2_rows, piv, Rraw, ldr, Rperm, Mout, ldm,
+                     bprime_out, tail1_out, stop_out, run_flag);
   return hipGetLastError();
 }
 

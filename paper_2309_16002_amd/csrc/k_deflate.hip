@@ -29,7 +29,11 @@
 // Lane layouts (measured on gfx950): for all three instructions lane l
 // supplies A[l%16][k(l)] and B[k(l)][l%16]; the 16x16 result is D[row][l%16]
 // with row = 4(l/16) + q for the FP32-accumulating instructions and
-// row = l/16 + 4q for the FP64 one (q = 0..3).
+// row = l/16 + 4q for the FP64 one (q = 0..3).  In phase 2 the result rows
+// are columns of R; they are assigned so that lane l's slot q always holds
+// column 4(l/16) + q of the 16-column tile (for FP64, tile row r holds column
+// pi(r) = 4 (r % 4) + r / 4), which makes every lane's four values contiguous
+// in memory.
 #include "rbrp_internal.h"
 
 #include <math.h>
@@ -79,82 +83,106 @@ __device__ __forceinline__ void split8(const float* x, bf8v& hi, bf8v& lo, bool 
 //   FP32/FP64: fragB1[g][bt][lane][4], fragA2[g][kb][lane][4]   (BT tiles of 16)
 //   BF16:      fragB1[g/2][bt][lane][8] (hi, then lo buffer of the same size),
 //              fragA2[g][ks][lane][8]   (ks: chunks of 32 b'-columns)
+//
+// Per-wave partial P tiles in LDS: tile t (= rt * BT + bt) of 16 x 16, stored
+// in accumulator order (lane, slot) with 4 floats of padding after each group
+// of 16 lanes, so that the transposed gathers of phase 2 hit distinct banks.
+constexpr int kLaneGroup = 68;            // 16 lanes x 4 slots + 4 padding
+constexpr int kTileElems = 4 * kLaneGroup;
 
-template <int MODE, int RT, int CT, int BT>
-__global__ __launch_bounds__(512) void k_deflate(
-    typename DT<MODE>::T* __restrict__ R, int64_t ldr, int64_t m, int nw,
-    const void* __restrict__ fragB1, const void* __restrict__ fragA2,
-    int64_t frag_stride, const int32_t* __restrict__ bprime_p,
-    typename DT<MODE>::T* __restrict__ L, int64_t ldl, int64_t kS,
-    const int32_t* __restrict__ sel_block, int32_t t, double* __restrict__ d,
+__device__ __forceinline__ int slot_off(int tile, int ln, int q) {
+  return tile * kTileElems + (ln >> 4) * kLaneGroup + (ln & 15) * 4 + q;
+}
+
+// Loads are issued in the order they are consumed (R chunk ct, then its Q'
+// fragments), kDepth chunks ahead, so that phase-1 MFMAs start as soon as the
+// first chunk arrives while the rest of the panel streams in; phase 2 streams
+// the updated R back out chunk by chunk.  NB, the number of active 16-wide
+// b' tiles, is a compile-time constant of each instantiated body.
+constexpr int kDepth = 3;   // default prefetch depth (chunks of 16 columns)
+
+template <int MODE, int RT, int CT, int BT, int NB, int DEPTH>
+__device__ __forceinline__ void deflate_body(
+    typename DT<MODE>::T* __restrict__ Rw, uint32_t ldr32, int64_t m, int nw, int w, int lane,
+    const void* __restrict__ fragB1, const void* __restrict__ fragA2, int64_t frag_stride,
+    int g0, int bp, typename DT<MODE>::T* __restrict__ Lp, uint32_t ldl32, int32_t t,
+    const int32_t* __restrict__ sb_s, typename DT<MODE>::T* __restrict__ Ps,
+    double* __restrict__ Ns, int64_t r0, double* __restrict__ d,
     double* __restrict__ part_sum, double* __restrict__ part_max) {
   typedef typename DT<MODE>::T T;
   typedef typename DT<MODE>::V V;
   constexpr int MP = 16 * RT;
   constexpr bool BF = (MODE == kModeBF16x3 || MODE == kModeBF16);
   constexpr bool SPLIT = (MODE == kModeBF16x3);
-  constexpr int SLOT = RT * BT * 64 * 4;  // accumulator elements per wave
-  extern __shared__ __align__(16) unsigned char smem[];
-  T* Ps = reinterpret_cast<T*>(smem);                          // nw * SLOT
-  double* Ns = reinterpret_cast<double*>(smem + (size_t)nw * SLOT * sizeof(T));  // nw * MP
-
-  const int bp = *bprime_p;
-  if (bp <= 0) return;
-  const int nbt = (bp + 15) >> 4;          // active 16-wide tiles of b'
-  const int nks = (bp + 31) >> 5;          // active 32-wide chunks (BF16 phase 2)
-  const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
+  constexpr int SLOT = RT * BT * kTileElems;
   const int l16 = lane & 15, lhi = lane >> 4;
-  const int64_t r0 = (int64_t)blockIdx.x * MP;
-  const int g0 = w * CT;                   // first global column tile of the wave
 
-  // ---- load the panel slice ----
   V Rreg[RT][CT];
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt) {
-    const T* rp = R + (r0 + 16 * rt + l16) * ldr;
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-      const int64_t c0 = 16 * (int64_t)(g0 + ct);
-      if constexpr (MODE == kModeF64) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Rreg[rt][ct][q] = rp[c0 + lhi + 4 * q];
-      } else {
-        Rreg[rt][ct] = *reinterpret_cast<const f4v*>(rp + c0 + 4 * lhi);
-      }
-    }
-  }
-
-  // ---- phase 1: partial P = R_slice Q'_slice ----
-  V Pacc[RT][BT];
+  V Pacc[RT][NB];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int bt = 0; bt < BT; ++bt)
+    for (int bt = 0; bt < NB; ++bt)
 #pragma unroll
       for (int q = 0; q < 4; ++q) Pacc[rt][bt][q] = (T)0;
 
+  auto load_r = [&](int ct) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+      Rreg[rt][ct] = *reinterpret_cast<const V*>(Rw + (uint32_t)(16 * rt + l16) * ldr32 +
+                                                 16 * ct + 4 * lhi);
+  };
+
+  // ---- phase 1: partial P = R_slice Q'_slice, R streamed in ----
   if constexpr (!BF) {
-    const V* fb = reinterpret_cast<const V*>(fragB1);
+    const V* fb = reinterpret_cast<const V*>(fragB1) + (int64_t)g0 * BT * 64;
+    V fr[DEPTH][NB];
+#pragma unroll
+    for (int k = 0; k < DEPTH; ++k) {
+      if (k < CT) {
+        load_r(k);
+#pragma unroll
+        for (int bt = 0; bt < NB; ++bt) fr[k][bt] = fb[(uint32_t)((k * BT + bt) * 64) + lane];
+      }
+    }
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
+      const int sl = ct % DEPTH;
 #pragma unroll
-      for (int bt = 0; bt < BT; ++bt) {
-        if (bt < nbt) {
-          const V bfr = fb[((int64_t)(g0 + ct) * BT + bt) * 64 + lane];
+      for (int bt = 0; bt < NB; ++bt)
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-              Pacc[rt][bt] = mfma4<MODE>(Rreg[rt][ct][i], bfr[i], Pacc[rt][bt]);
-        }
+          for (int rt = 0; rt < RT; ++rt)
+            Pacc[rt][bt] = mfma4<MODE>(Rreg[rt][ct][i], fr[sl][bt][i], Pacc[rt][bt]);
+      if (ct + DEPTH < CT) {
+        load_r(ct + DEPTH);
+#pragma unroll
+        for (int bt = 0; bt < NB; ++bt)
+          fr[sl][bt] = fb[(uint32_t)(((ct + DEPTH) * BT + bt) * 64) + lane];
       }
     }
   } else {
-    const bf8v* fbh = reinterpret_cast<const bf8v*>(fragB1);
+    constexpr int C2 = CT / 2;
+    const bf8v* fbh = reinterpret_cast<const bf8v*>(fragB1) + (int64_t)(g0 >> 1) * BT * 64;
     const bf8v* fbl = fbh + frag_stride;
+    bf8v frh[DEPTH][NB], frl[DEPTH][NB];
 #pragma unroll
-    for (int c2 = 0; c2 < CT / 2; ++c2) {
+    for (int k = 0; k < DEPTH; ++k) {
+      if (k < C2) {
+        load_r(2 * k);
+        load_r(2 * k + 1);
+#pragma unroll
+        for (int bt = 0; bt < NB; ++bt) {
+          const uint32_t o = (uint32_t)((k * BT + bt) * 64) + lane;
+          frh[k][bt] = fbh[o];
+          if constexpr (SPLIT) frl[k][bt] = fbl[o];
+        }
+      }
+    }
+#pragma unroll
+    for (int c2 = 0; c2 < C2; ++c2) {
+      const int sl = c2 % DEPTH;
       bf8v ah[RT], al[RT];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
@@ -166,145 +194,179 @@ __global__ __launch_bounds__(512) void k_deflate(
         }
         split8(x, ah[rt], al[rt], SPLIT);
       }
-      const int64_t gp = (g0 >> 1) + c2;
 #pragma unroll
-      for (int bt = 0; bt < BT; ++bt) {
-        if (bt < nbt) {
-          const int64_t o = (gp * BT + bt) * 64 + lane;
-          const bf8v bh = fbh[o];
+      for (int bt = 0; bt < NB; ++bt) {
 #pragma unroll
-          for (int rt = 0; rt < RT; ++rt) Pacc[rt][bt] = mfma_bf16(ah[rt], bh, Pacc[rt][bt]);
-          if constexpr (SPLIT) {
-            const bf8v bl = fbl[o];
+        for (int rt = 0; rt < RT; ++rt) Pacc[rt][bt] = mfma_bf16(ah[rt], frh[sl][bt], Pacc[rt][bt]);
+        if constexpr (SPLIT) {
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) {
-              Pacc[rt][bt] = mfma_bf16(ah[rt], bl, Pacc[rt][bt]);
-              Pacc[rt][bt] = mfma_bf16(al[rt], bh, Pacc[rt][bt]);
-            }
+          for (int rt = 0; rt < RT; ++rt) {
+            Pacc[rt][bt] = mfma_bf16(ah[rt], frl[sl][bt], Pacc[rt][bt]);
+            Pacc[rt][bt] = mfma_bf16(al[rt], frh[sl][bt], Pacc[rt][bt]);
           }
+        }
+      }
+      if (c2 + DEPTH < C2) {
+        load_r(2 * (c2 + DEPTH));
+        load_r(2 * (c2 + DEPTH) + 1);
+#pragma unroll
+        for (int bt = 0; bt < NB; ++bt) {
+          const uint32_t o = (uint32_t)(((c2 + DEPTH) * BT + bt) * 64) + lane;
+          frh[sl][bt] = fbh[o];
+          if constexpr (SPLIT) frl[sl][bt] = fbl[o];
         }
       }
     }
   }
 
-  // ---- cross-wave reduction of P in LDS (fixed wave order) ----
+  // ---- cross-wave reduction of P in LDS (fixed wave order), L written ----
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int bt = 0; bt < BT; ++bt)
-      if (bt < nbt) {
-        T* dst = Ps + (size_t)w * SLOT + ((rt * BT + bt) * 64 + lane) * 4;
+    for (int bt = 0; bt < NB; ++bt) {
+      T* dst = Ps + (size_t)w * SLOT + slot_off(rt * BT + bt, lane, 0);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) dst[q] = Pacc[rt][bt][q];
-      }
+      for (int q = 0; q < 4; ++q) dst[q] = Pacc[rt][bt][q];
+    }
   __syncthreads();
   {
-    const int nel = RT * BT * 64 * 4;
+    const int nel = RT * NB * 256;
     for (int e = threadIdx.x; e < nel; e += nw * 64) {
       const int q = e & 3;
       const int ln = (e >> 2) & 63;
-      const int tb = e >> 8;               // rt * BT + bt
-      const int bt = tb % BT, rt = tb / BT;
-      if (bt >= nbt) continue;
-      T s = Ps[e];
-      for (int ww = 1; ww < nw; ++ww) s += Ps[(size_t)ww * SLOT + e];
-      Ps[e] = s;
+      const int tb = e >> 8;                   // rt * NB + bt
+      const int bt = tb % NB, rt = tb / NB;
+      const int off = slot_off(rt * BT + bt, ln, q);
+      T s = Ps[off];
+      for (int ww = 1; ww < nw; ++ww) s += Ps[(size_t)ww * SLOT + off];
+      Ps[off] = s;
       const int row = 16 * rt + drow<MODE>(ln, q);
       const int bcol = 16 * bt + (ln & 15);
-      const int64_t grow = r0 + row;
-      if (grow < m && bcol < bp) {
-        const int32_t sb = sel_block[grow];
-        L[grow * ldl + kS + bcol] = (sb >= 0 && sb < t) ? (T)0 : s;
+      if (r0 + row < m && bcol < bp) {
+        const int32_t sb = sb_s[row];
+        Lp[(uint32_t)row * ldl32 + (uint32_t)bcol] = (sb >= 0 && sb < t) ? (T)0 : s;
       }
     }
   }
   __syncthreads();
 
-  // ---- phase 2: R <- R - P Q'^T on the register-resident slice ----
-  // P fragment for phase 2: B[k][col] = -P[16 rt + col][k]; the reduced P sits
-  // in slot 0 in phase-1 accumulator order.
+  // reduced P in slot 0, accumulator order of phase 1
   auto p_at = [&](int row, int bcol) -> T {
     const int rt = row >> 4, rr = row & 15;
     const int bt = bcol >> 4, bc = bcol & 15;
     int ln, q;
     if constexpr (MODE == kModeF64) { ln = 16 * (rr & 3) + bc; q = rr >> 2; }
     else { ln = 16 * (rr >> 2) + bc; q = rr & 3; }
-    return Ps[((rt * BT + bt) * 64 + ln) * 4 + q];
+    return Ps[slot_off(rt * BT + bt, ln, q)];
   };
 
+  // ---- phase 2: R <- R - P Q'^T, stored chunk by chunk; row norms in FP64 ----
+  double nrm[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) nrm[rt] = 0.0;
+  auto finish_chunk = [&](int ct) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double v = (double)Rreg[rt][ct][q];
+        nrm[rt] += v * v;
+      }
+      *reinterpret_cast<V*>(Rw + (uint32_t)(16 * rt + l16) * ldr32 + 16 * ct + 4 * lhi) =
+          Rreg[rt][ct];
+    }
+  };
   if constexpr (!BF) {
-    T Pf[RT][4 * BT];
+    T Pf[RT][4 * NB];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int ks = 0; ks < 4 * BT; ++ks)
-        Pf[rt][ks] = (ks < 4 * nbt) ? -p_at(16 * rt + l16, 4 * ks + lhi) : (T)0;
-    const V* fa = reinterpret_cast<const V*>(fragA2);
+      for (int ks = 0; ks < 4 * NB; ++ks) Pf[rt][ks] = -p_at(16 * rt + l16, 4 * ks + lhi);
+    const V* fa = reinterpret_cast<const V*>(fragA2) + (int64_t)g0 * BT * 64;
+    V fr[2][NB];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+      if (k < CT) {
+#pragma unroll
+        for (int kb = 0; kb < NB; ++kb) fr[k][kb] = fa[(uint32_t)((k * BT + kb) * 64) + lane];
+      }
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
+      const int sl = ct & 1;
 #pragma unroll
-      for (int kb = 0; kb < BT; ++kb) {
-        if (kb < nbt) {
-          const V afr = fa[((int64_t)(g0 + ct) * BT + kb) * 64 + lane];
+      for (int kb = 0; kb < NB; ++kb)
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-              Rreg[rt][ct] = mfma4<MODE>(afr[j], Pf[rt][4 * kb + j], Rreg[rt][ct]);
-        }
+          for (int rt = 0; rt < RT; ++rt)
+            Rreg[rt][ct] = mfma4<MODE>(fr[sl][kb][j], Pf[rt][4 * kb + j], Rreg[rt][ct]);
+      if (ct + 2 < CT) {
+#pragma unroll
+        for (int kb = 0; kb < NB; ++kb)
+          fr[sl][kb] = fa[(uint32_t)(((ct + 2) * BT + kb) * 64) + lane];
       }
+      finish_chunk(ct);
     }
   } else {
-    constexpr int KS = BT / 2;
-    bf8v Ph[RT][KS], Pl[RT][KS];
+    constexpr int KS = BT / 2;               // fragment chunks of 32 in the buffer
+    constexpr int NK = (NB + 1) / 2;         // active chunks of 32
+    bf8v Ph[RT][NK], Pl[RT][NK];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
+      for (int ks = 0; ks < NK; ++ks) {
         float x[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int bcol = 32 * ks + 8 * lhi + j;
-          x[j] = (ks < nks) ? -p_at(16 * rt + l16, bcol) : 0.0f;
+          x[j] = (bcol < 16 * NB) ? -p_at(16 * rt + l16, bcol) : 0.0f;
         }
         split8(x, Ph[rt][ks], Pl[rt][ks], SPLIT);
       }
-    const bf8v* fah = reinterpret_cast<const bf8v*>(fragA2);
+    const bf8v* fah = reinterpret_cast<const bf8v*>(fragA2) + (int64_t)g0 * KS * 64;
     const bf8v* fal = fah + frag_stride;
+    bf8v frh[2][NK], frl[2][NK];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+      if (k < CT) {
+#pragma unroll
+        for (int ks = 0; ks < NK; ++ks) {
+          const uint32_t o = (uint32_t)((k * KS + ks) * 64) + lane;
+          frh[k][ks] = fah[o];
+          if constexpr (SPLIT) frl[k][ks] = fal[o];
+        }
+      }
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
+      const int sl = ct & 1;
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        if (ks < nks) {
-          const int64_t o = ((int64_t)(g0 + ct) * KS + ks) * 64 + lane;
-          const bf8v ah = fah[o];
+      for (int ks = 0; ks < NK; ++ks) {
 #pragma unroll
-          for (int rt = 0; rt < RT; ++rt) Rreg[rt][ct] = mfma_bf16(ah, Ph[rt][ks], Rreg[rt][ct]);
-          if constexpr (SPLIT) {
-            const bf8v al = fal[o];
+        for (int rt = 0; rt < RT; ++rt) Rreg[rt][ct] = mfma_bf16(frh[sl][ks], Ph[rt][ks], Rreg[rt][ct]);
+        if constexpr (SPLIT) {
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) {
-              Rreg[rt][ct] = mfma_bf16(ah, Pl[rt][ks], Rreg[rt][ct]);
-              Rreg[rt][ct] = mfma_bf16(al, Ph[rt][ks], Rreg[rt][ct]);
-            }
+          for (int rt = 0; rt < RT; ++rt) {
+            Rreg[rt][ct] = mfma_bf16(frh[sl][ks], Pl[rt][ks], Rreg[rt][ct]);
+            Rreg[rt][ct] = mfma_bf16(frl[sl][ks], Ph[rt][ks], Rreg[rt][ct]);
           }
         }
       }
+      if (ct + 2 < CT) {
+#pragma unroll
+        for (int ks = 0; ks < NK; ++ks) {
+          const uint32_t o = (uint32_t)(((ct + 2) * KS + ks) * 64) + lane;
+          frh[sl][ks] = fah[o];
+          if constexpr (SPLIT) frl[sl][ks] = fal[o];
+        }
+      }
+      finish_chunk(ct);
     }
   }
 
-  // ---- squared row norms (FP64) and store ----
-  double nrm[RT];
+  // ---- squared row norms: lanes of one row, then waves in order ----
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
-    double s = 0.0;
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const double v = (double)Rreg[rt][ct][q];
-        s += v * v;
-      }
+    double s = nrm[rt];
     s += __shfl_xor(s, 16, kWave);
     s += __shfl_xor(s, 32, kWave);
     nrm[rt] = s;
@@ -313,20 +375,6 @@ __global__ __launch_bounds__(512) void k_deflate(
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) Ns[w * MP + 16 * rt + lane] = nrm[rt];
   }
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt) {
-    T* rp = R + (r0 + 16 * rt + l16) * ldr;
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-      const int64_t c0 = 16 * (int64_t)(g0 + ct);
-      if constexpr (MODE == kModeF64) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) rp[c0 + lhi + 4 * q] = Rreg[rt][ct][q];
-      } else {
-        *reinterpret_cast<f4v*>(rp + c0 + 4 * lhi) = Rreg[rt][ct];
-      }
-    }
-  }
   __syncthreads();
   if (w == 0) {
     double dv = 0.0;
@@ -334,7 +382,7 @@ __global__ __launch_bounds__(512) void k_deflate(
       double s = 0.0;
       for (int ww = 0; ww < nw; ++ww) s += Ns[ww * MP + lane];
       const int64_t row = r0 + lane;
-      const bool skel = row >= m || sel_block[row] >= 0;
+      const bool skel = row >= m || sb_s[lane] >= 0;
       dv = skel ? 0.0 : s;
       d[row] = dv;
     }
@@ -349,6 +397,57 @@ __global__ __launch_bounds__(512) void k_deflate(
       part_max[blockIdx.x] = mx;
     }
   }
+}
+
+template <int MODE, int RT, int CT, int BT, int NWMAX, int DEPTH = kDepth, int WPE = 2>
+__global__ __launch_bounds__(64 * NWMAX) __attribute__((amdgpu_waves_per_eu(WPE))) void k_deflate(
+    typename DT<MODE>::T* __restrict__ R, int64_t ldr, int64_t m, int nw,
+    const void* __restrict__ fragB1, const void* __restrict__ fragA2,
+    int64_t frag_stride, const int32_t* __restrict__ bprime_p,
+    typename DT<MODE>::T* __restrict__ L, int64_t ldl, int64_t kS,
+    const int32_t* __restrict__ sel_block, int32_t t, double* __restrict__ d,
+    double* __restrict__ part_sum, double* __restrict__ part_max) {
+  typedef typename DT<MODE>::T T;
+  constexpr int MP = 16 * RT;
+  constexpr int SLOT = RT * BT * kTileElems;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* Ps = reinterpret_cast<T*>(smem);                                            // nw * SLOT
+  double* Ns = reinterpret_cast<double*>(smem + (size_t)nw * SLOT * sizeof(T));  // nw * MP
+  __shared__ int32_t sb_s[MP];
+
+  const int lane = threadIdx.x & 63;
+  // wave index as a scalar, so that per-wave bases live in SGPRs and every
+  // load below is a scalar base + 32-bit lane offset
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t r0 = (int64_t)blockIdx.x * MP;
+  const int g0 = w * CT;                   // first global column tile of the wave
+  T* __restrict__ Rw = R + r0 * ldr + 16 * (int64_t)g0;   // this wave's panel slice
+  T* __restrict__ Lp = L + r0 * ldl + kS;
+  // skeleton flags of the panel's rows (for the L rows and the norms)
+  if (threadIdx.x < MP) {
+    const int64_t row = r0 + threadIdx.x;
+    sb_s[threadIdx.x] = row < m ? sel_block[row] : -2;
+  }
+  const int bp = *bprime_p;
+  if (bp <= 0) return;
+  const int nbt = (bp + 15) >> 4;          // active 16-wide tiles of b'
+#define RBRP_BODY(NBV)                                                                   \
+  deflate_body<MODE, RT, CT, BT, NBV, DEPTH>(Rw, (uint32_t)ldr, m, nw, w, lane, fragB1, fragA2,  \
+                                      frag_stride, g0, bp, Lp, (uint32_t)ldl, t, sb_s, Ps, \
+                                      Ns, r0, d, part_sum, part_max)
+  if constexpr (MODE == kModeBF16x3 || MODE == kModeBF16) {
+    // BF16 phase 2 works in chunks of 32 b'-columns: round the tile count up
+    const int nb2 = (nbt + 1) & ~1;
+    if constexpr (BT >= 8) { if (nb2 > 4) { RBRP_BODY(8); return; } }
+    if constexpr (BT >= 4) { if (nb2 > 2) { RBRP_BODY(4); return; } }
+    RBRP_BODY(2);
+  } else {
+    if constexpr (BT >= 8) { if (nbt > 4) { RBRP_BODY(8); return; } }
+    if constexpr (BT >= 4) { if (nbt > 2) { RBRP_BODY(4); return; } }
+    if constexpr (BT >= 2) { if (nbt > 1) { RBRP_BODY(2); return; } }
+    RBRP_BODY(1);
+  }
+#undef RBRP_BODY
 }
 
 // ---------------------------------------------------------------------------
@@ -376,9 +475,11 @@ __global__ __launch_bounds__(256) void k_make_frags(const double* __restrict__ Q
     const int bt = (int)(gb % BT);
     const int64_t g = gb / BT;
     const int l16 = lane & 15, lhi = lane >> 4;
-    const int dr = (MODE == kModeF64) ? (lhi + 4 * i) : (4 * lhi + i);
-    reinterpret_cast<T*>(fragB1)[e] = (T)q_at(16 * g + dr, 16 * bt + l16);
-    reinterpret_cast<T*>(fragA2)[e] = (T)q_at(16 * g + l16, 16 * bt + 4 * i + lhi);
+    // phase-1 operand: the column held by slot i of lane l; phase-2 operand:
+    // the column assigned to result row l % 16
+    const int pr = (MODE == kModeF64) ? (4 * (l16 & 3) + (l16 >> 2)) : l16;
+    reinterpret_cast<T*>(fragB1)[e] = (T)q_at(16 * g + 4 * lhi + i, 16 * bt + l16);
+    reinterpret_cast<T*>(fragA2)[e] = (T)q_at(16 * g + pr, 16 * bt + 4 * i + lhi);
   } else {
     // fragB1: (g2, bt, lane, j) with G/2 column-tile pairs; fragA2: (g, ks, lane, j)
     const int j = e & 7;
@@ -410,38 +511,59 @@ __global__ __launch_bounds__(256) void k_make_frags(const double* __restrict__ Q
 }
 
 // ---------------------------------------------------------------------------
-// Configuration: n_pad = 16 * CT * nw with CT in {2,4,8,16,32}, nw in [1,8].
+// Configuration: n_pad = 16 * CT * nw.  Workgroups of up to four waves keep
+// two workgroups resident per CU (registers <= 256 per lane); the widest
+// inputs use eight waves of 32 column tiles.
 
 struct DeflateCfg {
-  int ct, rt, nw;
+  int ct, rt, nw, nwmax;
 };
 
-static bool pick_cfg(int mode, int64_t ldr, DeflateCfg* c) {
-  const int cts[5] = {2, 4, 8, 16, 32};
-  for (int i = 0; i < 5; ++i) {
-    const int ct = cts[i];
-    if (ldr % (16 * ct)) continue;
-    const int64_t nw = ldr / (16 * ct);
-    if (nw < 1 || nw > 8) continue;
-    if (mode == kModeF64 && ct > 16) return false;
-    c->ct = ct;
-    c->nw = (int)nw;
-    c->rt = (ct >= 32 || (mode == kModeF64 && ct >= 16)) ? 1 : 2;
-    return true;
+struct Shape { int ct, nwmax; };
+static const Shape kShapes[] = {{4, 4}, {8, 4}, {16, 4}, {32, 4}, {32, 8}};
+
+static bool shape_ok(int mode, const Shape& sh) {
+  if (mode == kModeF64 && sh.ct > 16) return false;
+  return true;
+}
+
+static int rt_for(int mode, int ct) {
+  if (mode == kModeF64) return ct >= 16 ? 1 : 2;
+  return ct >= 32 ? 1 : 2;
+}
+
+// smallest 16*CT*nw >= n; ties go to the narrower column tile (more rows per
+// workgroup), then to fewer waves
+static bool best_cfg(int mode, int64_t n, DeflateCfg* out) {
+  int64_t best = -1;
+  for (const Shape& sh : kShapes) {
+    if (!shape_ok(mode, sh)) continue;
+    const int lo = sh.nwmax == 8 ? 5 : 1;
+    for (int nw = lo; nw <= sh.nwmax; ++nw) {
+      const int64_t v = 16LL * sh.ct * nw;
+      if (v < n) continue;
+      if (best < 0 || v < best) {
+        best = v;
+        out->ct = sh.ct;
+        out->nw = nw;
+        out->nwmax = sh.nwmax;
+        out->rt = rt_for(mode, sh.ct);
+      }
+    }
   }
-  return false;
+  return best > 0;
+}
+
+static bool pick_cfg(int mode, int64_t ldr, DeflateCfg* c) {
+  // ldr comes from deflate_pad_cols (FP32 shapes); recover the shape for mode
+  if (!best_cfg(mode, ldr, c)) return false;
+  return 16LL * c->ct * c->nw == ldr;
 }
 
 int64_t deflate_pad_cols(int64_t n) {
-  // smallest 16*CT*nw >= n over the supported shapes (ties: fewer waves)
-  int64_t best = -1;
-  const int cts[5] = {2, 4, 8, 16, 32};
-  for (int i = 0; i < 5; ++i)
-    for (int nw = 1; nw <= 8; ++nw) {
-      const int64_t v = 16LL * cts[i] * nw;
-      if (v >= n && (best < 0 || v < best)) best = v;
-    }
-  return best;
+  DeflateCfg c;
+  if (!best_cfg(kModeF32, n, &c)) return -1;
+  return 16LL * c.ct * c.nw;
 }
 
 static int bt_for(int mode, int bmax) {
@@ -466,31 +588,30 @@ int deflate_rows_per_wg(int mode, int64_t ldr) {
 int64_t deflate_num_partials(int64_t mr) { return ceil_div(mr, 16); }
 
 int64_t frag_elems(int mode, int64_t ldr, int bmax) {
-  // elements (T for FP32/FP64; bf16 for BF16, per hi/lo half) of one buffer
   const int bt = bt_for(mode, bmax);
   const int64_t G = ldr / 16;
-  return G * bt * 64 * 4 * ((mode == kModeBF16x3 || mode == kModeBF16) ? 1 : 1);
+  return G * bt * 64 * 4;
 }
 
-template <int MODE, int RT, int CT, int BT>
+template <int MODE, int RT, int CT, int BT, int NWMAX>
 static hipError_t run_deflate(const DeflateCfg& c, int64_t grid, hipStream_t s,
                               void* R, int64_t ldr, int64_t m, const void* fB,
                               const void* fA, int64_t fstride, const int32_t* bp,
                               void* L, int64_t ldl, int64_t kS, const int32_t* sel,
                               int32_t t, double* d, double* ps, double* pm) {
   typedef typename DT<MODE>::T T;
-  const size_t slot = (size_t)RT * BT * 64 * 4 * sizeof(T);
+  const size_t slot = (size_t)RT * BT * kTileElems * sizeof(T);
   const size_t lds = c.nw * slot + (size_t)c.nw * 16 * RT * sizeof(double);
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_deflate<MODE, RT, CT, BT>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_deflate<MODE, RT, CT, BT, NWMAX>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       160 * 1024);
+                                       160 * 1024 - 1024);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_deflate<MODE, RT, CT, BT>), dim3((unsigned)grid),
+  if (lds > 160 * 1024 - 1024) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_deflate<MODE, RT, CT, BT, NWMAX>), dim3((unsigned)grid),
                      dim3(64 * c.nw), lds, s, (T*)R, ldr, m, c.nw, fB, fA, fstride,
                      bp, (T*)L, ldl, kS, sel, t, d, ps, pm);
   return hipGetLastError();
@@ -502,21 +623,21 @@ static hipError_t dispatch_ct(const DeflateCfg& c, int64_t mr, hipStream_t s, vo
                               int64_t fstride, const int32_t* bp, void* L, int64_t ldl,
                               int64_t kS, const int32_t* sel, int32_t t, double* d,
                               double* ps, double* pm) {
-#define RBRP_DEF_CASE(CTV, RTV)                                                        \
-  if (c.ct == CTV && c.rt == RTV)                                                      \
-    return run_deflate<MODE, RTV, CTV, BT>(c, mr / (16 * RTV), s, R, ldr, m, fB, fA,   \
-                                           fstride, bp, L, ldl, kS, sel, t, d, ps, pm);
+#define RBRP_DEF_CASE(CTV, RTV, NWV)                                                   \
+  if (c.ct == CTV && c.rt == RTV && c.nwmax == NWV)                                   \
+    return run_deflate<MODE, RTV, CTV, BT, NWV>(c, mr / (16 * RTV), s, R, ldr, m, fB,  \
+                                                fA, fstride, bp, L, ldl, kS, sel, t, d, \
+                                                ps, pm);
   if constexpr (MODE == kModeF64) {
-    RBRP_DEF_CASE(2, 2)
-    RBRP_DEF_CASE(4, 2)
-    RBRP_DEF_CASE(8, 2)
-    RBRP_DEF_CASE(16, 1)
+    RBRP_DEF_CASE(4, 2, 4)
+    RBRP_DEF_CASE(8, 2, 4)
+    RBRP_DEF_CASE(16, 1, 4)
   } else {
-    RBRP_DEF_CASE(2, 2)
-    RBRP_DEF_CASE(4, 2)
-    RBRP_DEF_CASE(8, 2)
-    RBRP_DEF_CASE(16, 2)
-    RBRP_DEF_CASE(32, 1)
+    RBRP_DEF_CASE(4, 2, 4)
+    RBRP_DEF_CASE(8, 2, 4)
+    RBRP_DEF_CASE(16, 2, 4)
+    RBRP_DEF_CASE(32, 1, 4)
+    RBRP_DEF_CASE(32, 1, 8)
   }
 #undef RBRP_DEF_CASE
   return hipErrorInvalidConfiguration;

@@ -40,14 +40,21 @@ __global__ __launch_bounds__(kDiag) void k_diag_inv(const double* __restrict__ L
   for (int i = 0; i < kDiag; ++i)
     A[i][j] = (i < nbk && j < nbk) ? L1[(b0 + i) * k + b0 + j] : (i == j ? 1.0 : 0.0);
   __syncthreads();
-  // column j of the inverse: x_i = (delta_ij - sum_{p<i} A[i][p] x_p) / A[i][i]
+  // column j of the inverse: x_i = (delta_ij - sum_{p<i} A[i][p] x_p) / A[i][i];
+  // four partial sums break the FMA dependency chain
   for (int i = 0; i < kDiag; ++i) {
-    double v = (i == j) ? 1.0 : 0.0;
+    double v = 0.0;
     if (i >= j) {
-      for (int p = j; p < i; ++p) v -= A[i][p] * X[p][j];
-      v /= A[i][i];
-    } else {
-      v = 0.0;
+      double s0 = (i == j) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int p = j;
+      for (; p + 3 < i; p += 4) {
+        s0 -= A[i][p] * X[p][j];
+        s1 -= A[i][p + 1] * X[p + 1][j];
+        s2 -= A[i][p + 2] * X[p + 2][j];
+        s3 -= A[i][p + 3] * X[p + 3][j];
+      }
+      for (; p < i; ++p) s0 -= A[i][p] * X[p][j];
+      v = ((s0 + s1) + (s2 + s3)) / A[i][i];
     }
     X[i][j] = v;
   }
@@ -120,15 +127,9 @@ hipError_t launch_interp(const void* L, int l_f64, int64_t ldl, int64_t m, int64
                       nullptr, nullptr, 1, s);
   if (e != hipSuccess) return e;
   for (int it = 0; it < refine; ++it) {
-    if (l_f64)
-      hipLaunchKernelGGL(k_to_f64<double>, dim3((unsigned)ceil_div(m * k, 256)), dim3(256),
-                         0, s, (const double*)L, ldl, m, k, E);
-    else
-      hipLaunchKernelGGL(k_to_f64<float>, dim3((unsigned)ceil_div(m * k, 256)), dim3(256),
-                         0, s, (const float*)L, ldl, m, k, E);
     // E = L - W L1 ;  W += E Linv
-    e = launch_gemm_f64(0, 0, m, k, k, -1.0, W, 0, ldw, L1, k, 1.0, E, k, nullptr,
-                        nullptr, 1, s);
+    e = launch_gemm_f64_cin(m, k, k, -1.0, W, ldw, L1, k, 1.0, L, l_f64 ? 0 : 1, ldl, E, k, 1,
+                            s);
     if (e != hipSuccess) return e;
     e = launch_gemm_f64(0, 0, m, k, k, 1.0, E, 0, k, Linv, k, 1.0, W, ldw, nullptr,
                         nullptr, 1, s);

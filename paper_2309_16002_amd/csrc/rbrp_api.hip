@@ -8,12 +8,6 @@
 #include <stdlib.h>
 #include <string.h>
 
-namespace rbrp {
-hipError_t launch_cpqr_gram_ex(const double*, int64_t, int32_t, const int32_t*, double,
-                               int, const double*, int32_t*, double*, int64_t, double*,
-                               int32_t*, double*, int32_t*, hipStream_t);
-}
-
 using namespace rbrp;
 
 namespace {
@@ -60,6 +54,9 @@ struct Work {
   int32_t* piv2;
   double* Rraw;
   double* R2raw;
+  double* Mc;
+  double* Mc2;
+  double* Qtmp;
   double* Qt;
   void* fragB1;
   void* fragA2;
@@ -126,6 +123,9 @@ size_t layout(const Plan& p, char* base, Work* w) {
   w->piv2 = cv.take<int32_t>(kMaxB);
   w->Rraw = cv.take<double>((size_t)p.b * p.b);
   w->R2raw = cv.take<double>((size_t)p.b * p.b);
+  w->Mc = cv.take<double>((size_t)p.b * p.b);
+  w->Mc2 = cv.take<double>((size_t)p.b * p.b);
+  w->Qtmp = cv.take<double>((size_t)p.b * p.ldr);
   w->Qt = cv.take<double>((size_t)p.k_max * p.ldr);
   w->fragB1 = cv.take<char>(frag_bytes(mode, p.ldr, p.b));
   w->fragA2 = cv.take<char>(frag_bytes(mode, p.ldr, p.b));
@@ -317,31 +317,36 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     RBRP_HIP(launch_gather_rows(X, dtype, n, ldx, w.idx, w.sc, bt, w.Vt, ldr, w.xs2, s));
     if (kS > 0) {
       for (int pass = 0; pass < 2; ++pass) {
-        RBRP_HIP(launch_gemm_f64(0, 1, kS, bt, ldr, 1.0, w.Qt, 0, ldr, w.Vt, ldr, 0.0, w.C,
-                                 bt, nullptr, nullptr, 0, s));
+        RBRP_HIP(launch_gemm_nt_small(kS, bt, ldr, 1.0, w.Qt, ldr, w.Vt, ldr, 0.0, w.C, bt,
+                                      nullptr, nullptr, s));
         RBRP_HIP(launch_gemm_f64(1, 0, bt, ldr, kS, -1.0, w.C, 0, bt, w.Qt, ldr, 1.0, w.Vt,
                                  ldr, nullptr, nullptr, 0, s));
       }
     }
-    // robust blockwise filter: pivoted Cholesky of V^T V
-    RBRP_HIP(launch_gemm_f64(0, 1, bt, bt, ldr, 1.0, w.Vt, 0, ldr, w.Vt, ldr, 0.0, w.G, bt,
-                             nullptr, nullptr, 0, s));
-    RBRP_HIP(launch_cpqr_gram_ex(w.G, bt, bt, &w.sc->nt, tau_b, 1, w.xs2, w.piv, w.Rraw, bt,
-                                 nullptr, &w.sc->bprime, &w.sc->tail1, &w.sc->stop_rank, s));
-    double* Qn = w.Qt + kS * ldr;
-    RBRP_HIP(launch_qform(w.Vt, ldr, w.piv, w.Rraw, bt, &w.sc->bprime, bt, ldr, Qn, ldr, s));
-    // reorthogonalisation: project against the basis, then Cholesky QR
+    // robust blockwise filter: pivoted Cholesky of V^T V, then the kept columns'
+    // orthonormal basis Q' = V(:, piv(1:b')) R11^{-1}
+    RBRP_HIP(launch_gemm_nt_small(bt, bt, ldr, 1.0, w.Vt, ldr, w.Vt, ldr, 0.0, w.G, bt, nullptr,
+                                  nullptr, s));
+    RBRP_HIP(launch_cpqr_piv(w.G, bt, bt, &w.sc->nt, tau_b, w.xs2, w.piv, w.Rraw, bt, w.Mc, bt,
+                             &w.sc->bprime, &w.sc->tail1, &w.sc->stop_rank, s));
+    RBRP_HIP(launch_qsolve(w.Vt, ldr, w.piv, w.Mc, bt, &w.sc->bprime, bt, ldr, w.Qtmp, ldr, s));
+    // second pass: project against the basis, then Cholesky QR
     if (kS > 0) {
-      RBRP_HIP(launch_gemm_f64(0, 1, kS, bt, ldr, 1.0, w.Qt, 0, ldr, Qn, ldr, 0.0, w.C, bt,
-                               nullptr, &w.sc->bprime, 0, s));
-      RBRP_HIP(launch_gemm_f64(1, 0, bt, ldr, kS, -1.0, w.C, 0, bt, w.Qt, ldr, 1.0, Qn, ldr,
-                               &w.sc->bprime, nullptr, 0, s));
+      RBRP_HIP(launch_gemm_nt_small(kS, bt, ldr, 1.0, w.Qt, ldr, w.Qtmp, ldr, 0.0, w.C, bt,
+                                    nullptr, nullptr, s));
+      RBRP_HIP(launch_gemm_f64(1, 0, bt, ldr, kS, -1.0, w.C, 0, bt, w.Qt, ldr, 1.0, w.Qtmp,
+                               ldr, nullptr, nullptr, 0, s));
     }
-    RBRP_HIP(launch_gemm_f64(0, 1, bt, bt, ldr, 1.0, Qn, 0, ldr, Qn, ldr, 0.0, w.G, bt,
-                             &w.sc->bprime, &w.sc->bprime, 0, s));
+    RBRP_HIP(launch_gemm_nt_small(bt, bt, ldr, 1.0, w.Qtmp, ldr, w.Qtmp, ldr, 0.0, w.G, bt,
+                                  nullptr, nullptr, s));
+    RBRP_HIP(launch_ortho_first_order(w.G, bt, &w.sc->bprime, bt, w.Mc2, bt,
+                                      &w.sc->need_exact, s));
     RBRP_HIP(launch_cpqr_gram_ex(w.G, bt, bt, &w.sc->bprime, 0.0, 0, nullptr, w.piv2, w.R2raw,
-                                 bt, nullptr, &w.sc->b2, nullptr, nullptr, s));
-    RBRP_HIP(launch_qform(Qn, ldr, nullptr, w.R2raw, bt, &w.sc->b2, bt, ldr, Qn, ldr, s));
+                                 bt, nullptr, w.Mc2, bt, &w.sc->b2, nullptr, nullptr, s,
+                                 &w.sc->need_exact));
+    double* Qn = w.Qt + kS * ldr;
+    RBRP_HIP(launch_gemm_f64(0, 0, bt, ldr, bt, 1.0, w.Mc2, 0, bt, w.Qtmp, ldr, 0.0, Qn, ldr,
+                             nullptr, nullptr, 0, s));
     RBRP_HIP(launch_append(w.idx, w.piv, &w.sc->bprime, kS, t, S, w.sel_block, s));
     // deflation of the residual
     int mode = p.native_mode;
@@ -467,8 +472,8 @@ rbrp_status rbrp_sample_block(const double* d, const uint8_t* excluded, int64_t 
 
 size_t rbrp_block_cpqr_workspace_size(int64_t n, int32_t nb) {
   if (n <= 0 || nb < 1 || nb > kMaxB) return 0;
-  return 6 * kAlign + sizeof(DevScalars) + sizeof(double) * (3 * (size_t)nb * nb) +
-         sizeof(int32_t) * kMaxB;
+  return 10 * kAlign + sizeof(DevScalars) + sizeof(double) * (5 * (size_t)nb * nb) +
+         sizeof(double) * (size_t)nb * n + sizeof(int32_t) * kMaxB;
 }
 
 rbrp_status rbrp_block_cpqr(const double* Vt, int64_t n, int32_t nb, int64_t ldv,
@@ -485,21 +490,27 @@ rbrp_status rbrp_block_cpqr(const double* Vt, int64_t n, int32_t nb, int64_t ldv
   double* G = cv.take<double>((size_t)nb * nb);
   double* Rraw = cv.take<double>((size_t)nb * nb);
   double* R2 = cv.take<double>((size_t)nb * nb);
+  double* Mc = cv.take<double>((size_t)nb * nb);
+  double* Mc2 = cv.take<double>((size_t)nb * nb);
+  double* Qtmp = cv.take<double>((size_t)nb * n);
   int32_t* piv2 = cv.take<int32_t>(kMaxB);
   hipStream_t s = (hipStream_t)stream;
   DevScalars* h = host_scalars();
   if (!h) return RBRP_E_HIP;
   RBRP_HIP(hipMemsetAsync(sc, 0, sizeof(DevScalars), s));
-  RBRP_HIP(launch_gemm_f64(0, 1, nb, nb, n, 1.0, Vt, 0, ldv, Vt, ldv, 0.0, G, nb, nullptr,
-                           nullptr, 0, s));
-  RBRP_HIP(launch_cpqr_gram_ex(G, nb, nb, nullptr, tau_b, 1, nullptr, piv, Rraw, nb, R,
-                               &sc->bprime, &sc->tail1, nullptr, s));
-  RBRP_HIP(launch_qform(Vt, ldv, piv, Rraw, nb, &sc->bprime, nb, n, Qt, ldq, s));
-  RBRP_HIP(launch_gemm_f64(0, 1, nb, nb, n, 1.0, Qt, 0, ldq, Qt, ldq, 0.0, G, nb,
-                           &sc->bprime, &sc->bprime, 0, s));
+  RBRP_HIP(launch_gemm_nt_small(nb, nb, n, 1.0, Vt, ldv, Vt, ldv, 0.0, G, nb, nullptr,
+                                nullptr, s));
+  RBRP_HIP(launch_cpqr_piv(G, nb, nb, nullptr, tau_b, nullptr, piv, Rraw, nb, R, nb,
+                           &sc->bprime, &sc->tail1, nullptr, s));
+  RBRP_HIP(launch_qsolve(Vt, ldv, piv, R, nb, &sc->bprime, nb, n, Qtmp, n, s));
+  RBRP_HIP(launch_gemm_nt_small(nb, nb, n, 1.0, Qtmp, n, Qtmp, n, 0.0, G, nb, nullptr,
+                                nullptr, s));
+  RBRP_HIP(launch_ortho_first_order(G, nb, &sc->bprime, nb, Mc2, nb, &sc->need_exact, s));
   RBRP_HIP(launch_cpqr_gram_ex(G, nb, nb, &sc->bprime, 0.0, 0, nullptr, piv2, R2, nb,
-                               nullptr, &sc->b2, nullptr, nullptr, s));
-  RBRP_HIP(launch_qform(Qt, ldq, nullptr, R2, nb, &sc->b2, nb, n, Qt, ldq, s));
+                               nullptr, Mc2, nb, &sc->b2, nullptr, nullptr, s,
+                               &sc->need_exact));
+  RBRP_HIP(launch_gemm_f64(0, 0, nb, n, nb, 1.0, Mc2, 0, nb, Qtmp, n, 0.0, Qt, ldq, nullptr,
+                           nullptr, 0, s));
   rbrp_status rs = fetch(h, sc, s);
   if (rs != RBRP_OK) return rs;
   *bprime_host = h->bprime;

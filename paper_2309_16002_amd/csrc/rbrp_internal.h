@@ -37,7 +37,8 @@ struct DevScalars {
   int32_t stop_rank;   // last block numerically inside span(Q)
   int32_t npos;        // rows with positive weight
   int32_t b2;          // steps completed by the reorthogonalisation Cholesky
-  int32_t pad[2];
+  int32_t need_exact;  // reorthogonalisation needs the exact Cholesky
+  int32_t pad[1];
 };
 
 // ---- launch wrappers (defined next to their kernels) ----
@@ -99,17 +100,52 @@ hipError_t launch_gemm_f64(int transA, int transB, int64_t M, int64_t N,
                            const int32_t* m_dev, const int32_t* n_dev,
                            int b_lower_tri, hipStream_t s);
 
+// C = alpha A B + beta Cin (A, B FP64 row-major; Cin FP32 or FP64, own ld).
+hipError_t launch_gemm_f64_cin(int64_t M, int64_t N, int64_t K, double alpha,
+                               const double* A, int64_t lda, const double* B, int64_t ldb,
+                               double beta, const void* Cin, int cin_f32, int64_t ldcin,
+                               double* C, int64_t ldc, int b_lower_tri, hipStream_t s);
+
 // Pivoted Cholesky of the nb x nb Gram matrix G (FP64) in one workgroup:
 // pivots, pivot rows of R with unpermuted columns (Rraw, row p = R_V(p,:)),
 // optionally the pivoted-order R (Rperm, nb x nb), b' by the truncation rule,
 // tail_1 = ||V||_F^2 and the rank-guard flag.  pivoted = 0 gives plain
 // Cholesky (for the reorthogonalisation pass).  nb <= kMaxB.
+// Mout (nb x nb, ld ldm, optional) receives R11^{-T} scattered to the
+// sampled order (zero outside the first b' rows), so that the orthonormal
+// basis rows of the kept columns are Q'^T = Mout V^T.
 hipError_t launch_cpqr_gram_ex(const double* G, int64_t ldg, int32_t nb,
                                const int32_t* nb_dev, double tau_b, int pivoted,
                                const double* xs2_rows, int32_t* piv,
-                               double* Rraw, int64_t ldr, double* Rperm,
-                               int32_t* bprime_out, double* tail1_out,
-                               int32_t* stop_out, hipStream_t s);
+                               double* Rraw, int64_t ldr, double* Rperm, double* Mout,
+                               int64_t ldm, int32_t* bprime_out, double* tail1_out,
+                               int32_t* stop_out, hipStream_t s,
+                               const int32_t* run_flag = nullptr);
+
+// Fast pivoted Cholesky for the filter (256 threads): pivots, b', pivot rows
+// Rraw (unpermuted columns), R11 in pivoted order (Rp, zero-padded to nb).
+hipError_t launch_cpqr_piv(const double* G, int64_t ldg, int32_t nb, const int32_t* nb_dev,
+                           double tau_b, const double* xs2_rows, int32_t* piv, double* Rraw,
+                           int64_t ldr, double* Rp, int64_t ldp, int32_t* bprime_out,
+                           double* tail1_out, int32_t* stop_out, hipStream_t s);
+
+// Qt[p,:] = (Vt[piv[p],:] - sum_{q<p} Rp[q][p] Qt[q,:]) / Rp[p][p], p < b';
+// rows b'..nb_host-1 zero.
+hipError_t launch_qsolve(const double* Vt, int64_t ldv, const int32_t* piv, const double* Rp,
+                         int64_t ldp, const int32_t* bprime, int32_t nb_host, int64_t ncols,
+                         double* Qt, int64_t ldq, hipStream_t s);
+
+// First-order Cholesky-QR factor M2 = R2^{-T} of G2 = I + E when max|E| <=
+// 1e-8 (need_exact = 0), else need_exact = 1 and M2 is left to the exact path.
+hipError_t launch_ortho_first_order(const double* G2, int64_t ldg, const int32_t* bprime,
+                                    int32_t nb_host, double* M2, int64_t ldm,
+                                    int32_t* need_exact, hipStream_t s);
+
+// C = alpha A B^T + beta C for small M, N and long K (split over waves).
+hipError_t launch_gemm_nt_small(int64_t M, int64_t N, int64_t K, double alpha,
+                                const double* A, int64_t lda, const double* B, int64_t ldb,
+                                double beta, double* C, int64_t ldc, const int32_t* m_dev,
+                                const int32_t* n_dev, hipStream_t s);
 
 // Qt_out[p,:] = (Vt[piv[p],:] - sum_{q<p} R[q][p] Qt_out[q,:]) / R[p][p]
 // for p < b' (row-oriented forward substitution with R^T).
