@@ -186,24 +186,6 @@ hipError_t launch_gemm_f64(int transA, int transB, int64_t M, int64_t N,
   return hipGetLastError();
 }
 
-// C = alpha A B + beta Cin with A FP64 (no transposes) and Cin of FP32 or
-// FP64 (its own leading dimension): the residual L - W L_1 of the W
-// refinement, read straight from the FP32 factor.
-hipError_t launch_gemm_f64_cin(int64_t M, int64_t N, int64_t K, double alpha,
-                               const double* A, int64_t lda, const double* B, int64_t ldb,
-                               double beta, const void* Cin, int cin_f32, int64_t ldcin,
-                               double* C, int64_t ldc, int b_lower_tri, hipStream_t s) {
-  if (M <= 0 || N <= 0) return hipSuccess;
-  dim3 g((unsigned)ceil_div(N, GB_N), (unsigned)ceil_div(M, GB_M));
-  if (cin_f32)
-    dispatch<double, float>(0, 0, g, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
-                            (const float*)Cin, ldcin, nullptr, nullptr, b_lower_tri);
-  else
-    dispatch<double, double>(0, 0, g, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
-                             (const double*)Cin, ldcin, nullptr, nullptr, b_lower_tri);
-  return hipGetLastError();
-}
-
 }  // namespace rbrp
 
 namespace rbrp {
@@ -270,6 +252,256 @@ hipError_t launch_gemm_nt_small(int64_t M, int64_t N, int64_t K, double alpha,
   hipLaunchKernelGGL(k_gemm_nt16, g, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta,
                      C, ldc, m_dev, n_dev);
   return hipGetLastError();
+}
+
+}  // namespace rbrp
+
+namespace rbrp {
+
+// C = alpha A B + beta Cin for tall A (M >> N, K): the three products of the
+// interpolation-matrix solve, W = L L_1^{-1} and its refinement
+// W += (L - W L_1) L_1^{-1} (Alg. 3).  A is M x K row-major (FP32 factor or
+// FP64), B is K x N FP64 and may be lower triangular (then column tile j
+// only reads K rows >= 64 j).
+//
+// 128 x 64 output tile per workgroup; four waves each own 64 x 32 of it as
+// 4 x 2 tiles of v_mfma_f64_16x16x4f64.  K goes through double-buffered LDS
+// TB_K at a time with a two-deep register pipeline: while the MFMAs of step
+// t run, step t+1 waits in registers and the loads of step t+2 are in
+// flight, so short K loops (k of a few hundred) still hide HBM latency.
+// The workgroup index is mapped so that all column tiles of one 128-row
+// strip run on the same XCD (blocks are dealt to the eight XCDs
+// round-robin), which keeps the strip's rows in that XCD's L2.
+//
+// Vector path (VA): A 16-byte aligned with lda >= round_up(K, TB_K), so every
+// step loads whole vectors inside the row; the K positions >= K are zeroed
+// when written to LDS.  Otherwise each element is loaded from a clamped
+// index.  Rows >= M of A and columns >= N of B only reach outputs that are
+// not stored, so they are loaded from clamped addresses and not masked.
+constexpr int TB_M = 128, TB_N = 64;
+constexpr int TA_LD = TB_M + 16, TBB_LD = TB_N + 16;  // row strides: 16 doubles = half the banks
+
+template <typename TA, int TB_K>
+struct TallStage {
+  static constexpr int NA = TB_M * TB_K / 256, NB = TB_N * TB_K / 256;
+  static constexpr int VW = 16 / sizeof(TA), NAV = NA / VW;
+  typedef TA av_t __attribute__((ext_vector_type(VW)));
+  av_t a[NAV];
+  double b[NB];
+};
+
+template <typename TA, bool VA, typename TC, int TB_K, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_gemm_tall(
+    int64_t M, int64_t N, int64_t K, double alpha, const TA* __restrict__ A, int64_t lda,
+    const double* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C,
+    int64_t ldc, const TC* __restrict__ Cin, int64_t ldcin, int64_t nrt, int64_t nct,
+    int xcd_map, int b_lower_tri) {
+  typedef TallStage<TA, TB_K> St;
+  constexpr int NA = St::NA, NB = St::NB, VW = St::VW, NAV = St::NAV;
+  typedef typename St::av_t av_t;
+  __shared__ double As[2][TB_K][TA_LD];
+  __shared__ double Bs[2][TB_K][TBB_LD];
+  int64_t r, c;
+  {
+    const uint32_t id = blockIdx.x, nc = (uint32_t)nct;
+    if (xcd_map) {
+      const uint32_t x = id & 7u, s = id >> 3;
+      r = (int64_t)(s / nc) * 8 + x;
+      c = s % nc;
+    } else {
+      r = id / nc;
+      c = id % nc;
+    }
+  }
+  if (r >= nrt) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wy = w >> 1, wx = w & 1;
+  // VA staging: A row ai, NA consecutive k from ak.  Element staging: K
+  // column ke of rows re + RS q.  B: k row bk, NB columns from bj.
+  constexpr int RS = 256 / TB_K;
+  const int ai = tid >> 1, ak = (tid & 1) * NA;
+  const int ke = tid % TB_K, re = tid / TB_K;
+  const int bk = tid / (TB_N / NB), bj = (tid % (TB_N / NB)) * NB;
+
+  {
+    const int64_t i0 = r * TB_M, j0 = c * TB_N;
+    d4v acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = (d4v){0.0, 0.0, 0.0, 0.0};
+    const int64_t ga = i0 + ai;
+    const TA* ap = A + (ga < M ? ga : M - 1) * lda;
+    const int64_t gbj = j0 + bj;
+
+    auto fetch = [&](St& st, int64_t k0) {
+      if constexpr (VA) {
+#pragma unroll
+        for (int v = 0; v < NAV; ++v)
+          st.a[v] = *reinterpret_cast<const av_t*>(ap + k0 + ak + v * VW);
+      } else {
+#pragma unroll
+        for (int v = 0; v < NAV; ++v)
+#pragma unroll
+          for (int e = 0; e < VW; ++e) {
+            const int64_t row = i0 + re + RS * (v * VW + e);
+            const int64_t kk = k0 + ke;
+            st.a[v][e] = A[(row < M ? row : M - 1) * lda + (kk < K ? kk : K - 1)];
+          }
+      }
+      const int64_t gk = (k0 + bk < K) ? k0 + bk : K - 1;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int64_t gj = (gbj + q < N) ? gbj + q : N - 1;
+        st.b[q] = B[gk * ldb + gj];
+      }
+    };
+    auto stash = [&](const St& st, int buf, int64_t k0) {
+#pragma unroll
+      for (int v = 0; v < NAV; ++v)
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+          const int q = v * VW + e;
+          const double xv = (double)st.a[v][e];
+          if constexpr (VA)
+            As[buf][ak + q][ai] = (k0 + ak + q < K) ? xv : 0.0;
+          else
+            As[buf][ke][re + RS * q] = (k0 + ke < K) ? xv : 0.0;
+        }
+      const bool krow = k0 + bk < K;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) Bs[buf][bk][bj + q] = krow ? st.b[q] : 0.0;
+    };
+    auto mma = [&](int buf) {
+#pragma unroll
+      for (int ks = 0; ks < TB_K / 4; ++ks) {
+        const int kr = 4 * ks + (lane >> 4);
+        double av[4], bv[2];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) av[a] = As[buf][kr][64 * wy + 16 * a + (lane & 15)];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bv[b] = Bs[buf][kr][32 * wx + 16 * b + (lane & 15)];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
+    };
+
+    // K steps kbeg + t TB_K, t < nt.  At the top of step t, LDS buffer t%2
+    // holds step t and register set (t+1)%2 holds step t+1.  Loads and
+    // stores run unconditionally (steps past the end re-load the last one
+    // into a buffer that is not read again), so the loop body has no
+    // branches and each wait covers exactly the older register set.
+    int64_t kbeg = 0;
+    if (b_lower_tri) kbeg = (j0 / TB_K) * TB_K;  // B[k][j] = 0 for k < j
+    const int64_t nt = (K > kbeg) ? ceil_div(K - kbeg, TB_K) : 0;
+    if (nt > 0) {
+      auto kstep = [&](int64_t t) { return kbeg + (t < nt ? t : nt - 1) * TB_K; };
+      St s0, s1;
+      fetch(s0, kbeg);
+      fetch(s1, kstep(1));
+      stash(s0, 0, kbeg);
+      __syncthreads();
+      int64_t t = 0;
+      for (; t + 2 <= nt; t += 2) {
+        // even step t: LDS 0, registers s1 = step t+1; s0 is free
+        fetch(s0, kstep(t + 2));
+        mma(0);
+        stash(s1, 1, kstep(t + 1));
+        __syncthreads();
+        // odd step t+1: LDS 1, registers s0 = step t+2; s1 is free
+        fetch(s1, kstep(t + 3));
+        mma(1);
+        stash(s0, 0, kstep(t + 2));
+        __syncthreads();
+      }
+      if (t < nt) mma(0);  // nt odd: the last step sits in LDS 0
+    }
+
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t gi = i0 + 64 * wy + 16 * a + (lane >> 4) + 4 * q;
+        if (gi >= M) continue;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int64_t gj = j0 + 32 * wx + 16 * b + (lane & 15);
+          if (gj < N) {
+            double v = alpha * acc[a][b][q];
+            if (beta != 0.0) {
+              if (Cin) v += beta * (double)Cin[gi * ldcin + gj];
+              else v += beta * C[gi * ldc + gj];
+            }
+            C[gi * ldc + gj] = v;
+          }
+        }
+      }
+  }
+}
+
+template <typename TA, typename TC, int BK = 8, int WPE = 3>
+static void dispatch_tall(int64_t M, int64_t N, int64_t K, double alpha, const TA* A,
+                          int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                          int64_t ldc, const TC* Cin, int64_t ldcin, int blt, hipStream_t s) {
+  const int64_t nrt = ceil_div(M, TB_M), nct = ceil_div(N, TB_N);
+  const int xcd = nrt >= 16;
+  const int64_t nblk = (xcd ? round_up(nrt, 8) : nrt) * nct;
+  const int vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) &&
+                  (lda % (int64_t)(16 / sizeof(TA)) == 0) && lda >= round_up(K, BK);
+  if (vec)
+    hipLaunchKernelGGL((k_gemm_tall<TA, true, TC, BK, WPE>), dim3((unsigned)nblk), dim3(256),
+                       0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, Cin, ldcin, nrt, nct,
+                       xcd, blt);
+  else
+    hipLaunchKernelGGL((k_gemm_tall<TA, false, TC, BK, WPE>), dim3((unsigned)nblk), dim3(256),
+                       0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, Cin, ldcin, nrt, nct,
+                       xcd, blt);
+}
+
+template <typename TA, typename TC>
+struct TallD {
+  static void run(int64_t M, int64_t N, int64_t K, double alpha, const TA* A, int64_t lda,
+                  const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                  const TC* Cin, int64_t ldcin, int blt, hipStream_t s) {
+    dispatch_tall<TA, TC>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, Cin, ldcin, blt, s);
+  }
+};
+
+template <template <typename, typename> class D>
+static hipError_t gemm_typed(int64_t M, int64_t N, int64_t K, double alpha, const void* A,
+                            int a_f32, int64_t lda, const double* B, int64_t ldb, double beta,
+                            const void* Cin, int cin_f32, int64_t ldcin, double* C,
+                            int64_t ldc, int b_lower_tri, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  if (a_f32) {
+    if (cin_f32)
+      D<float, float>::run(M, N, K, alpha, (const float*)A, lda, B, ldb, beta, C, ldc,
+                                  (const float*)Cin, ldcin, b_lower_tri, s);
+    else
+      D<float, double>::run(M, N, K, alpha, (const float*)A, lda, B, ldb, beta, C, ldc,
+                                   (const double*)Cin, ldcin, b_lower_tri, s);
+  } else {
+    if (cin_f32)
+      D<double, float>::run(M, N, K, alpha, (const double*)A, lda, B, ldb, beta, C, ldc,
+                                   (const float*)Cin, ldcin, b_lower_tri, s);
+    else
+      D<double, double>::run(M, N, K, alpha, (const double*)A, lda, B, ldb, beta, C,
+                                    ldc, (const double*)Cin, ldcin, b_lower_tri, s);
+  }
+  return hipGetLastError();
+}
+
+
+hipError_t launch_gemm_tall(int64_t M, int64_t N, int64_t K, double alpha, const void* A,
+                            int a_f32, int64_t lda, const double* B, int64_t ldb, double beta,
+                            const void* Cin, int cin_f32, int64_t ldcin, double* C,
+                            int64_t ldc, int b_lower_tri, hipStream_t s) {
+  return gemm_typed<TallD>(M, N, K, alpha, A, a_f32, lda, B, ldb, beta, Cin, cin_f32, ldcin, C,
+                           ldc, b_lower_tri, s);
 }
 
 }  // namespace rbrp

@@ -63,16 +63,6 @@ __global__ __launch_bounds__(kDiag) void k_diag_inv(const double* __restrict__ L
     if (j < nbk) Linv[(b0 + i) * k + b0 + j] = X[i][j];
 }
 
-template <typename TL>
-__global__ __launch_bounds__(256) void k_to_f64(const TL* __restrict__ L, int64_t ldl,
-                                                int64_t m, int64_t k,
-                                                double* __restrict__ E) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= m * k) return;
-  const int64_t i = e / k, p = e - i * k;
-  E[e] = (double)L[i * ldl + p];
-}
-
 __global__ __launch_bounds__(256) void k_identity_rows(const int64_t* __restrict__ S,
                                                        int64_t k, double* __restrict__ W,
                                                        int64_t ldw) {
@@ -86,9 +76,13 @@ __global__ void k_zero(double* __restrict__ x, int64_t n) {
   if (e < n) x[e] = 0.0;
 }
 
+// Leading dimension of the m x k FP64 intermediates: rows 16-byte aligned
+// and padded to whole K steps of the tall GEMM.
+static int64_t interp_ld(int64_t k) { return round_up(k, 16); }
+
 size_t interp_workspace_doubles(int64_t m, int64_t k) {
-  // L1, L1inv, T (kDiag x k), E (m x k)
-  return (size_t)(2 * k * k + kDiag * k + m * k);
+  // L1, L1inv, T (kDiag x k), W0 and E (m x interp_ld(k) each)
+  return (size_t)(2 * k * k + kDiag * k + 2 * m * interp_ld(k));
 }
 
 hipError_t launch_interp(const void* L, int l_f64, int64_t ldl, int64_t m, int64_t k,
@@ -98,7 +92,9 @@ hipError_t launch_interp(const void* L, int l_f64, int64_t ldl, int64_t m, int64
   double* L1 = ws;
   double* Linv = L1 + k * k;
   double* T = Linv + k * k;
-  double* E = T + kDiag * k;
+  const int64_t lde = interp_ld(k);
+  double* W0 = T + kDiag * k;
+  double* E = W0 + m * lde;
   hipError_t e;
   if (l_f64)
     hipLaunchKernelGGL(k_gather_l1<double>, dim3((unsigned)k), dim3(256), 0, s,
@@ -122,17 +118,20 @@ hipError_t launch_interp(const void* L, int l_f64, int64_t ldl, int64_t m, int64
                         Linv + i0 * k, k, nullptr, nullptr, 0, s);
     if (e != hipSuccess) return e;
   }
-  // W = L Linv
-  e = launch_gemm_f64(0, 0, m, k, k, 1.0, L, l_f64 ? 0 : 1, ldl, Linv, k, 0.0, W, ldw,
-                      nullptr, nullptr, 1, s);
+  // W = L Linv, refined as W += (L - W L1) Linv.  The iterate lives in W0
+  // (padded rows, so it can be the A operand of the next product) and only
+  // the last step writes the caller's W.
+  const int lf32 = l_f64 ? 0 : 1;
+  e = launch_gemm_tall(m, k, k, 1.0, L, lf32, ldl, Linv, k, 0.0, nullptr, 0, 0,
+                       refine > 0 ? W0 : W, refine > 0 ? lde : ldw, 1, s);
   if (e != hipSuccess) return e;
   for (int it = 0; it < refine; ++it) {
-    // E = L - W L1 ;  W += E Linv
-    e = launch_gemm_f64_cin(m, k, k, -1.0, W, ldw, L1, k, 1.0, L, l_f64 ? 0 : 1, ldl, E, k, 1,
-                            s);
+    // E = L - W0 L1 ;  W0 (or W, last step) = W0 + E Linv
+    e = launch_gemm_tall(m, k, k, -1.0, W0, 0, lde, L1, k, 1.0, L, lf32, ldl, E, lde, 1, s);
     if (e != hipSuccess) return e;
-    e = launch_gemm_f64(0, 0, m, k, k, 1.0, E, 0, k, Linv, k, 1.0, W, ldw, nullptr,
-                        nullptr, 1, s);
+    const bool last = it + 1 == refine;
+    e = launch_gemm_tall(m, k, k, 1.0, E, 0, lde, Linv, k, 1.0, W0, 0, lde, last ? W : W0,
+                         last ? ldw : lde, 1, s);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_identity_rows, dim3((unsigned)k), dim3(256), 0, s, S, k, W, ldw);

@@ -28,7 +28,7 @@ struct Carver {
 
 struct Plan {
   rbrp_dtype dt;
-  int64_t m, n, mr, ldr, k_max, ntiles, nparts;
+  int64_t m, n, mr, ldr, k_max, ldl, ntiles, nparts;
   int32_t b;
   int native_mode;   // deflation mode of the NATIVE precision
   bool bf16;
@@ -91,6 +91,7 @@ bool make_plan(rbrp_dtype dt, int64_t m, int64_t n, int32_t b, const rbrp_option
   if (p->ldr <= 0) return false;
   p->k_max = (o.k_max > 0) ? o.k_max : (m < n ? m : n);
   if (p->k_max > m || p->k_max > n) return false;
+  p->ldl = round_up(p->k_max, 16);  // rows of L 64-byte aligned, padded to whole GEMM K steps
   p->bf16 = o.precision == RBRP_PREC_BF16;
   p->r_f64 = dt == RBRP_F64;
   p->native_mode = p->r_f64 ? kModeF64 : kModeF32;
@@ -129,7 +130,7 @@ size_t layout(const Plan& p, char* base, Work* w) {
   w->Qt = cv.take<double>((size_t)p.k_max * p.ldr);
   w->fragB1 = cv.take<char>(frag_bytes(mode, p.ldr, p.b));
   w->fragA2 = cv.take<char>(frag_bytes(mode, p.ldr, p.b));
-  w->L = cv.take<char>((size_t)p.m * p.k_max * rs);
+  w->L = cv.take<char>((size_t)p.m * p.ldl * rs);
   w->interp = cv.take<double>(interp_workspace_doubles(p.m, p.k_max));
   return cv.off + kAlign;
 }
@@ -359,7 +360,7 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     prof.end();
     prof.begin(3);
     RBRP_HIP(launch_deflate(mode, w.R, p.mr, ldr, m, w.fragB1, w.fragA2, &w.sc->bprime, b,
-                            w.L, k_max, kS, w.sel_block, t, w.d, w.part_sum, w.part_max, s));
+                            w.L, p.ldl, kS, w.sel_block, t, w.d, w.part_sum, w.part_max, s));
     prof.end();
     RBRP_HIP(launch_reduce(w.part_sum, w.part_max, p.mr / def_rows, w.sc, 0, s));
     rs = fetch(h, w.sc, s);
@@ -377,7 +378,7 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
   st.resid_tracked = sqrt(fmax(sum_d, 0.0) / D0);
   if (W && kS > 0) {
     prof.begin(4);
-    RBRP_HIP(launch_interp(w.L, p.r_f64, k_max, m, kS, S, W, ldw, refine, w.interp, s));
+    RBRP_HIP(launch_interp(w.L, p.r_f64, p.ldl, m, kS, S, W, ldw, refine, w.interp, s));
     prof.end();
   }
   RBRP_HIP(hipStreamSynchronize(s));

@@ -101,11 +101,12 @@ hipError_t launch_gemm_f64(int transA, int transB, int64_t M, int64_t N,
                            int b_lower_tri, hipStream_t s);
 
 // C = alpha A B + beta Cin (A, B FP64 row-major; Cin FP32 or FP64, own ld).
-hipError_t launch_gemm_f64_cin(int64_t M, int64_t N, int64_t K, double alpha,
-                               const double* A, int64_t lda, const double* B, int64_t ldb,
-                               double beta, const void* Cin, int cin_f32, int64_t ldcin,
-                               double* C, int64_t ldc, int b_lower_tri, hipStream_t s);
-
+// C = alpha A B + beta Cin (Cin == nullptr: C itself) for tall A (m x K, FP32
+// or FP64, row-major) and FP64 B (K x N), B optionally lower triangular.
+hipError_t launch_gemm_tall(int64_t M, int64_t N, int64_t K, double alpha, const void* A,
+                            int a_f32, int64_t lda, const double* B, int64_t ldb, double beta,
+                            const void* Cin, int cin_f32, int64_t ldcin, double* C,
+                            int64_t ldc, int b_lower_tri, hipStream_t s);
 // Pivoted Cholesky of the nb x nb Gram matrix G (FP64) in one workgroup:
 // pivots, pivot rows of R with unpermuted columns (Rraw, row p = R_V(p,:)),
 // optionally the pivoted-order R (Rperm, nb x nb), b' by the truncation rule,
