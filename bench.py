@@ -12,10 +12,17 @@ Workload (default): the adversarial Gaussian-mixture matrix, 100000 x 1000
 FP32, eps = 1e-3, block size b = 64, FP32 ("plain") deflation.
 
 The JSON line carries:
-  roofline      the fused deflation kernel (the O(m n k) part) against the
-                FP32 MFMA peak: algorithmic flops 4 m n b' per launch over the
+  roofline      the fused deflation kernel (the O(m n k) part, R <- R - (R Q') Q'^T
+                with the row norms): its arithmetic intensity is b'/2 flop per
+                byte of FP32 residual traffic, so with the accepted block sizes
+                of this workload it is bound by HBM; achieved = algorithmic bytes
+                per launch (R read + written, the new L columns, d) over the
                 kernel's average duration, timed with HIP events that the
-                library records on its stream inside the timed region;
+                library records on its own stream inside the timed region.  The
+                same launches against the MFMA peak are in roofline["mfma"];
+  bf16_form     the same workload with the BF16 precision form (deflation
+                products on BF16 MFMA, FP32 accumulation), timed the same way:
+                the metric's "BF16-MFMA vs FP32 plain" comparison;
   cpu_baseline  the CPU FP64 oracle (literal Algorithm 2 + Algorithm 3) on the
                 same matrix, median of a few runs on the host's cores.
 """
@@ -39,11 +46,11 @@ PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "f64": 78.6}
 HBM_GBS = 8000.0
 
 WORKLOADS = {
-    "adversarial_gmm_fp32": dict(m=100000, n=1000, eps=1e-3, b=64, precision="native",
-                                 dtype="f32"),
-    "svd_geometric_fp64": dict(m=2000, n=500, eps=1e-2, b=16, precision="native",
-                               dtype="f64"),
+    "adversarial_gmm_fp32": dict(m=100000, n=1000, eps=1e-3, b=64, dtype="f32"),
+    "svd_geometric_fp64": dict(m=2000, n=500, eps=1e-2, b=16, dtype="f64"),
+    "svd_power_bf16": dict(m=200000, n=2048, eps=1e-4, b=128, dtype="f32"),
 }
+RIDGE = {d: PEAK_TFLOPS[d] * 1e12 / (HBM_GBS * 1e9) for d in PEAK_TFLOPS}
 
 
 def _kernel_sha():
@@ -73,8 +80,10 @@ def make_input(name):
     return config_matrix(name)
 
 
-def cpu_baseline(X, cfg, repeats):
-    """The oracle as it stands, on the host's cores (median of ``repeats``)."""
+def cpu_baseline(X, cfg, budget_s, max_repeats):
+    """The oracle as it stands, on the host's cores: whole decompositions of
+    the same matrix (seeds 0, 1, ...) until about ``budget_s`` seconds of work
+    (at most ``max_repeats``); the median run time gives rows/s."""
     import numpy as np
     from oracle import rbrp as oracle_rbrp, w_from_l
     try:
@@ -86,9 +95,9 @@ def cpu_baseline(X, cfg, repeats):
     X64 = np.asarray(X, dtype=np.float64)
     times = []
     k = None
-    for r in range(repeats):
+    while len(times) < max_repeats and sum(times) < budget_s:
         t0 = time.perf_counter()
-        res = oracle_rbrp(X64, cfg["eps"], cfg["b"], seed=r, form="A")
+        res = oracle_rbrp(X64, cfg["eps"], cfg["b"], seed=len(times), form="A")
         w_from_l(res.L, res.S)
         times.append(time.perf_counter() - t0)
         k = res.k
@@ -96,8 +105,9 @@ def cpu_baseline(X, cfg, repeats):
     m = X64.shape[0]
     return {"value": m / t, "unit": "rows/s", "cores": int(cores), "kind": "oracle",
             "sample": (f"full workload {X64.shape[0]}x{X64.shape[1]} (FP32 input promoted "
-                       f"to FP64), literal Algorithm 2 + Algorithm 3, median of {repeats} "
-                       f"runs (seeds 0..{repeats - 1}), {t:.3f} s per run, k={k}")}
+                       f"to FP64), literal Algorithm 2 + Algorithm 3, {len(times)} runs "
+                       f"(seeds 0..{len(times) - 1}, {sum(times):.1f} s of work), median "
+                       f"{t:.3f} s per run, k={k}")}
 
 
 def main():
@@ -106,8 +116,12 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="adversarial_gmm_fp32", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-repeats", type=int, default=5)
+    ap.add_argument("--cpu-budget", type=float, default=10.0, metavar="SECONDS",
+                    help="CPU oracle baseline: seconds of oracle work to time")
+    ap.add_argument("--cpu-repeats", type=int, default=31, help="at most this many oracle runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true",
+                    help="skip the BF16 precision-form leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device-to-device copy of MB megabytes (the "
                          "reference for HBM byte counters) and exit")
@@ -142,58 +156,76 @@ def main():
     X = make_input(args.workload)
     m, n = X.shape
     Xg = torch.from_numpy(X).to(dev)
-    ws = torch.empty(rb.workspace_size(m, n, cfg["b"], cfg["dtype"],
-                                       precision=cfg["precision"]),
-                     dtype=torch.uint8, device=dev)
+    need = max(rb.workspace_size(m, n, cfg["b"], cfg["dtype"], precision=p)
+               for p in (("native", "bf16") if cfg["dtype"] == "f32" else ("native",)))
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
     k_max = min(m, n)
     S_buf = torch.empty(k_max, dtype=torch.int64, device=dev)
     W_buf = torch.empty((m, k_max), dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
 
-    def step(seed, profile):
-        return rb.rbrp_id(Xg, cfg["eps"], cfg["b"], seed, workspace=ws, out_S=S_buf,
-                          out_W=W_buf, precision=cfg["precision"], profile=profile)
+    def run_form(precision, steps, warmup):
+        """Time `steps` decompositions in one precision form; returns the
+        per-step results, the wall time and the last step's FP64 error."""
+        def step(seed):
+            return rb.rbrp_id(Xg, cfg["eps"], cfg["b"], seed, workspace=ws, out_S=S_buf,
+                              out_W=W_buf, precision=precision, profile=True)
+        for i in range(warmup):
+            step(1000 + i)
+            print(f"[bench] {precision} warmup {i + 1}/{warmup} done", file=sys.stderr,
+                  flush=True)
+        torch.cuda.synchronize()
+        results = []
+        t0 = time.perf_counter()
+        for i in range(steps):
+            results.append(step(i))
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        print(f"[bench] {precision}: timed {steps} steps in {total:.3f} s", file=sys.stderr,
+              flush=True)
+        # untimed check that the result met eps: ||X - W X_S||_F <= eps ||X||_F
+        # in FP64 for the last step (its outputs are still in the buffers)
+        X64 = Xg.double()
+        last = results[-1]
+        E = X64 - last.W @ X64[last.S]
+        err = (torch.linalg.norm(E) / torch.linalg.norm(X64)).item()
+        del E, X64
+        return results, total, err
 
-    for i in range(args.warmup):
-        step(1000 + i, True)
-        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    results = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        results.append(step(i, True))
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-    print(f"[bench] timed {args.steps} steps in {total:.3f} s", file=sys.stderr, flush=True)
+    def deflation_roofline(results, dtype, s_r):
+        flops = sum(r.profile["deflate_flops"] for r in results)
+        ms_def = sum(r.profile["ms_deflate"] for r in results)
+        launches = sum(r.profile["deflate_launches"] for r in results)
+        sum_bp = flops / (4.0 * m * n)
+        nbytes = launches * (2.0 * m * n * s_r + 8.0 * m) + m * s_r * sum_bp
+        sec = ms_def * 1e-3
+        gbs = nbytes / sec / 1e9 if sec > 0 else 0.0
+        tfl = flops / sec / 1e12 if sec > 0 else 0.0
+        ai = flops / nbytes if nbytes > 0 else 0.0
+        mfma = {"achieved": round(tfl, 3), "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
+                "frac": round(tfl / PEAK_TFLOPS[dtype], 4)}
+        hbm = {"achieved": round(gbs, 1), "peak": HBM_GBS, "unit": "GB/s",
+               "frac": round(gbs / HBM_GBS, 4)}
+        bound = "hbm" if ai < RIDGE[dtype] else "mfma"
+        head = hbm if bound == "hbm" else mfma
+        return dict(bound=bound, **head, launches=launches,
+                    avg_launch_ms=round(ms_def / max(launches, 1), 4),
+                    bytes_per_launch=nbytes / max(launches, 1),
+                    flops_per_launch=flops / max(launches, 1),
+                    arithmetic_intensity=round(ai, 2), ridge=round(RIDGE[dtype], 2),
+                    mfma=mfma, hbm=hbm)
 
-    # untimed check that the result met eps: ||X - W X_S||_F <= eps ||X||_F in
-    # FP64 for the last step (its outputs are still in the buffers); every
-    # step's tracked residual must meet eps as well
-    X64 = Xg.double()
-    nx = torch.linalg.norm(X64).item()
-    last = results[-1]
-    E = X64 - last.W @ X64[last.S]
-    err_last = torch.linalg.norm(E).item() / nx
-    del E, X64
+    main_prec = "native"
+    results, total, err_last = run_form(main_prec, args.steps, args.warmup)
     errs = [err_last] + [r.resid_tracked for r in results]
     accurate = all(e <= cfg["eps"] * (1 + 1e-6) for e in errs)
-
     ms_per_step = 1e3 * total / args.steps
     value = m * args.steps / total
-    flops = sum(r.profile["deflate_flops"] for r in results)
-    ms_def = sum(r.profile["ms_deflate"] for r in results)
-    launches = sum(r.profile["deflate_launches"] for r in results)
-    dtype = cfg["dtype"] if cfg["precision"] == "native" else "bf16"
-    peak = PEAK_TFLOPS[dtype]
-    achieved = flops / (ms_def * 1e-3) / 1e12 if ms_def > 0 else 0.0
-    traffic = _traffic(args.workload)
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": traffic,
-                "kernel": "k_deflate (P = R Q', R -= P Q'^T, row norms)",
-                "launches": launches,
-                "avg_launch_ms": round(ms_def / max(launches, 1), 4),
-                "flops_per_launch": flops / max(launches, 1)}
+    dtype = cfg["dtype"]
+    s_r = 8 if dtype == "f64" else 4
+    roofline = deflation_roofline(results, dtype, s_r)
+    roofline["traffic"] = _traffic(args.workload)
+    roofline["kernel"] = "k_deflate (P = R Q', R -= P Q'^T, row norms)"
     phases = {key: round(statistics.mean(r.profile[key] for r in results), 4)
               for key in ("ms_init", "ms_select", "ms_filter", "ms_deflate", "ms_interp")}
     ks = [r.k for r in results]
@@ -204,7 +236,7 @@ def main():
         "dtype": dtype, "data": "synthetic",
         "config": {"workload": args.workload, "m": m, "n": n, "eps": cfg["eps"],
                    "b": cfg["b"], "tau_b": 1.0 / cfg["b"],
-                   "deflation": "fp32-mfma" if dtype == "f32" else dtype,
+                   "deflation": "fp64-mfma" if dtype == "f64" else "fp32-mfma (plain)",
                    "parallelism": "single-gpu"},
         "roofline": roofline,
         "eps_accurate": accurate, "rel_error_last_step": err_last,
@@ -213,9 +245,27 @@ def main():
         "blocks_median": statistics.median(r.blocks for r in results),
         "phases_ms_mean": phases,
     }
+    if dtype == "f32" and not args.no_bf16:
+        res16, tot16, err16 = run_form("bf16", args.steps, 1)
+        errs16 = [err16] + [r.resid_tracked for r in res16]
+        v16 = m * args.steps / tot16
+        rf16 = deflation_roofline(res16, "bf16", 4)
+        line["bf16_form"] = {
+            "value": v16, "unit": "rows/s", "ms_per_step": 1e3 * tot16 / args.steps,
+            "speedup_vs_fp32_plain": v16 / value,
+            "eps_accurate": all(e <= cfg["eps"] * (1 + 1e-6) for e in errs16),
+            "rel_error_last_step": err16,
+            "k_median": statistics.median(r.k for r in res16),
+            "blocks_split_median": statistics.median(r.blocks_split for r in res16),
+            "theta": 25 * cfg["eps"],
+            "deflation_roofline": rf16,
+            "phases_ms_mean": {key: round(statistics.mean(r.profile[key] for r in res16), 4)
+                               for key in ("ms_init", "ms_select", "ms_filter",
+                                           "ms_deflate", "ms_interp")},
+        }
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(X, cfg, args.cpu_repeats)
+        line["cpu_baseline"] = cpu_baseline(X, cfg, args.cpu_budget, args.cpu_repeats)
     print(json.dumps(line), flush=True)
 
 

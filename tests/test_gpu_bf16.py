@@ -1,0 +1,125 @@
+"""BF16 precision form of rbrp_id: the deflation products run on BF16 MFMA
+with FP32 accumulation, split into hi + lo parts (three products) while the
+relative residual rho = sqrt(sum d / sum d0) is above theta (default 25 eps)
+and as one product below it; the residual norms, the basis and W stay FP64.
+
+Stated bounds (measured on 20000 x 500/512 matrices; the tests allow margin):
+
+* the returned (S, W) meets eps, recomputed in FP64;
+* the true error exceeds the optimum on the GPU's own skeletons by at most
+  the BF16 floor, about 3e-5 ||X||_F for the split products (L carries the
+  hi + lo rounding, about 2^-16 relative) plus 4e-3 theta for the single
+  products;
+* the tracked residual agrees with the true error to that floor;
+* the first block equals the oracle's (its probabilities come from X);
+* the number of skeletons is close to the FP32 plain form's.
+
+One product from the first block on (theta huge) is not a supported setting:
+its error reaches 1e-3 relative and W degrades; it is run here only to show
+the switch is needed, with no accuracy claim.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import rbrp as oracle_rbrp, w_lstsq, relative_id_error
+from workloads import adversarial_gmm, svd_matrix, power_spectrum
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+BF16_SPLIT_FLOOR = 5e-5   # relative, split products (measured 2.7e-5)
+BF16_PLAIN_COEF = 4e-3    # times theta, single products after the switch
+
+
+@pytest.fixture(scope="module")
+def rb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2309_16002_amd as rb
+    rb.lib()
+    return rb
+
+
+def _run(rb, X, eps, b, seed, **kw):
+    print(f"rbrp_id m={X.shape[0]} n={X.shape[1]} eps={eps} b={b} seed={seed} {kw}", flush=True)
+    res = rb.rbrp_id(torch.from_numpy(np.ascontiguousarray(X)).to("cuda"), eps, b, seed, **kw)
+    torch.cuda.synchronize()
+    return res
+
+
+def _errors(X, res):
+    X64 = X.astype(np.float64)
+    S = res.S.cpu().tolist()
+    W = res.W.cpu().numpy()
+    assert np.array_equal(W[S], np.eye(res.k))
+    return relative_id_error(X64, W, S), relative_id_error(X64, w_lstsq(X64, S), S)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_bf16_adversarial_gmm(rb, seed):
+    eps, b = 1e-3, 64
+    X = adversarial_gmm(20000, 500, sub_dim=100, n_comp=20, seed=3)
+    res = _run(rb, X, eps, b, seed, precision="bf16")
+    ref32 = _run(rb, X, eps, b, seed)
+    oracle = oracle_rbrp(X.astype(np.float64), eps, b, seed)
+    bp0 = oracle.blocks[0][1]
+    assert res.bprime[0] == bp0
+    assert res.S.cpu().tolist()[:bp0] == oracle.S[:bp0]
+    assert res.blocks_split >= 1          # rho starts at 1 > theta
+    e_true, e_opt = _errors(X, res)
+    theta = 25 * eps
+    floor = BF16_SPLIT_FLOOR + BF16_PLAIN_COEF * theta
+    assert e_true <= eps
+    assert e_true <= e_opt + floor
+    assert abs(res.resid_tracked - e_true) <= floor
+    assert abs(res.k - ref32.k) <= max(b, 0.15 * ref32.k)
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-4])
+def test_bf16_power_spectrum(rb, eps):
+    b = 64
+    X = svd_matrix(20000, 512, power_spectrum(512, 1.5), seed=5).astype(np.float32)
+    res = _run(rb, X, eps, b, 1, precision="bf16")
+    e_true, e_opt = _errors(X, res)
+    floor = BF16_SPLIT_FLOOR + BF16_PLAIN_COEF * 25 * eps
+    assert e_true <= eps
+    assert e_true <= e_opt + floor
+    assert abs(res.resid_tracked - e_true) <= floor
+    ref32 = _run(rb, X, eps, b, 1)
+    assert abs(res.k - ref32.k) <= max(b, 0.15 * ref32.k)
+
+
+def test_bf16_split_everywhere(rb):
+    # theta -> 0: every block uses the three-product split form
+    eps, b = 1e-3, 64
+    X = adversarial_gmm(20000, 500, sub_dim=100, n_comp=20, seed=3)
+    res = _run(rb, X, eps, b, 1, precision="bf16", theta=1e-30)
+    assert res.blocks_split == res.blocks
+    e_true, e_opt = _errors(X, res)
+    assert e_true <= eps
+    assert e_true <= e_opt + BF16_SPLIT_FLOOR
+    assert abs(res.resid_tracked - e_true) <= BF16_SPLIT_FLOOR
+
+
+def test_bf16_plain_from_start_is_worse(rb):
+    # theta -> infinity: one BF16 product from the first block.  Its tracked
+    # residual carries ~1e-3 relative error, far above the split form's; this
+    # is why the controller starts with the split products.
+    eps, b = 1e-2, 64
+    X = svd_matrix(20000, 512, power_spectrum(512, 1.5), seed=5).astype(np.float32)
+    plain = _run(rb, X, eps, b, 1, precision="bf16", theta=1e30)
+    split = _run(rb, X, eps, b, 1, precision="bf16", theta=1e-30)
+    assert plain.blocks_split == 0 and split.blocks_split == split.blocks
+    ep, _ = _errors(X, plain)
+    es, _ = _errors(X, split)
+    assert abs(split.resid_tracked - es) < 0.1 * abs(plain.resid_tracked - ep)
+
+
+def test_bf16_deterministic(rb):
+    X = adversarial_gmm(8000, 300, sub_dim=60, n_comp=10, seed=4)
+    a = _run(rb, X, 1e-3, 32, 9, precision="bf16")
+    c = _run(rb, X, 1e-3, 32, 9, precision="bf16")
+    assert a.S.cpu().tolist() == c.S.cpu().tolist()
+    assert torch.equal(a.W, c.W)
