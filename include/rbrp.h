@@ -186,6 +186,78 @@ rbrp_status rbrp_block_cpqr(const double* Vt, int64_t n, int32_t nb,
                             int32_t* bprime_host, void* workspace,
                             size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many independent IDs (for instance the off-diagonal blocks of
+ * a hierarchical-matrix compression, the fast-direct-solver use the paper
+ * motivates in section 6) in one persistent launch.  Each ID runs the same
+ * Alg. 2 + Alg. 3 as rbrp_id with options tau_b, fixed_rank and w_refine
+ * (greedy selection and the BF16 form are not provided here); the Philox
+ * counter of ID i is (j, t, i, 0), i = its index in ``descs``.  The deflation
+ * products run in the input's precision on the vector ALUs; norms, basis and
+ * W are FP64.  No host synchronisation, no allocation and no memset: the call
+ * may be captured in a HIP graph and replayed.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  const void* X;     /* device, m x n row-major (ldx >= n), dtype of the call */
+  int64_t m, n, ldx;
+  int64_t* S;        /* device [k_cap]: skeleton rows in selection order       */
+  double* W;         /* device m x ldw FP64 row-major (ldw >= k_cap), or NULL:
+                        columns 0..k-1 written, W(S,:) = I                     */
+  int64_t ldw;
+  int32_t k_cap;     /* 1 <= k_cap <= min(m, n, shape.k_cap_max)                */
+  int32_t b;         /* block size 1..shape.b_max; 0 -> shape.b_max             */
+} rbrp_batch_desc;
+
+typedef struct {
+  int64_t m_max;      /* largest m, <= 16384                                   */
+  int64_t n_max;      /* largest n, <= 256                                     */
+  int32_t b_max;      /* largest b, <= 32                                      */
+  int32_t k_cap_max;  /* largest k_cap, <= 256                                 */
+  int32_t num_wg;     /* persistent workgroups; 0 -> 512 (two per CU)          */
+  int32_t reserved;
+} rbrp_batch_shape;
+
+/* Workspace bytes of rbrp_id_batched for this shape (per-workgroup scratch
+ * sized for the largest ID); 0 if the shape is out of range. */
+size_t rbrp_batch_workspace_size(rbrp_dtype dtype, const rbrp_batch_shape* shape);
+
+/*
+ * count IDs described by descs [count] (device).  order [count] (device, may
+ * be NULL): the queue order, a permutation of 0..count-1 (largest IDs first
+ * balances the tail; rbrp_batch_autotune computes one).  Outputs per ID i
+ * (device): k_out[i] = |S|, status_out[i] (RBRP_OK, RBRP_E_CAPACITY,
+ * RBRP_E_NONFINITE, RBRP_E_INVALID for a descriptor outside the shape,
+ * RBRP_E_HIP if a block lost orthogonality), resid_out[i] (may be NULL):
+ * tracked relative residual.  Host-side validation covers the scalar
+ * arguments and the shape only; descriptors are checked on the device.
+ */
+rbrp_status rbrp_id_batched(const rbrp_batch_desc* descs, const int32_t* order,
+                            int32_t count, rbrp_dtype dtype, double eps,
+                            uint64_t seed, const rbrp_options* opt,
+                            const rbrp_batch_shape* shape, int32_t* k_out,
+                            int32_t* status_out, double* resid_out,
+                            void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Autotuner of the batched form.  descs_host [count] is the host copy of the
+ * descriptors, descs [count] their device copy.  Size classes by n
+ * (<= 64, <= 128, > 128); for each class the block sizes 8, 16 and 32
+ * (<= shape->b_max) are timed on that class's IDs, then the number of
+ * persistent workgroups (256, 512, 768, those the workspace fits).  On
+ * return the device descriptors carry the chosen b, order [count] (device)
+ * holds the largest-first queue order, shape->num_wg the chosen count and
+ * b_class_host [3] the block size per class.  Synchronises the stream; runs
+ * the batch several times (outputs are overwritten).
+ */
+rbrp_status rbrp_batch_autotune(const rbrp_batch_desc* descs_host,
+                                rbrp_batch_desc* descs, int32_t count,
+                                rbrp_dtype dtype, double eps, uint64_t seed,
+                                const rbrp_options* opt, rbrp_batch_shape* shape,
+                                int32_t* order, int32_t* k_out,
+                                int32_t* status_out, double* resid_out,
+                                void* workspace, size_t ws_bytes, void* stream,
+                                int32_t* b_class_host);
+
 #ifdef __cplusplus
 }
 #endif

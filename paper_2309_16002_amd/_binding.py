@@ -57,6 +57,31 @@ class rbrp_stats(ctypes.Structure):
     ]
 
 
+class rbrp_batch_desc(ctypes.Structure):
+    _fields_ = [
+        ("X", ctypes.c_void_p),
+        ("m", ctypes.c_int64),
+        ("n", ctypes.c_int64),
+        ("ldx", ctypes.c_int64),
+        ("S", ctypes.c_void_p),
+        ("W", ctypes.c_void_p),
+        ("ldw", ctypes.c_int64),
+        ("k_cap", ctypes.c_int32),
+        ("b", ctypes.c_int32),
+    ]
+
+
+class rbrp_batch_shape(ctypes.Structure):
+    _fields_ = [
+        ("m_max", ctypes.c_int64),
+        ("n_max", ctypes.c_int64),
+        ("b_max", ctypes.c_int32),
+        ("k_cap_max", ctypes.c_int32),
+        ("num_wg", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
 class RBRPError(RuntimeError):
     def __init__(self, status, where):
         self.status = status
@@ -86,6 +111,14 @@ SIGNATURES = {
     "rbrp_block_cpqr_workspace_size": (_sz, [_i64, _i32]),
     "rbrp_block_cpqr": (_c.c_int, [_vp, _i64, _i32, _i64, _dbl, _vp, _vp, _vp, _i64,
                                    _c.POINTER(_i32), _vp, _sz, _vp]),
+    "rbrp_batch_workspace_size": (_sz, [_c.c_int, _c.POINTER(rbrp_batch_shape)]),
+    "rbrp_id_batched": (_c.c_int, [_vp, _vp, _i32, _c.c_int, _dbl, _u64,
+                                   _c.POINTER(rbrp_options), _c.POINTER(rbrp_batch_shape),
+                                   _vp, _vp, _vp, _vp, _sz, _vp]),
+    "rbrp_batch_autotune": (_c.c_int, [_c.POINTER(rbrp_batch_desc), _vp, _i32, _c.c_int,
+                                       _dbl, _u64, _c.POINTER(rbrp_options),
+                                       _c.POINTER(rbrp_batch_shape), _vp, _vp, _vp, _vp,
+                                       _vp, _sz, _vp, _c.POINTER(_i32)]),
 }
 
 
@@ -291,3 +324,114 @@ def block_cpqr(Vt, tau_b):
     if status != RBRP_OK:
         raise RBRPError(status, "rbrp_block_cpqr")
     return piv, R, Qt[: bp.value], int(bp.value)
+
+
+class BatchPlan:
+    """Device buffers of one batch of independent IDs (rbrp_id_batched).
+
+    Built once per set of input matrices; a launch only passes pointers, so
+    it can be captured in a graph.  Outputs are packed: ``S_all`` holds
+    k_cap_i entries per ID, ``W_all`` an m_i x k_cap_i block per ID."""
+
+    def __init__(self, Xs, b=16, k_caps=None, want_w=True, num_wg=0):
+        torch = _torch()
+        if not Xs:
+            raise ValueError("empty batch")
+        dev = Xs[0].device
+        dt = _dtype_code(Xs[0])
+        for X in Xs:
+            _check_matrix(X)
+            if _dtype_code(X) != dt or X.device != dev:
+                raise ValueError("all matrices of a batch share dtype and device")
+        self.Xs = list(Xs)
+        self.count = len(Xs)
+        self.dtype = dt
+        self.device = dev
+        ms = [int(X.shape[0]) for X in Xs]
+        ns = [int(X.shape[1]) for X in Xs]
+        ks = [min(m, n) for m, n in zip(ms, ns)] if k_caps is None else [int(k) for k in k_caps]
+        self.ms, self.ns, self.ks = ms, ns, ks
+        self.s_off = [0]
+        for k in ks:
+            self.s_off.append(self.s_off[-1] + k)
+        self.w_off = [0]
+        for m, k in zip(ms, ks):
+            self.w_off.append(self.w_off[-1] + m * k)
+        self.S_all = torch.empty(max(self.s_off[-1], 1), dtype=torch.int64, device=dev)
+        self.W_all = (torch.empty(max(self.w_off[-1], 1), dtype=torch.float64, device=dev)
+                      if want_w else None)
+        self.k_out = torch.zeros(self.count, dtype=torch.int32, device=dev)
+        self.status_out = torch.zeros(self.count, dtype=torch.int32, device=dev)
+        self.resid_out = torch.zeros(self.count, dtype=torch.float64, device=dev)
+        self.order = torch.arange(self.count, dtype=torch.int32, device=dev)
+        self.shape = rbrp_batch_shape()
+        self.shape.m_max = max(ms)
+        self.shape.n_max = max(ns)
+        self.shape.b_max = 32
+        self.shape.k_cap_max = max(ks)
+        self.shape.num_wg = int(num_wg)
+        self.descs_host = (rbrp_batch_desc * self.count)()
+        for i, X in enumerate(Xs):
+            d = self.descs_host[i]
+            d.X = X.data_ptr()
+            d.m, d.n, d.ldx = ms[i], ns[i], _ld(X)
+            d.S = self.S_all.data_ptr() + 8 * self.s_off[i]
+            d.W = (self.W_all.data_ptr() + 8 * self.w_off[i]) if want_w else None
+            d.ldw = ks[i]
+            d.k_cap = ks[i]
+            d.b = int(b)
+        raw = bytes(self.descs_host)
+        self.descs = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
+        self._alloc_workspace()
+
+    def _alloc_workspace(self, num_wg=None):
+        torch = _torch()
+        sh = rbrp_batch_shape.from_buffer_copy(self.shape)
+        if num_wg is not None:
+            sh.num_wg = num_wg
+        nbytes = int(lib().rbrp_batch_workspace_size(self.dtype, ctypes.byref(sh)))
+        if nbytes == 0:
+            raise RBRPError(RBRP_E_INVALID, "rbrp_batch_workspace_size")
+        if getattr(self, "workspace", None) is None or self.workspace.numel() < nbytes:
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+
+    def result(self, i):
+        """(S, k, W, status, tracked residual) of ID i (synchronises)."""
+        k = int(self.k_out[i].item())
+        S = self.S_all[self.s_off[i]:self.s_off[i] + k]
+        W = None
+        if self.W_all is not None:
+            W = self.W_all[self.w_off[i]:self.w_off[i + 1]].view(self.ms[i], self.ks[i])[:, :k]
+        return S, k, W, int(self.status_out[i].item()), float(self.resid_out[i].item())
+
+
+def rbrp_id_batched(plan, eps, seed=0, stream=None, **opts):
+    """Launch all IDs of ``plan`` (no synchronisation; outputs in the plan)."""
+    o = make_options(**opts)
+    st = stream if stream is not None else _stream_ptr(plan.device)
+    status = lib().rbrp_id_batched(_ptr(plan.descs), _ptr(plan.order), plan.count,
+                                   plan.dtype, float(eps), int(seed), ctypes.byref(o),
+                                   ctypes.byref(plan.shape), _ptr(plan.k_out),
+                                   _ptr(plan.status_out), _ptr(plan.resid_out),
+                                   _ptr(plan.workspace), plan.workspace.numel(), st)
+    if status != RBRP_OK:
+        raise RBRPError(status, "rbrp_id_batched")
+    return plan
+
+
+def batch_autotune(plan, eps, seed=0, **opts):
+    """Tune block size per size class and the persistent grid; returns the
+    chosen block size per class (n <= 64, <= 128, > 128)."""
+    o = make_options(**opts)
+    plan._alloc_workspace(num_wg=768)
+    bcls = (ctypes.c_int32 * 3)()
+    status = lib().rbrp_batch_autotune(plan.descs_host, _ptr(plan.descs), plan.count,
+                                       plan.dtype, float(eps), int(seed), ctypes.byref(o),
+                                       ctypes.byref(plan.shape), _ptr(plan.order),
+                                       _ptr(plan.k_out), _ptr(plan.status_out),
+                                       _ptr(plan.resid_out), _ptr(plan.workspace),
+                                       plan.workspace.numel(), _stream_ptr(plan.device),
+                                       bcls)
+    if status != RBRP_OK:
+        raise RBRPError(status, "rbrp_batch_autotune")
+    return [int(x) for x in bcls]

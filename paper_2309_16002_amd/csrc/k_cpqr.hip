@@ -20,7 +20,7 @@
 // substitution, one thread per column), and a second pass on the result
 // (projection against the basis + unpivoted Cholesky QR) restores
 // orthonormality to working precision.
-#include "rbrp_internal.h"
+#include "rbrp_wg.h"
 
 #include <math.h>
 
@@ -215,8 +215,6 @@ __global__ __launch_bounds__(128) void k_cpqr_gram(
 // pivot rows of R with unpermuted columns (Rraw), R11 in pivoted order
 // (Rp, nb x nb, zero outside the leading b' x b' upper triangle), ||V||_F^2
 // and the rank-guard flag.
-constexpr int kPivThreads = 256;
-
 __global__ __launch_bounds__(kPivThreads) void k_cpqr_piv(
     const double* __restrict__ G, int64_t ldg, int32_t nb_host,
     const int32_t* __restrict__ nb_dev, double tau_b,
@@ -225,123 +223,9 @@ __global__ __launch_bounds__(kPivThreads) void k_cpqr_piv(
     int32_t* __restrict__ bprime_out, double* __restrict__ tail1_out,
     int32_t* __restrict__ stop_out) {
   extern __shared__ double Ss[];
-  __shared__ double rrow[kMaxB];
-  __shared__ int32_t chosen_s[kMaxB];
-  __shared__ int32_t pivs[kMaxB];
-  __shared__ double wbest[2], wtail[2];
-  __shared__ int32_t wbi[2];
-  __shared__ int32_t s_done;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wv = tid >> 6;
-  int nb = nb_host;
-  if (nb_dev) nb = min(nb, *nb_dev);
-  const int ld = nb + 1;
-  for (int e = tid; e < nb * nb; e += kPivThreads) {
-    const int r = e / nb, c = e - r * nb;
-    Ss[r * ld + c] = G[(int64_t)r * ldg + c];
-  }
-  if (tid < kMaxB) chosen_s[tid] = (tid < nb) ? 0 : 1;
-  __syncthreads();
-  const bool owner = tid < nb;                 // owns diagonal entry tid
-  double dj = owner ? Ss[tid * ld + tid] : 0.0;
-  bool chosen = !owner;
-  double thr = 0.0;
-  int bp = 0;
-  // update assignment: column c = tid % nb (or none), rows r0, r0 + rstep, ...
-  const int nb2 = nb > 0 ? nb : 1;
-  const int ucol = tid % nb2;
-  const int urow0 = tid / nb2;
-  const int rstep = kPivThreads / nb2;
-  for (int p = 0; p <= nb; ++p) {
-    if (wv < 2) {
-      double best = chosen ? -INFINITY : dj;
-      int bi = chosen ? -1 : tid;
-      double tail = chosen ? 0.0 : fmax(dj, 0.0);
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        const double ob = __shfl_xor(best, off, kWave);
-        const int oi = __shfl_xor(bi, off, kWave);
-        tail += __shfl_xor(tail, off, kWave);
-        if (oi >= 0 && (bi < 0 || ob > best || (ob == best && oi < bi))) {
-          best = ob;
-          bi = oi;
-        }
-      }
-      if (lane == 0) {
-        wbest[wv] = best;
-        wbi[wv] = bi;
-        wtail[wv] = tail;
-      }
-    }
-    __syncthreads();
-    double best = wbest[0];
-    int bi = wbi[0];
-    double tail = wtail[0] + wtail[1];
-    if (wbi[1] >= 0 && (bi < 0 || wbest[1] > best || (wbest[1] == best && wbi[1] < bi))) {
-      best = wbest[1];
-      bi = wbi[1];
-    }
-    bool done = false;
-    if (p == 0) {
-      thr = tau_b * tail * (1.0 - 4.0 * nb * 1.1102230246251565e-16);
-      if (tid == 0 && tail1_out) *tail1_out = tail;
-      if (xs2_rows) {
-        double xs2 = 0.0;
-        for (int q = 0; q < nb; ++q) xs2 += xs2_rows[q];
-        if (!(tail > 1e-26 * xs2)) {
-          done = true;
-          if (stop_out && tid == 0) *stop_out = 1;
-        }
-      }
-    }
-    if (p == nb || bi < 0 || !(best > 0.0)) done = true;
-    if (p > 0 && tail < thr) done = true;
-    if (done) {
-      bp = p;
-      break;
-    }
-    const int jp = bi;
-    const double r = sqrt(best);
-    if (tid < nb) {
-      double v;
-      if (tid == jp) v = r;
-      else if (chosen) v = 0.0;
-      else v = Ss[jp * ld + tid] / r;
-      rrow[tid] = v;
-      Rraw[(int64_t)p * ldr + tid] = v;
-      if (tid == jp) {
-        chosen = true;
-        chosen_s[tid] = 1;
-        pivs[p] = jp;
-      }
-      dj -= v * v;
-    }
-    __syncthreads();
-    // rank-one update of the remaining Schur complement
-    if (urow0 < rstep && tid < rstep * nb) {
-      const double rc = rrow[ucol];
-      if (rc != 0.0) {
-#pragma unroll 8
-        for (int i = urow0; i < nb; i += rstep) Ss[i * ld + ucol] -= rrow[i] * rc;
-      }
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    int q = bp;
-    for (int c = 0; c < nb; ++c)
-      if (!chosen_s[c]) pivs[q++] = c;
-    *bprime_out = bp;
-  }
-  __syncthreads();
-  if (tid < nb) piv[tid] = pivs[tid];
-  // R11 in pivoted order, zero outside the leading b' x b' upper triangle
-  for (int e = tid; e < nb_host * nb_host; e += kPivThreads) {
-    const int a = e / nb_host, c = e - a * nb_host;
-    double v = 0.0;
-    if (a < bp && c >= a && c < nb) v = Rraw[(int64_t)a * ldr + pivs[c]];
-    Rp[(int64_t)a * ldp + c] = v;
-  }
+  __shared__ PivShared sh;
+  wg_piv_chol(G, ldg, nb_host, nb_dev, tau_b, xs2_rows, piv, Rraw, ldr, Rp, ldp, bprime_out,
+              tail1_out, stop_out, Ss, sh);
 }
 
 // Rows of Qtmp: Qtmp[p,:] = (Vt[piv[p],:] - sum_{q<p} R11[q][p] Qtmp[q,:]) /

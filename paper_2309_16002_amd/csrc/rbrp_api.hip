@@ -3,6 +3,9 @@
 // Algorithm 3 for W.
 #include "rbrp_internal.h"
 
+#include <algorithm>
+#include <vector>
+
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -516,6 +519,147 @@ rbrp_status rbrp_block_cpqr(const double* Vt, int64_t n, int32_t nb, int64_t ldv
   if (rs != RBRP_OK) return rs;
   *bprime_host = h->bprime;
   return RBRP_OK;
+}
+
+
+size_t rbrp_batch_workspace_size(rbrp_dtype dtype, const rbrp_batch_shape* shape) {
+  if ((dtype != RBRP_F32 && dtype != RBRP_F64) || !rbrp::batch_shape_ok(shape)) return 0;
+  return rbrp::batch_workspace_size(dtype, shape);
+}
+
+static rbrp_status batch_check(int32_t count, rbrp_dtype dtype, double eps,
+                               const rbrp_options* opt, const rbrp_batch_shape* shape,
+                               const void* descs, const int32_t* k_out,
+                               const int32_t* status_out, const void* workspace,
+                               size_t ws_bytes, rbrp_options* o) {
+  if (count < 0 || !descs || !k_out || !status_out || !workspace) return RBRP_E_INVALID;
+  if (dtype != RBRP_F32 && dtype != RBRP_F64) return RBRP_E_INVALID;
+  if (!(eps >= 0.0) || !(eps < 1.0)) return RBRP_E_INVALID;
+  if (!rbrp::batch_shape_ok(shape)) return RBRP_E_INVALID;
+  rbrp_default_options(o);
+  if (opt) *o = *opt;
+  if (o->greedy || o->precision != RBRP_PREC_NATIVE) return RBRP_E_UNSUPPORTED;
+  if (ws_bytes < rbrp::batch_workspace_size(dtype, shape)) return RBRP_E_WORKSPACE;
+  if (rbrp::batch_lds_needed(dtype, shape) > 128 * 1024) return RBRP_E_UNSUPPORTED;
+  return RBRP_OK;
+}
+
+rbrp_status rbrp_id_batched(const rbrp_batch_desc* descs, const int32_t* order,
+                            int32_t count, rbrp_dtype dtype, double eps, uint64_t seed,
+                            const rbrp_options* opt, const rbrp_batch_shape* shape,
+                            int32_t* k_out, int32_t* status_out, double* resid_out,
+                            void* workspace, size_t ws_bytes, void* stream) {
+  rbrp_options o;
+  const rbrp_status v = batch_check(count, dtype, eps, opt, shape, descs, k_out, status_out,
+                                    workspace, ws_bytes, &o);
+  if (v != RBRP_OK) return v;
+  if (count == 0) return RBRP_OK;
+  RBRP_HIP(rbrp::launch_batched(descs, order, count, dtype, eps, seed, o, *shape, k_out,
+                                status_out, resid_out, workspace, (hipStream_t)stream));
+  return RBRP_OK;
+}
+
+rbrp_status rbrp_batch_autotune(const rbrp_batch_desc* descs_host, rbrp_batch_desc* descs,
+                                int32_t count, rbrp_dtype dtype, double eps, uint64_t seed,
+                                const rbrp_options* opt, rbrp_batch_shape* shape,
+                                int32_t* order, int32_t* k_out, int32_t* status_out,
+                                double* resid_out, void* workspace, size_t ws_bytes,
+                                void* stream, int32_t* b_class_host) {
+  rbrp_options o;
+  const rbrp_status v = batch_check(count, dtype, eps, opt, shape, descs, k_out, status_out,
+                                    workspace, ws_bytes, &o);
+  if (v != RBRP_OK) return v;
+  if (!descs_host || !order || !b_class_host) return RBRP_E_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  constexpr int kClasses = 3;
+  auto cls = [](int64_t n) { return n <= 64 ? 0 : (n <= 128 ? 1 : 2); };
+  // largest-first queue order by the work estimate m n min(m, n)
+  std::vector<int32_t> ord(count);
+  for (int32_t i = 0; i < count; ++i) ord[i] = i;
+  auto work = [&](int32_t i) {
+    const rbrp_batch_desc& d = descs_host[i];
+    return (double)d.m * (double)d.n * (double)(d.m < d.n ? d.m : d.n);
+  };
+  std::stable_sort(ord.begin(), ord.end(),
+                   [&](int32_t a, int32_t b) { return work(a) > work(b); });
+  std::vector<rbrp_batch_desc> cur(descs_host, descs_host + count);
+  hipEvent_t e0, e1;
+  RBRP_HIP(hipEventCreate(&e0));
+  RBRP_HIP(hipEventCreate(&e1));
+  rbrp_status st = RBRP_OK;
+  auto timed = [&](const std::vector<int32_t>& ord_c, const rbrp_batch_shape& sh,
+                   float* ms) -> rbrp_status {
+    RBRP_HIP(hipMemcpyAsync(descs, cur.data(), sizeof(rbrp_batch_desc) * count,
+                            hipMemcpyHostToDevice, s));
+    RBRP_HIP(hipMemcpyAsync(order, ord_c.data(), sizeof(int32_t) * ord_c.size(),
+                            hipMemcpyHostToDevice, s));
+    float best = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      RBRP_HIP(hipEventRecord(e0, s));
+      RBRP_HIP(rbrp::launch_batched(descs, order, (int32_t)ord_c.size(), dtype, eps, seed, o,
+                                    sh, k_out, status_out, resid_out, workspace, s));
+      RBRP_HIP(hipEventRecord(e1, s));
+      RBRP_HIP(hipEventSynchronize(e1));
+      float t = 0.f;
+      RBRP_HIP(hipEventElapsedTime(&t, e0, e1));
+      if (t < best) best = t;
+    }
+    *ms = best;
+    return RBRP_OK;
+  };
+  const int32_t cand_b[3] = {8, 16, 32};
+  for (int c = 0; c < kClasses && st == RBRP_OK; ++c) {
+    std::vector<int32_t> members;
+    for (int32_t i : ord)
+      if (cls(descs_host[i].n) == c) members.push_back(i);
+    b_class_host[c] = 0;
+    if (members.empty()) continue;
+    float best_ms = 1e30f;
+    int32_t best_b = 0;
+    for (int32_t bc : cand_b) {
+      if (bc > shape->b_max) continue;
+      for (int32_t i : members) cur[i].b = bc;
+      float ms = 0.f;
+      st = timed(members, *shape, &ms);
+      if (st != RBRP_OK) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_b = bc;
+      }
+    }
+    for (int32_t i : members) cur[i].b = best_b;
+    b_class_host[c] = best_b;
+  }
+  if (st == RBRP_OK) {
+    const int32_t cand_wg[3] = {256, 512, 768};
+    float best_ms = 1e30f;
+    int32_t best_wg = shape->num_wg;
+    for (int32_t nwg : cand_wg) {
+      rbrp_batch_shape sh = *shape;
+      sh.num_wg = nwg;
+      if (rbrp::batch_workspace_size(dtype, &sh) > ws_bytes) continue;
+      float ms = 0.f;
+      st = timed(ord, sh, &ms);
+      if (st != RBRP_OK) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_wg = nwg;
+      }
+    }
+    shape->num_wg = best_wg;
+  }
+  if (st == RBRP_OK) {
+    hipError_t e = hipMemcpyAsync(descs, cur.data(), sizeof(rbrp_batch_desc) * count,
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(order, ord.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice,
+                         s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = RBRP_E_HIP;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
 }
 
 }  // extern "C"

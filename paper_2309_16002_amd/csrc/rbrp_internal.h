@@ -191,4 +191,13 @@ size_t interp_workspace_doubles(int64_t m, int64_t k);
 // Deflation arithmetic modes.
 enum DeflateMode { kModeF64 = 0, kModeF32 = 1, kModeBF16x3 = 2, kModeBF16 = 3 };
 
+// ---- batched form (k_batched.hip) ----
+bool batch_shape_ok(const rbrp_batch_shape* sh);
+size_t batch_workspace_size(rbrp_dtype dt, const rbrp_batch_shape* sh);
+size_t batch_lds_needed(rbrp_dtype dt, const rbrp_batch_shape* sh);
+hipError_t launch_batched(const rbrp_batch_desc* descs, const int32_t* order, int32_t count,
+                          rbrp_dtype dt, double eps, uint64_t seed, const rbrp_options& o,
+                          const rbrp_batch_shape& sh, int32_t* k_out, int32_t* status_out,
+                          double* resid_out, void* workspace, hipStream_t s);
+
 }  // namespace rbrp

@@ -1,0 +1,473 @@
+// Workgroup-level building blocks shared by the per-step kernels and the
+// batched kernel: the exact integer block sampler of Alg. 2 (weights,
+// Philox4x64-10 draws, successive sampling) and the pivoted Cholesky of the
+// block filter.  Every function here is called by all threads of one
+// workgroup and ends past a barrier.
+#pragma once
+
+#include "rbrp_internal.h"
+
+#include <math.h>
+
+namespace rbrp {
+
+constexpr int kSampleThreads = 256;
+
+__device__ __forceinline__ int ceil_log2_dev(int64_t m) {
+  if (m <= 1) return 0;
+  return 64 - __clzll((unsigned long long)(m - 1));
+}
+
+__device__ __forceinline__ int weight_shift(double dmax, int64_t m) {
+  int e = 0;
+  frexp(dmax, &e);
+  return 62 - e - ceil_log2_dev(m);
+}
+
+__device__ __forceinline__ uint64_t weight_of(double di, int s) {
+  if (!(di > 0.0)) return 0;
+  return (uint64_t)floor(ldexp(di, s));
+}
+
+// ---- Philox4x64-10 ----
+__device__ __forceinline__ uint64_t philox_word0(uint64_t j, uint64_t t,
+                                                 uint64_t id, uint64_t seed) {
+  uint64_t c0 = j, c1 = t, c2 = id, c3 = 0;
+  uint64_t k0 = seed, k1 = 0;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B97F4A7C15ull;
+      k1 += 0xBB67AE8584CAA73Bull;
+    }
+    const uint64_t lo0 = 0xD2E7470EE14C6C93ull * c0;
+    const uint64_t hi0 = __umul64hi(0xD2E7470EE14C6C93ull, c0);
+    const uint64_t lo1 = 0xCA5A826395121157ull * c2;
+    const uint64_t hi1 = __umul64hi(0xCA5A826395121157ull, c2);
+    const uint64_t n0 = hi1 ^ c1 ^ k0;
+    const uint64_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  return c0;
+}
+
+// Global inclusive prefix at row i.
+__device__ __forceinline__ uint64_t cdf_at(const uint64_t* cdf_local,
+                                           const uint64_t* tile_excl, int64_t i) {
+  return tile_excl[i / kScanTile] + cdf_local[i];
+}
+
+// Weight of row i recovered from the local prefix.
+__device__ __forceinline__ uint64_t weight_at(const uint64_t* cdf_local, int64_t i) {
+  const uint64_t prev = (i % kScanTile) ? cdf_local[i - 1] : 0;
+  return cdf_local[i] - prev;
+}
+
+// Weights of one tile of kScanTile rows (256 threads x 8 rows) and their
+// inclusive prefix within the tile; tile totals (weight and number of
+// positive weights) to tile_sum / tile_pos.  wsum / wpos: 4 entries in LDS.
+// Ends with every thread past a barrier.
+__device__ __forceinline__ void wg_weights_scan_tile(
+    const double* __restrict__ d, const int32_t* __restrict__ sel_block,
+    const uint8_t* __restrict__ excluded, int64_t m, double dmax, int64_t tile,
+    uint64_t* __restrict__ cdf_local, uint64_t* __restrict__ tile_sum,
+    int32_t* __restrict__ tile_pos, uint64_t* wsum, int32_t* wpos) {
+  const int s = dmax > 0.0 ? weight_shift(dmax, m) : 0;
+  const int64_t base = tile * kScanTile + threadIdx.x * 8;
+  uint64_t w[8];
+  int pos = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int64_t i = base + q;
+    uint64_t v = 0;
+    if (i < m && dmax > 0.0) {
+      const bool out = (sel_block && sel_block[i] >= 0) || (excluded && excluded[i]);
+      if (!out) v = weight_of(d[i], s);
+    }
+    w[q] = v;
+    pos += v != 0;
+  }
+#pragma unroll
+  for (int q = 1; q < 8; ++q) w[q] += w[q - 1];
+  // exclusive scan of thread totals across the wave
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint64_t incl = w[7];
+  int ipos = pos;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint64_t o = __shfl_up(incl, off, kWave);
+    const int op = __shfl_up(ipos, off, kWave);
+    if (lane >= off) {
+      incl += o;
+      ipos += op;
+    }
+  }
+  if (lane == 63) {
+    wsum[wv] = incl;
+    wpos[wv] = ipos;
+  }
+  __syncthreads();
+  uint64_t wave_off = 0;
+  for (int i = 0; i < wv; ++i) wave_off += wsum[i];
+  const uint64_t excl = incl - w[7] + wave_off;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int64_t i = base + q;
+    if (i < m) cdf_local[i] = w[q] + excl;
+  }
+  if (threadIdx.x == 0) {
+    tile_sum[tile] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    tile_pos[tile] = wpos[0] + wpos[1] + wpos[2] + wpos[3];
+  }
+  __syncthreads();
+}
+
+// LDS state of the block sampler (one workgroup of kSampleThreads threads).
+template <int MAXTILES>
+struct SampleShared {
+  uint64_t tile_excl[MAXTILES + 1];
+  int64_t acc_idx[kMaxB];
+  uint64_t acc_w[kMaxB];
+  int64_t cand[kSampleThreads];
+  int32_t flag[kSampleThreads];
+  uint64_t red[kSampleThreads];
+  int32_t nacc, npos, total_new;
+  uint64_t W;
+};
+
+// b rows drawn without replacement from the tiled integer CDF (weights and
+// per-tile prefixes from wg_weights_scan_tile), candidates counted from 0
+// with Philox counter (j, t, ident, 0) and key (seed, 0).  Writes idx[0..nt)
+// and *nt_out (and *npos_out, the number of positive weights).  Called by all
+// kSampleThreads threads of the workgroup; ends past a barrier.
+template <int MAXTILES>
+__device__ __forceinline__ void wg_sample(
+    const uint64_t* __restrict__ cdf_local, const uint64_t* __restrict__ tile_sum,
+    const int32_t* __restrict__ tile_pos, int64_t m, int32_t b, uint64_t seed,
+    uint64_t t, uint64_t ident, int64_t* __restrict__ idx, int32_t* nt_out,
+    int32_t* npos_out, SampleShared<MAXTILES>& sh) {
+  int32_t& s_nacc = sh.nacc;
+  int32_t& s_npos = sh.npos;
+  int32_t& s_total_new = sh.total_new;
+  uint64_t& s_W = sh.W;
+  uint64_t* tile_excl = sh.tile_excl;
+  int64_t* acc_idx = sh.acc_idx;
+  uint64_t* acc_w = sh.acc_w;
+  int64_t* cand = sh.cand;
+  int32_t* flag = sh.flag;
+  uint64_t* red = sh.red;
+  const int tid = threadIdx.x;
+  const int64_t ntiles = ceil_div(m, kScanTile);
+
+  // exclusive prefix of tile totals (serial: ntiles is small)
+  if (tid == 0) {
+    uint64_t run = 0;
+    int npos = 0;
+    for (int64_t T = 0; T < ntiles; ++T) {
+      tile_excl[T] = run;
+      run += tile_sum[T];
+      npos += tile_pos[T];
+    }
+    tile_excl[ntiles] = run;
+    s_W = run;
+    s_npos = npos;
+    s_nacc = 0;
+  }
+  __syncthreads();
+  const uint64_t W = s_W;
+  const int npos = s_npos;
+
+  if (npos <= b) {
+    // every row with positive weight, in index order
+    int nacc = 0;
+    for (int64_t T = 0; T < ntiles; ++T) {
+      if (tile_pos[T] == 0) continue;
+      const int64_t r0 = T * kScanTile;
+      for (int64_t c0 = r0; c0 < r0 + kScanTile && c0 < m; c0 += kSampleThreads) {
+        const int64_t i = c0 + tid;
+        const int pos = (i < m && i < r0 + kScanTile) ? (weight_at(cdf_local, i) != 0) : 0;
+        flag[tid] = pos;
+        __syncthreads();
+        if (tid == 0) {
+          int run = nacc;
+          for (int q = 0; q < kSampleThreads; ++q) {
+            const int f = flag[q];
+            flag[q] = run;
+            run += f;
+          }
+          s_total_new = run;
+        }
+        __syncthreads();
+        if (pos) idx[flag[tid]] = i;
+        nacc = s_total_new;
+        __syncthreads();
+      }
+    }
+    if (tid == 0) {
+      *nt_out = nacc;
+      if (npos_out) *npos_out = npos;
+    }
+    __syncthreads();
+    return;
+  }
+
+  // rejection form: chunks of candidates resolved in parallel
+  const int64_t jmax = (int64_t)kRejectionFactor * b;
+  for (int64_t j0 = 0; j0 < jmax; j0 += kSampleThreads) {
+    const int nacc = s_nacc;
+    if (nacc >= b) break;
+    const int64_t j = j0 + tid;
+    int64_t my = -1;
+    if (j < jmax) {
+      const uint64_t x = philox_word0((uint64_t)j, t, ident, seed);
+      const uint64_t target = __umul64hi(x, W);
+      // tile: smallest T with tile_excl[T+1] > target
+      int64_t lo = 0, hi = ntiles - 1;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (tile_excl[mid + 1] > target) hi = mid; else lo = mid + 1;
+      }
+      const uint64_t local = target - tile_excl[lo];
+      int64_t a = lo * kScanTile, z = min(m, (lo + 1) * (int64_t)kScanTile) - 1;
+      while (a < z) {
+        const int64_t mid = (a + z) >> 1;
+        if (cdf_local[mid] > local) z = mid; else a = mid + 1;
+      }
+      my = a;
+    }
+    cand[tid] = my;
+    __syncthreads();
+    int isnew = 0;
+    if (my >= 0) {
+      isnew = 1;
+      for (int q = 0; q < nacc && isnew; ++q) isnew = acc_idx[q] != my;
+      for (int q = 0; q < tid && isnew; ++q) isnew = cand[q] != my;
+    }
+    flag[tid] = isnew;
+    __syncthreads();
+    if (tid == 0) {
+      int run = 0;
+      for (int q = 0; q < kSampleThreads; ++q) {
+        const int f = flag[q];
+        flag[q] = run;
+        run += f;
+      }
+      s_total_new = run;
+    }
+    __syncthreads();
+    if (isnew) {
+      const int p = nacc + flag[tid];
+      if (p < b) {
+        acc_idx[p] = my;
+        acc_w[p] = weight_at(cdf_local, my);
+      }
+    }
+    __syncthreads();
+    if (tid == 0) s_nacc = min(b, nacc + s_total_new);
+    __syncthreads();
+  }
+
+  // removal form: weights of accepted rows removed, one draw per candidate
+  for (int64_t j = jmax; s_nacc < b; ++j) {
+    const int nacc = s_nacc;
+    // W' = W - sum of accepted weights
+    uint64_t part = 0;
+    for (int q = tid; q < nacc; q += kSampleThreads) part += acc_w[q];
+    red[tid] = part;
+    __syncthreads();
+    if (tid == 0) {
+      uint64_t tot = 0;
+      for (int q = 0; q < kSampleThreads; ++q) tot += red[q];
+      red[0] = tot;
+    }
+    __syncthreads();
+    const uint64_t Wp = W - red[0];
+    __syncthreads();
+    const uint64_t x = philox_word0((uint64_t)j, t, ident, seed);
+    const uint64_t target = __umul64hi(x, Wp);
+    int64_t lo = 0, hi = m - 1;
+    while (lo < hi) {  // uniform across the workgroup
+      const int64_t mid = (lo + hi) >> 1;
+      uint64_t adj = 0;
+      for (int q = tid; q < nacc; q += kSampleThreads)
+        if (acc_idx[q] <= mid) adj += acc_w[q];
+      red[tid] = adj;
+      __syncthreads();
+      if (tid == 0) {
+        uint64_t tot = 0;
+        for (int q = 0; q < kSampleThreads; ++q) tot += red[q];
+        red[0] = cdf_at(cdf_local, tile_excl, mid) - tot;
+      }
+      __syncthreads();
+      const bool above = red[0] > target;
+      __syncthreads();
+      if (above) hi = mid; else lo = mid + 1;
+    }
+    if (tid == 0) {
+      acc_idx[nacc] = lo;
+      acc_w[nacc] = weight_at(cdf_local, lo);
+      s_nacc = nacc + 1;
+    }
+    __syncthreads();
+  }
+  const int nt = s_nacc;
+  for (int q = tid; q < nt; q += kSampleThreads) idx[q] = acc_idx[q];
+  if (tid == 0) {
+    *nt_out = nt;
+    if (npos_out) *npos_out = npos;
+  }
+  __syncthreads();
+}
+
+// LDS state of the pivoted Cholesky (besides the nb x (nb+1) Schur buffer).
+struct PivShared {
+  double rrow[kMaxB];
+  int32_t chosen[kMaxB];
+  int32_t pivs[kMaxB];
+  double wbest[2], wtail[2];
+  int32_t wbi[2];
+};
+
+constexpr int kPivThreads = 256;
+
+// Pivoted Cholesky of the block's Gram matrix for the filter (kPivThreads
+// threads).  The Schur complement S (nb x nb, row stride nb + 1) lives in
+// LDS (Ss); thread j < nb keeps the diagonal entry S[j][j] in a register.
+// Per pivot step: a fixed-order argmax / sum over the diagonal (waves 0-1),
+// the pivot row of R written to LDS, and the rank-one update of S spread
+// over all threads (each thread updates nb*nb/256 independent entries, so
+// LDS latency overlaps).  Outputs: pivots (kept ones first, the rest in
+// increasing order), b', the pivot rows of R with unpermuted columns (Rraw),
+// R11 in pivoted order (Rp, nb x nb, zero outside the leading b' x b' upper
+// triangle), ||V||_F^2 and the rank-guard flag.  Ends past a barrier.
+__device__ __forceinline__ void wg_piv_chol(
+    const double* __restrict__ G, int64_t ldg, int32_t nb_host,
+    const int32_t* __restrict__ nb_dev, double tau_b,
+    const double* __restrict__ xs2_rows, int32_t* __restrict__ piv,
+    double* __restrict__ Rraw, int64_t ldr, double* __restrict__ Rp, int64_t ldp,
+    int32_t* __restrict__ bprime_out, double* __restrict__ tail1_out,
+    int32_t* __restrict__ stop_out, double* Ss, PivShared& sh) {
+  double* rrow = sh.rrow;
+  int32_t* chosen_s = sh.chosen;
+  int32_t* pivs = sh.pivs;
+  double* wbest = sh.wbest;
+  double* wtail = sh.wtail;
+  int32_t* wbi = sh.wbi;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  int nb = nb_host;
+  if (nb_dev) nb = min(nb, *nb_dev);
+  const int ld = nb + 1;
+  for (int e = tid; e < nb * nb; e += kPivThreads) {
+    const int r = e / nb, c = e - r * nb;
+    Ss[r * ld + c] = G[(int64_t)r * ldg + c];
+  }
+  if (tid < kMaxB) chosen_s[tid] = (tid < nb) ? 0 : 1;
+  __syncthreads();
+  const bool owner = tid < nb;                 // owns diagonal entry tid
+  double dj = owner ? Ss[tid * ld + tid] : 0.0;
+  bool chosen = !owner;
+  double thr = 0.0;
+  int bp = 0;
+  // update assignment: column c = tid % nb (or none), rows r0, r0 + rstep, ...
+  const int nb2 = nb > 0 ? nb : 1;
+  const int ucol = tid % nb2;
+  const int urow0 = tid / nb2;
+  const int rstep = kPivThreads / nb2;
+  for (int p = 0; p <= nb; ++p) {
+    if (wv < 2) {
+      double best = chosen ? -INFINITY : dj;
+      int bi = chosen ? -1 : tid;
+      double tail = chosen ? 0.0 : fmax(dj, 0.0);
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double ob = __shfl_xor(best, off, kWave);
+        const int oi = __shfl_xor(bi, off, kWave);
+        tail += __shfl_xor(tail, off, kWave);
+        if (oi >= 0 && (bi < 0 || ob > best || (ob == best && oi < bi))) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        wbest[wv] = best;
+        wbi[wv] = bi;
+        wtail[wv] = tail;
+      }
+    }
+    __syncthreads();
+    double best = wbest[0];
+    int bi = wbi[0];
+    double tail = wtail[0] + wtail[1];
+    if (wbi[1] >= 0 && (bi < 0 || wbest[1] > best || (wbest[1] == best && wbi[1] < bi))) {
+      best = wbest[1];
+      bi = wbi[1];
+    }
+    bool done = false;
+    if (p == 0) {
+      thr = tau_b * tail * (1.0 - 4.0 * nb * 1.1102230246251565e-16);
+      if (tid == 0 && tail1_out) *tail1_out = tail;
+      if (xs2_rows) {
+        double xs2 = 0.0;
+        for (int q = 0; q < nb; ++q) xs2 += xs2_rows[q];
+        if (!(tail > 1e-26 * xs2)) {
+          done = true;
+          if (stop_out && tid == 0) *stop_out = 1;
+        }
+      }
+    }
+    if (p == nb || bi < 0 || !(best > 0.0)) done = true;
+    if (p > 0 && tail < thr) done = true;
+    if (done) {
+      bp = p;
+      break;
+    }
+    const int jp = bi;
+    const double r = sqrt(best);
+    if (tid < nb) {
+      double v;
+      if (tid == jp) v = r;
+      else if (chosen) v = 0.0;
+      else v = Ss[jp * ld + tid] / r;
+      rrow[tid] = v;
+      Rraw[(int64_t)p * ldr + tid] = v;
+      if (tid == jp) {
+        chosen = true;
+        chosen_s[tid] = 1;
+        pivs[p] = jp;
+      }
+      dj -= v * v;
+    }
+    __syncthreads();
+    // rank-one update of the remaining Schur complement
+    if (urow0 < rstep && tid < rstep * nb) {
+      const double rc = rrow[ucol];
+      if (rc != 0.0) {
+#pragma unroll 8
+        for (int i = urow0; i < nb; i += rstep) Ss[i * ld + ucol] -= rrow[i] * rc;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    int q = bp;
+    for (int c = 0; c < nb; ++c)
+      if (!chosen_s[c]) pivs[q++] = c;
+    *bprime_out = bp;
+  }
+  __syncthreads();
+  if (tid < nb) piv[tid] = pivs[tid];
+  // R11 in pivoted order, zero outside the leading b' x b' upper triangle
+  for (int e = tid; e < nb_host * nb_host; e += kPivThreads) {
+    const int a = e / nb_host, c = e - a * nb_host;
+    double v = 0.0;
+    if (a < bp && c >= a && c < nb) v = Rraw[(int64_t)a * ldr + pivs[c]];
+    Rp[(int64_t)a * ldp + c] = v;
+  }
+  __syncthreads();
+}
+
+}  // namespace rbrp

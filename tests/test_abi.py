@@ -111,3 +111,57 @@ def test_no_cpu_fallback_in_binding():
     # the binding only marshals arguments: it never imports the oracle
     src = open(os.path.join(ROOT, "paper_2309_16002_amd", "_binding.py")).read()
     assert "oracle" not in src and "numpy" not in src
+
+
+def _shape(m=1024, n=256, b=32, k=256, nwg=0):
+    sh = B.rbrp_batch_shape()
+    sh.m_max, sh.n_max, sh.b_max, sh.k_cap_max, sh.num_wg = m, n, b, k, nwg
+    return sh
+
+
+def test_batch_workspace_size_validates(L):
+    assert L.rbrp_batch_workspace_size(0, ctypes.byref(_shape())) > 0
+    big = L.rbrp_batch_workspace_size(1, ctypes.byref(_shape()))
+    assert big > L.rbrp_batch_workspace_size(0, ctypes.byref(_shape()))
+    assert L.rbrp_batch_workspace_size(0, ctypes.byref(_shape(n=257))) == 0
+    assert L.rbrp_batch_workspace_size(0, ctypes.byref(_shape(b=33))) == 0
+    assert L.rbrp_batch_workspace_size(0, ctypes.byref(_shape(k=257))) == 0
+    assert L.rbrp_batch_workspace_size(0, ctypes.byref(_shape(m=16385))) == 0
+    assert L.rbrp_batch_workspace_size(2, ctypes.byref(_shape())) == 0
+    assert L.rbrp_batch_workspace_size(0, None) == 0
+    # scratch grows with the number of persistent workgroups
+    assert (L.rbrp_batch_workspace_size(0, ctypes.byref(_shape(nwg=768)))
+            > L.rbrp_batch_workspace_size(0, ctypes.byref(_shape(nwg=256))))
+
+
+def _call_batched(L, descs=1, count=4, dt=0, eps=1e-3, opt=None, shape=True, k=1, st=1,
+                  ws=1, wsb=1 << 40):
+    sh = _shape()
+    return L.rbrp_id_batched(ctypes.c_void_p(descs) if descs else None, None, count, dt, eps,
+                             1, ctypes.byref(opt) if opt else None,
+                             ctypes.byref(sh) if shape else None,
+                             ctypes.c_void_p(k) if k else None,
+                             ctypes.c_void_p(st) if st else None, None,
+                             ctypes.c_void_p(ws) if ws else None, wsb, None)
+
+
+def test_batched_rejects_before_device_work(L):
+    # dangling non-null pointers: only host validation may run
+    assert _call_batched(L, descs=0) == B.RBRP_E_INVALID
+    assert _call_batched(L, k=0) == B.RBRP_E_INVALID
+    assert _call_batched(L, st=0) == B.RBRP_E_INVALID
+    assert _call_batched(L, ws=0) == B.RBRP_E_INVALID
+    assert _call_batched(L, count=-1) == B.RBRP_E_INVALID
+    assert _call_batched(L, dt=5) == B.RBRP_E_INVALID
+    assert _call_batched(L, eps=-1.0) == B.RBRP_E_INVALID
+    assert _call_batched(L, eps=1.0) == B.RBRP_E_INVALID
+    assert _call_batched(L, shape=False) == B.RBRP_E_INVALID
+    assert _call_batched(L, wsb=1) == B.RBRP_E_WORKSPACE
+    assert _call_batched(L, opt=B.make_options(greedy=True)) == B.RBRP_E_UNSUPPORTED
+    assert _call_batched(L, opt=B.make_options(precision="bf16")) == B.RBRP_E_UNSUPPORTED
+    assert _call_batched(L, count=0) == B.RBRP_OK   # nothing to do, nothing launched
+
+
+def test_batch_desc_layout():
+    assert ctypes.sizeof(B.rbrp_batch_desc) == 64
+    assert ctypes.sizeof(B.rbrp_batch_shape) == 32
