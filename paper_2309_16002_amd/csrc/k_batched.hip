@@ -18,7 +18,11 @@
 // transposed (R^T, n x m) in per-workgroup scratch that stays in cache, and
 // the products run on the vector ALUs with one thread per row: a thread
 // holds its row's b' projections in registers and reads Q' from LDS as
-// broadcasts.
+// broadcasts.  With one workgroup per CU there is little other work to hide
+// memory latency, so the sampled block lives in LDS for the projections and
+// the filter, the small triangular factors of the W solve live in LDS when
+// they fit, and every loop over global data loads eight independent values
+// before using them.
 #include "rbrp_wg.h"
 
 namespace rbrp {
@@ -28,13 +32,17 @@ constexpr int kBatchMaxB = 32;      // block size limit of the batched form
 constexpr int kBatchMaxTiles = 8;   // rows per ID <= 8 * kScanTile
 constexpr int kBatchMaxN = 256;     // columns per ID
 constexpr int kBatchMaxK = 256;     // skeletons per ID
+constexpr int kChunk = 8;           // independent loads issued together
 
-// Per-workgroup scratch geometry (bytes offsets inside one workgroup's slice).
+// Per-workgroup scratch geometry (byte offsets inside one workgroup's slice)
+// and the dynamic LDS layout.  n8 = n_max rounded up to kChunk: R^T and Q
+// carry zero columns up to n8 so that chunked loops need no tail.
 struct BatchGeom {
-  int64_t mpad, nmax, kcap, bmax;
-  int64_t off_rt, off_d, off_sel, off_cdf, off_tsum, off_tpos, off_qt, off_vt, off_qtmp,
-      off_c, off_g, off_rraw, off_rp, off_idx, off_xs2, off_piv, off_l, off_l1, off_linv;
-  int64_t slice;   // bytes per workgroup
+  int64_t mpad, nmax, n8, kcap, bmax, bq;   // bq: row stride of Q'^T (bmax rounded to 8)
+  int64_t off_rt, off_d, off_sel, off_cdf, off_tsum, off_tpos, off_qt, off_c, off_g,
+      off_rraw, off_rp, off_idx, off_xs2, off_piv, off_l, off_l1, off_linv;
+  int64_t slice;                    // bytes per workgroup
+  int64_t lds_a, lds_q, lds_s, lds_w;  // LDS bytes: block, Q'^T, Schur, row buffers
 };
 
 static int64_t take(int64_t& off, int64_t bytes) {
@@ -48,18 +56,18 @@ static BatchGeom batch_geom(rbrp_dtype dt, const rbrp_batch_shape& sh) {
   const int64_t ts = dt == RBRP_F64 ? 8 : 4;
   g.mpad = round_up(sh.m_max, 64);
   g.nmax = sh.n_max;
+  g.n8 = round_up(sh.n_max, kChunk);
   g.kcap = sh.k_cap_max;
   g.bmax = sh.b_max;
+  g.bq = round_up(sh.b_max, 8);
   int64_t off = 0;
-  g.off_rt = take(off, g.nmax * g.mpad * ts);
+  g.off_rt = take(off, g.n8 * g.mpad * ts);
   g.off_d = take(off, g.mpad * 8);
   g.off_sel = take(off, g.mpad * 4);
   g.off_cdf = take(off, g.mpad * 8);
   g.off_tsum = take(off, (kBatchMaxTiles + 1) * 8);
   g.off_tpos = take(off, (kBatchMaxTiles + 1) * 4);
-  g.off_qt = take(off, g.kcap * g.nmax * 8);
-  g.off_vt = take(off, g.bmax * g.nmax * 8);
-  g.off_qtmp = take(off, g.bmax * g.nmax * 8);
+  g.off_qt = take(off, g.kcap * g.n8 * 8);
   g.off_c = take(off, g.kcap * g.bmax * 8);
   g.off_g = take(off, g.bmax * g.bmax * 8);
   g.off_rraw = take(off, g.bmax * g.bmax * 8);
@@ -71,6 +79,13 @@ static BatchGeom batch_geom(rbrp_dtype dt, const rbrp_batch_shape& sh) {
   g.off_l1 = take(off, g.kcap * g.kcap * 8);
   g.off_linv = take(off, g.kcap * g.kcap * 8);
   g.slice = off;
+  g.lds_a = round_up(g.bmax * g.n8 * 8, 16);
+  g.lds_q = round_up(g.n8 * g.bq * ts, 16);
+  // room for L_1 and L_1^{-1} of the W solve in LDS up to k = 64
+  const int64_t kw = g.kcap < 64 ? g.kcap : 64;
+  if (g.lds_a + g.lds_q < 2 * kw * kw * 8) g.lds_a = 2 * kw * kw * 8 - g.lds_q;
+  g.lds_s = round_up(g.bmax * (g.bmax + 1) * 8, 16);
+  g.lds_w = (kBT / 64) * 2 * g.kcap * 8;
   return g;
 }
 
@@ -99,42 +114,116 @@ __device__ __forceinline__ void wg_sum_max(double s, double mx, double* red, dou
   __syncthreads();
 }
 
-// A (na rows of length n, row stride ldv) -= Q^T-projection: C = Qt[0:k] A^T,
-// A -= C^T Qt[0:k] (FP64).
-__device__ __forceinline__ void wg_project(double* __restrict__ A, int64_t ldv, int na,
-                                           const double* __restrict__ Qt, int64_t ldq,
-                                           int64_t k, int64_t n, double* __restrict__ C) {
+// Rows of the LDS block As (na rows, stride n8) minus their projection on
+// the basis: C = Qt[0:k] As^T (C in global scratch, k x na), As -= C^T Qt.
+// Qt rows (stride n8) are zero beyond column n, as are the rows of As.
+__device__ __forceinline__ void lds_project(double* __restrict__ As, int na, int64_t n8,
+                                            const double* __restrict__ Qt, int64_t k,
+                                            double* __restrict__ C) {
   const int tid = threadIdx.x;
   for (int64_t e = tid; e < k * na; e += kBT) {
     const int64_t p = e / na, j = e - p * na;
-    const double* q = Qt + p * ldq;
-    const double* a = A + j * ldv;
-    double s = 0.0;
-    for (int64_t c = 0; c < n; ++c) s += q[c] * a[c];
-    C[p * na + j] = s;
+    const double* q = Qt + p * n8;
+    const double* a = As + j * n8;
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t c0 = 0; c0 < n8; c0 += kChunk) {
+      double qv[kChunk];
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) qv[u] = q[c0 + u];
+#pragma unroll
+      for (int u = 0; u < kChunk; u += 2) {
+        s0 += qv[u] * a[c0 + u];
+        s1 += qv[u + 1] * a[c0 + u + 1];
+      }
+    }
+    C[p * na + j] = s0 + s1;
   }
   __syncthreads();
-  for (int64_t e = tid; e < na * n; e += kBT) {
-    const int64_t j = e / n, c = e - j * n;
-    double v = A[j * ldv + c];
-    for (int64_t p = 0; p < k; ++p) v -= C[p * na + j] * Qt[p * ldq + c];
-    A[j * ldv + c] = v;
+  for (int64_t e = tid; e < na * n8; e += kBT) {
+    const int64_t j = e / n8, c = e - j * n8;
+    double v = As[j * n8 + c];
+    int64_t p0 = 0;
+    for (; p0 + kChunk <= k; p0 += kChunk) {
+      double cv[kChunk], qv[kChunk];
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) {
+        cv[u] = C[(p0 + u) * na + j];
+        qv[u] = Qt[(p0 + u) * n8 + c];
+      }
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) v -= cv[u] * qv[u];
+    }
+    for (; p0 < k; ++p0) v -= C[p0 * na + j] * Qt[p0 * n8 + c];
+    As[j * n8 + c] = v;
   }
   __syncthreads();
 }
 
-// G = A A^T for na rows of A (FP64).
-__device__ __forceinline__ void wg_gram(const double* __restrict__ A, int64_t ldv, int na,
-                                        int64_t n, double* __restrict__ G, int64_t ldg) {
+// G = As As^T for na rows of the LDS block (global G, stride ldg).
+__device__ __forceinline__ void lds_gram(const double* __restrict__ As, int na, int64_t n8,
+                                         double* __restrict__ G, int64_t ldg) {
   for (int e = threadIdx.x; e < na * na; e += kBT) {
     const int i = e / na, j = e - i * na;
-    const double* a = A + (int64_t)i * ldv;
-    const double* b = A + (int64_t)j * ldv;
-    double s = 0.0;
-    for (int64_t c = 0; c < n; ++c) s += a[c] * b[c];
-    G[(int64_t)i * ldg + j] = s;
+    const double* a = As + (int64_t)i * n8;
+    const double* b = As + (int64_t)j * n8;
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t c = 0; c < n8; c += 2) {
+      s0 += a[c] * b[c];
+      s1 += a[c + 1] * b[c + 1];
+    }
+    G[(int64_t)i * ldg + j] = s0 + s1;
   }
   __syncthreads();
+}
+
+// Deflation of the residual by the new basis block, one thread per row:
+// P = R Q' (b' <= NBT values in registers), L(i, kS:kS+b') = P (zero on rows
+// of earlier skeletons), R <- R - P Q'^T, d_i = ||R_i||^2 (FP64), 0 on
+// skeletons.  QfT (LDS) is n8 x bq, zero outside b' columns and n rows.
+template <int NBT, typename T>
+__device__ __forceinline__ void deflate_rows(T* __restrict__ RT, int64_t mpad, int64_t m,
+                                             int64_t n8, const T* __restrict__ QfT,
+                                             int64_t bq, T* __restrict__ L, int64_t ldl,
+                                             int64_t kS, int bp,
+                                             const int32_t* __restrict__ sel, int32_t t,
+                                             double* __restrict__ d) {
+  for (int64_t i = threadIdx.x; i < m; i += kBT) {
+    T acc[NBT];
+#pragma unroll
+    for (int j = 0; j < NBT; ++j) acc[j] = (T)0;
+    for (int64_t c0 = 0; c0 < n8; c0 += kChunk) {
+      T r[kChunk];
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) r[u] = RT[(c0 + u) * mpad + i];
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) {
+        const T* qc = QfT + (c0 + u) * bq;
+#pragma unroll
+        for (int j = 0; j < NBT; ++j) acc[j] += r[u] * qc[j];
+      }
+    }
+    const int32_t sb = sel[i];
+    const bool earlier = sb >= 0 && sb < t;
+    T* lr = L + i * ldl + kS;
+#pragma unroll
+    for (int j = 0; j < NBT; ++j)
+      if (j < bp) lr[j] = earlier ? (T)0 : acc[j];
+    double nrm = 0.0;
+    for (int64_t c0 = 0; c0 < n8; c0 += kChunk) {
+      T r[kChunk];
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) r[u] = RT[(c0 + u) * mpad + i];
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) {
+        const T* qc = QfT + (c0 + u) * bq;
+#pragma unroll
+        for (int j = 0; j < NBT; ++j) r[u] -= acc[j] * qc[j];
+        RT[(c0 + u) * mpad + i] = r[u];
+        nrm += (double)r[u] * (double)r[u];
+      }
+    }
+    d[i] = sb >= 0 ? 0.0 : nrm;
+  }
 }
 
 template <typename T>
@@ -150,15 +239,19 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
   __shared__ uint64_t wsum[4];
   __shared__ int32_t wpos[4];
   __shared__ int32_t s_item, s_nt, s_bp, s_stop, s_flag;
-  __shared__ double s_sum, s_max, s_tail1;
+  __shared__ double s_tail1;
 
   const int tid = threadIdx.x;
-  const int64_t nmax = geom.nmax, mpad = geom.mpad, kcapw = geom.kcap, bmax = geom.bmax;
-  // LDS: Q'^T in the deflation precision (n x bmax), the Schur buffer of the
-  // filter ((bmax) x (bmax + 1)), and a per-wave row buffer for W (4 x kcap)
-  T* QfT = reinterpret_cast<T*>(dsm);
-  double* Ss = reinterpret_cast<double*>(dsm + round_up(nmax * bmax * sizeof(T), 16));
-  double* wrow = Ss + bmax * (bmax + 1);
+  const int64_t nmax = geom.nmax, n8 = geom.n8, mpad = geom.mpad, kcapw = geom.kcap;
+  const int64_t bmax = geom.bmax, bq = geom.bq;
+  // LDS: the sampled block / new basis rows (bmax x n8, FP64), Q'^T in the
+  // deflation precision (n8 x bq), the Schur buffer of the filter, and two
+  // row buffers per wave for W.  The first two regions hold L_1 and L_1^{-1}
+  // during the W solve when they fit.
+  double* As = reinterpret_cast<double*>(dsm);
+  T* QfT = reinterpret_cast<T*>(dsm + geom.lds_a);
+  double* Ss = reinterpret_cast<double*>(dsm + geom.lds_a + geom.lds_q);
+  double* wrow = reinterpret_cast<double*>(dsm + geom.lds_a + geom.lds_q + geom.lds_s);
 
   char* base = scratch + (int64_t)blockIdx.x * geom.slice;
   T* RT = reinterpret_cast<T*>(base + geom.off_rt);
@@ -168,8 +261,6 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
   uint64_t* tsum = reinterpret_cast<uint64_t*>(base + geom.off_tsum);
   int32_t* tpos = reinterpret_cast<int32_t*>(base + geom.off_tpos);
   double* Qt = reinterpret_cast<double*>(base + geom.off_qt);
-  double* Vt = reinterpret_cast<double*>(base + geom.off_vt);
-  double* Qtmp = reinterpret_cast<double*>(base + geom.off_qtmp);
   double* C = reinterpret_cast<double*>(base + geom.off_c);
   double* G = reinterpret_cast<double*>(base + geom.off_g);
   double* Rraw = reinterpret_cast<double*>(base + geom.off_rraw);
@@ -178,8 +269,8 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
   double* xs2 = reinterpret_cast<double*>(base + geom.off_xs2);
   int32_t* piv = reinterpret_cast<int32_t*>(base + geom.off_piv);
   T* L = reinterpret_cast<T*>(base + geom.off_l);
-  double* L1 = reinterpret_cast<double*>(base + geom.off_l1);
-  double* Linv = reinterpret_cast<double*>(base + geom.off_linv);
+  double* L1g = reinterpret_cast<double*>(base + geom.off_l1);
+  double* Linvg = reinterpret_cast<double*>(base + geom.off_linv);
 
   while (true) {
     if (tid == 0) s_item = atomicAdd(queue, 1);
@@ -209,18 +300,31 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
     const double tau_b = prm.tau_b > 0.0 ? prm.tau_b : 1.0 / b;
     const double tau = prm.eps * prm.eps;
 
-    // ---- initial norms, R^T <- X^T, skeleton flags ----
+    // ---- initial norms, R^T <- X^T (zero columns n..n8), skeleton flags ----
     double part = 0.0;
     int bad = 0;
     for (int64_t i = tid; i < m; i += kBT) {
       const T* xr = X + i * ldx;
       double s = 0.0;
-      for (int64_t c = 0; c < n; ++c) {
-        const T x = xr[c];
+      int64_t c0 = 0;
+      for (; c0 + kChunk <= n; c0 += kChunk) {
+        T xv[kChunk];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) xv[u] = xr[c0 + u];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+          bad |= !isfinite((double)xv[u]);
+          s += (double)xv[u] * (double)xv[u];
+          RT[(c0 + u) * mpad + i] = xv[u];
+        }
+      }
+      for (; c0 < n; ++c0) {
+        const T x = xr[c0];
         bad |= !isfinite((double)x);
         s += (double)x * (double)x;
-        RT[c * mpad + i] = x;
+        RT[c0 * mpad + i] = x;
       }
+      for (int64_t c = n; c < n8; ++c) RT[c * mpad + i] = (T)0;
       d[i] = s;
       sel[i] = -1;
       part += s;
@@ -260,48 +364,54 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
                                 idx, &s_nt, nullptr, ssh);
       const int nt = s_nt;
       if (nt <= 0) break;
-      // ---- V^T: sampled rows of X in FP64, projected twice against Q ----
-      for (int64_t e = tid; e < nt * n; e += kBT) {
-        const int64_t j = e / n, c = e - j * n;
-        Vt[j * nmax + c] = (double)X[idx[j] * ldx + c];
+      // ---- V^T: sampled rows of X in FP64 (LDS), projected twice against Q ----
+      for (int64_t e = tid; e < nt * n8; e += kBT) {
+        const int64_t j = e / n8, c = e - j * n8;
+        As[j * n8 + c] = c < n ? (double)X[idx[j] * ldx + c] : 0.0;
       }
       __syncthreads();
       if (tid < nt) {
         double s = 0.0;
-        for (int64_t c = 0; c < n; ++c) s += Vt[tid * nmax + c] * Vt[tid * nmax + c];
+        for (int64_t c = 0; c < n8; ++c) s += As[tid * n8 + c] * As[tid * n8 + c];
         xs2[tid] = s;
       }
       __syncthreads();
       if (kS > 0) {
-        wg_project(Vt, nmax, nt, Qt, nmax, kS, n, C);
-        wg_project(Vt, nmax, nt, Qt, nmax, kS, n, C);
+        lds_project(As, nt, n8, Qt, kS, C);
+        lds_project(As, nt, n8, Qt, kS, C);
       }
       // ---- robust blockwise filter: pivoted Cholesky of V^T V ----
-      wg_gram(Vt, nmax, nt, n, G, bmax);
+      lds_gram(As, nt, n8, G, bmax);
       if (tid == 0) s_stop = 0;
       __syncthreads();
       wg_piv_chol(G, bmax, nt, nullptr, tau_b, xs2, piv, Rraw, bmax, Rp, bmax, &s_bp, &s_tail1,
                   &s_stop, Ss, psh);
       const int bp = s_bp;
       if (s_stop || bp <= 0) break;
-      // ---- Q' = V(:, piv(1:b')) R11^{-1}: one thread per column ----
-      for (int64_t c = tid; c < n; c += kBT) {
+      // ---- Q' = V(:, piv(1:b')) R11^{-1}, in place in As (one thread per
+      // column: the column's kept entries are read before any is written) ----
+      for (int64_t c = tid; c < n8; c += kBT) {
         double q[kBatchMaxB];
+#pragma unroll
+        for (int p = 0; p < kBatchMaxB; ++p)
+          if (p < bp) q[p] = As[(int64_t)piv[p] * n8 + c];
 #pragma unroll
         for (int p = 0; p < kBatchMaxB; ++p) {
           if (p < bp) {
-            double v = Vt[(int64_t)piv[p] * nmax + c];
+            double v = q[p];
 #pragma unroll
             for (int r = 0; r < p; ++r) v -= Rp[r * bmax + p] * q[r];
             q[p] = v / Rp[p * bmax + p];
-            Qtmp[p * nmax + c] = q[p];
           }
         }
+#pragma unroll
+        for (int p = 0; p < kBatchMaxB; ++p)
+          if (p < bp) As[p * n8 + c] = q[p];
       }
       __syncthreads();
       // ---- reorthogonalisation: project, then Cholesky QR ----
-      if (kS > 0) wg_project(Qtmp, nmax, bp, Qt, nmax, kS, n, C);
-      wg_gram(Qtmp, nmax, bp, n, G, bmax);
+      if (kS > 0) lds_project(As, bp, n8, Qt, kS, C);
+      lds_gram(As, bp, n8, G, bmax);
       // Cholesky G = R2^T R2 (right-looking, in place in the upper triangle)
       if (tid == 0) s_flag = 0;
       __syncthreads();
@@ -327,20 +437,23 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
         status = RBRP_E_HIP;  // the new block lost orthogonality beyond repair
         break;
       }
-      // Qn = R2^{-T} Qtmp into Qt rows kS.., and its copy for the deflation
-      for (int64_t c = tid; c < n; c += kBT) {
+      // Qn = R2^{-T} Qtmp into Qt rows kS.. (zero beyond column n) and its
+      // copy for the deflation (zero beyond b' columns and n rows)
+      for (int64_t c = tid; c < n8; c += kBT) {
         double q[kBatchMaxB];
 #pragma unroll
         for (int p = 0; p < kBatchMaxB; ++p) {
           if (p < bp) {
-            double v = Qtmp[p * nmax + c];
+            double v = As[p * n8 + c];
 #pragma unroll
             for (int r = 0; r < p; ++r) v -= G[r * bmax + p] * q[r];
-            q[p] = v / G[p * bmax + p];
-            Qt[(kS + p) * nmax + c] = q[p];
-            QfT[c * bmax + p] = (T)q[p];
+            q[p] = c < n ? v / G[p * bmax + p] : 0.0;
+            Qt[(kS + p) * n8 + c] = q[p];
           }
         }
+#pragma unroll
+        for (int p = 0; p < kBatchMaxB; ++p)
+          if (p < bq) QfT[c * bq + p] = p < bp ? (T)q[p] : (T)0;
       }
       // append the kept skeletons
       if (tid < bp) {
@@ -350,35 +463,15 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
       }
       __syncthreads();
       // ---- deflation: P = R Q', L(:, kS:kS+b') = P, R <- R - P Q'^T ----
-      for (int64_t i = tid; i < m; i += kBT) {
-        T acc[kBatchMaxB];
-#pragma unroll
-        for (int j = 0; j < kBatchMaxB; ++j) acc[j] = (T)0;
-        for (int64_t c = 0; c < n; ++c) {
-          const T r = RT[c * mpad + i];
-          const T* qc = QfT + c * bmax;
-#pragma unroll
-          for (int j = 0; j < kBatchMaxB; ++j)
-            if (j < bp) acc[j] += r * qc[j];
-        }
-        const int32_t sb = sel[i];
-        const bool earlier = sb >= 0 && sb < t;
-        T* lr = L + i * kcapw + kS;
-#pragma unroll
-        for (int j = 0; j < kBatchMaxB; ++j)
-          if (j < bp) lr[j] = earlier ? (T)0 : acc[j];
-        double nrm = 0.0;
-        for (int64_t c = 0; c < n; ++c) {
-          T r = RT[c * mpad + i];
-          const T* qc = QfT + c * bmax;
-#pragma unroll
-          for (int j = 0; j < kBatchMaxB; ++j)
-            if (j < bp) r -= acc[j] * qc[j];
-          RT[c * mpad + i] = r;
-          nrm += (double)r * (double)r;
-        }
-        d[i] = sb >= 0 ? 0.0 : nrm;
-      }
+      const int nbt = (bp + 7) & ~7;
+      if (nbt <= 8)
+        deflate_rows<8, T>(RT, mpad, m, n8, QfT, bq, L, kcapw, kS, bp, sel, t, d);
+      else if (nbt <= 16)
+        deflate_rows<16, T>(RT, mpad, m, n8, QfT, bq, L, kcapw, kS, bp, sel, t, d);
+      else if (nbt <= 24)
+        deflate_rows<24, T>(RT, mpad, m, n8, QfT, bq, L, kcapw, kS, bp, sel, t, d);
+      else
+        deflate_rows<32, T>(RT, mpad, m, n8, QfT, bq, L, kcapw, kS, bp, sel, t, d);
       __syncthreads();
       kS += bp;
     }
@@ -399,6 +492,9 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
     if (!ds.W || k == 0) continue;
 
     // ---- W = L L_1^{-1}, one refinement step per prm.refine, W(S,:) = I ----
+    const bool wl = 2 * k * k * 8 <= geom.lds_a + geom.lds_q;
+    double* L1 = wl ? As : L1g;
+    double* Linv = wl ? As + k * k : Linvg;
     for (int64_t e = tid; e < k * k; e += kBT) {
       const int64_t j = e / k, p = e - j * k;
       L1[e] = (p <= j) ? (double)L[ds.S[j] * kcapw + p] : 0.0;
@@ -416,15 +512,23 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
     __syncthreads();
     {
       const int lane = tid & 63, wv = tid >> 6;
-      double* wr = wrow + wv * kcapw;          // this wave's row buffer
+      double* wl_row = wrow + wv * 2 * kcapw;   // this wave's copy of the row of L
+      double* wbuf = wl_row + kcapw;            // and of w, then of the residual e
       constexpr int KS = kBatchMaxK / 64;
       for (int64_t i = wv; i < m; i += kBT / 64) {
         const T* lr = L + i * kcapw;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const int64_t p = lane + 64 * s;
+          if (p < k) wl_row[p] = (double)lr[p];
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         double w[KS];
 #pragma unroll
         for (int s = 0; s < KS; ++s) w[s] = 0.0;
         for (int64_t p = 0; p < k; ++p) {
-          const double lp = (double)lr[p];
+          const double lp = wl_row[p];
 #pragma unroll
           for (int s = 0; s < KS; ++s) {
             const int64_t j = lane + 64 * s;
@@ -436,7 +540,7 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
 #pragma unroll
           for (int s = 0; s < KS; ++s) {
             const int64_t j = lane + 64 * s;
-            if (j < k) wr[j] = w[s];
+            if (j < k) wbuf[j] = w[s];
           }
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -446,8 +550,8 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
             const int64_t p = lane + 64 * s;
             double v = 0.0;
             if (p < k) {
-              v = (double)lr[p];
-              for (int64_t j = p; j < k; ++j) v -= wr[j] * L1[j * k + p];
+              v = wl_row[p];
+              for (int64_t j = p; j < k; ++j) v -= wbuf[j] * L1[j * k + p];
             }
             ev[s] = v;
           }
@@ -456,13 +560,13 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
 #pragma unroll
           for (int s = 0; s < KS; ++s) {
             const int64_t p = lane + 64 * s;
-            if (p < k) wr[p] = ev[s];
+            if (p < k) wbuf[p] = ev[s];
           }
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
           // w += e L_1^{-1}
           for (int64_t p = 0; p < k; ++p) {
-            const double ep = wr[p];
+            const double ep = wbuf[p];
 #pragma unroll
             for (int s = 0; s < KS; ++s) {
               const int64_t j = lane + 64 * s;
@@ -477,6 +581,8 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
           const int64_t j = lane + 64 * s;
           if (j < k) ds.W[i * ds.ldw + j] = w[s];
         }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       }
     }
     __syncthreads();
@@ -492,10 +598,8 @@ __global__ void k_batch_queue_reset(int32_t* q) {
   if (threadIdx.x == 0) *q = 0;
 }
 
-static size_t batch_lds_bytes(rbrp_dtype dt, const BatchGeom& g) {
-  const size_t ts = dt == RBRP_F64 ? 8 : 4;
-  return round_up(g.nmax * g.bmax * ts, 16) + (size_t)g.bmax * (g.bmax + 1) * 8 +
-         (size_t)(kBT / 64) * g.kcap * 8;
+static size_t batch_lds_bytes(rbrp_dtype, const BatchGeom& g) {
+  return (size_t)(g.lds_a + g.lds_q + g.lds_s + g.lds_w);
 }
 
 static int default_num_wg() { return 256 * 2; }

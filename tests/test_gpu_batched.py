@@ -49,7 +49,7 @@ def _launch(rb, Xs, eps, b, seed, **kw):
     return plan
 
 
-@pytest.mark.parametrize("b", [8, 16])
+@pytest.mark.parametrize("b", [8, 12, 16])
 def test_fp64_batch_matches_oracle(rb, b):
     eps, seed = 1e-3, 5
     Xs = _fp64_batch(24, 300 + b)
