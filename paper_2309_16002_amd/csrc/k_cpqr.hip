@@ -228,69 +228,61 @@ __global__ __launch_bounds__(kPivThreads) void k_cpqr_piv(
               tail1_out, stop_out, Ss, sh);
 }
 
-// Rows of Qtmp: Qtmp[p,:] = (Vt[piv[p],:] - sum_{q<p} R11[q][p] Qtmp[q,:]) /
-// R11[p][p] for p < b' (the orthonormal basis of the kept columns,
-// Q' = V(:, piv(1:b')) R11^{-1}), rows b'..nb_host-1 set to zero.  One thread
-// per column; the column's unknowns are solved in chunks of 64 held in
-// registers (fully unrolled), R11 is read from LDS as broadcasts.
-constexpr int kSolveChunk = 64;
+// Q' = V(:, piv(1:b')) R11^{-1} (the orthonormal basis of the kept columns),
+// as rows of Qtmp: first R11^{-1} by back substitution in one workgroup
+// (thread j < b' solves column j; R11 and the inverse live in LDS as packed
+// upper triangles), then
+// Qtmp = (R11^{-1})^T-weighted sums of the pivoted rows of V^T on MFMA
+// (k_gemm_tn16: 16 x 16 output tiles over all columns).  Rows b'..nb_host-1
+// of Qtmp come out zero (R11^{-1} is zero outside its leading b' x b' block).
+// Upper triangles packed row by row: element (i, j), i <= j < nb, at
+// i nb - i (i - 1) / 2 + (j - i).
+__device__ __forceinline__ int tri_off(int i, int j, int nb) {
+  return i * nb - (i * (i - 1)) / 2 + (j - i);
+}
 
-__global__ __launch_bounds__(64) void k_qsolve(const double* __restrict__ Vt, int64_t ldv,
-                                               const int32_t* __restrict__ piv,
-                                               const double* __restrict__ Rp, int64_t ldp,
-                                               const int32_t* __restrict__ bprime,
-                                               int32_t nb_host, int64_t ncols,
-                                               double* __restrict__ Qt, int64_t ldq) {
-  extern __shared__ double Rs[];
-  __shared__ int32_t ps[kMaxB];
+__global__ __launch_bounds__(256) void k_tri_inv_upper(const double* __restrict__ Rp,
+                                                       int64_t ldp,
+                                                       const int32_t* __restrict__ bprime,
+                                                       int32_t nb_host,
+                                                       double* __restrict__ Rinv,
+                                                       int64_t ldi) {
+  // R11 and its inverse, upper triangles packed in LDS (2 x nb (nb + 1) / 2)
+  extern __shared__ double tri[];
   const int bp = *bprime;
-  for (int e = threadIdx.x; e < bp * bp; e += 64) {
-    const int a = e / bp, c = e - a * bp;
-    Rs[e] = Rp[(int64_t)a * ldp + c];
+  const int nb = bp;
+  double* Rs = tri;
+  double* Xs = tri + (nb * (nb + 1)) / 2;
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+    const int i = e / nb, c = e - i * nb;
+    if (c >= i) Rs[tri_off(i, c, nb)] = Rp[(int64_t)i * ldp + c];
   }
-  for (int e = threadIdx.x; e < bp; e += 64) ps[e] = piv[e];
   __syncthreads();
-  const int64_t c = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (c >= ncols) return;
-  for (int p0 = 0; p0 < nb_host; p0 += kSolveChunk) {
-    double x[kSolveChunk];
-#pragma unroll
-    for (int i = 0; i < kSolveChunk; ++i) {
-      const int p = p0 + i;
-      x[i] = (p < bp) ? Vt[(int64_t)ps[p] * ldv + c] : 0.0;
-    }
-    // contributions of earlier chunks (already stored)
-    for (int q = 0; q < p0 && q < bp; ++q) {
-      const double xq = Qt[(int64_t)q * ldq + c];
-#pragma unroll
-      for (int i = 0; i < kSolveChunk; ++i) {
-        const int p = p0 + i;
-        if (p < bp) x[i] -= Rs[q * bp + p] * xq;
+  const int j = threadIdx.x;
+  if (j < bp) {
+    // column j: X[j][j] = 1 / R[j][j]; X[i][j] = -(sum_{p=i+1..j} R[i][p] X[p][j]) / R[i][i]
+    Xs[tri_off(j, j, nb)] = 1.0 / Rs[tri_off(j, j, nb)];
+    for (int i = j - 1; i >= 0; --i) {
+      const double* ri = Rs + tri_off(i, 0, nb);  // ri[p] = R[i][p] for p >= i
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int p = i + 1;
+      for (; p + 3 <= j; p += 4) {
+        s0 += ri[p] * Xs[tri_off(p, j, nb)];
+        s1 += ri[p + 1] * Xs[tri_off(p + 1, j, nb)];
+        s2 += ri[p + 2] * Xs[tri_off(p + 2, j, nb)];
+        s3 += ri[p + 3] * Xs[tri_off(p + 3, j, nb)];
       }
+      for (; p <= j; ++p) s0 += ri[p] * Xs[tri_off(p, j, nb)];
+      Xs[tri_off(i, j, nb)] = -((s0 + s1) + (s2 + s3)) / ri[i];
     }
-#pragma unroll
-    for (int i = 0; i < kSolveChunk; ++i) {
-      const int p = p0 + i;
-      if (p < bp) {
-#pragma unroll
-        for (int k = 0; k < i; ++k) x[i] -= Rs[(p0 + k) * bp + p] * x[k];
-        x[i] /= Rs[p * bp + p];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < kSolveChunk; ++i) {
-      const int p = p0 + i;
-      if (p < nb_host) Qt[(int64_t)p * ldq + c] = (p < bp) ? x[i] : 0.0;
-    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nb_host * nb_host; e += blockDim.x) {
+    const int i = e / nb_host, c = e - i * nb_host;
+    Rinv[(int64_t)i * ldi + c] = (i < bp && c < bp && i <= c) ? Xs[tri_off(i, c, nb)] : 0.0;
   }
 }
 
-// Re-orthonormalisation factor for Qn = M2 Qtmp from G2 = Qtmp Qtmp^T
-// (b' x b').  With E = G2 - I, the Cholesky factor is R2 = I + U with
-// U = triu(E) - diag(E)/2 + O(|E|^2), so M2 = R2^{-T} = I - tril(E) +
-// diag(E)/2 + O(|E|^2).  When max|E| <= 1e-8 the first-order form is exact to
-// rounding and is written here (flag 0); otherwise flag 1 asks the exact
-// Cholesky path that follows to do the work.
 __global__ __launch_bounds__(256) void k_ortho_first_order(const double* __restrict__ G2,
                                                            int64_t ldg,
                                                            const int32_t* __restrict__ bprime,
@@ -348,21 +340,24 @@ hipError_t launch_cpqr_piv(const double* G, int64_t ldg, int32_t nb, const int32
 
 hipError_t launch_qsolve(const double* Vt, int64_t ldv, const int32_t* piv, const double* Rp,
                          int64_t ldp, const int32_t* bprime, int32_t nb_host, int64_t ncols,
-                         double* Qt, int64_t ldq, hipStream_t s) {
+                         double* Qt, int64_t ldq, double* Rinv_ws, hipStream_t s) {
   if (ncols <= 0) return hipSuccess;
   if (nb_host <= 0 || nb_host > kMaxB) return hipErrorInvalidValue;
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_qsolve,
+    hipError_t e = hipFuncSetAttribute((const void*)k_tri_inv_upper,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(kMaxB * kMaxB * sizeof(double)));
+                                       (int)(kMaxB * (kMaxB + 1) * sizeof(double)));
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_qsolve, dim3((unsigned)ceil_div(ncols, 64)), dim3(64),
-                     (size_t)nb_host * nb_host * sizeof(double), s, Vt, ldv, piv, Rp, ldp,
-                     bprime, nb_host, ncols, Qt, ldq);
-  return hipGetLastError();
+  hipLaunchKernelGGL(k_tri_inv_upper, dim3(1), dim3(kMaxB < 256 ? 256 : kMaxB),
+                     (size_t)nb_host * (nb_host + 1) * sizeof(double), s, Rp, ldp, bprime,
+                     nb_host, Rinv_ws, (int64_t)nb_host);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_gemm_tn_small(nb_host, ncols, nb_host, 1.0, Rinv_ws, nb_host, Vt, ldv, 0.0, Qt,
+                              ldq, s, piv, bprime);
 }
 
 hipError_t launch_ortho_first_order(const double* G2, int64_t ldg, const int32_t* bprime,

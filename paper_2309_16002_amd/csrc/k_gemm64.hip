@@ -254,6 +254,68 @@ hipError_t launch_gemm_nt_small(int64_t M, int64_t N, int64_t K, double alpha,
   return hipGetLastError();
 }
 
+
+// C[M x N] = alpha A[K x M]^T B[K x N] + beta C for small M and long N
+// (the basis projections V <- V - C^T Q of the sampled rows: M = b, K = |S|,
+// N = n; and Q' = R11^{-T}-weighted pivoted rows of V, with B's rows taken
+// through brow and K bounded on the device by *k_dev).  One workgroup per 16 x 16 output tile; its four waves take
+// interleaved 16-deep K chunks straight from global memory (16 consecutive
+// elements of a row of A or B per quarter-wave), and the partial tiles are
+// summed in LDS in wave order.  MFMA step s of a chunk uses K index
+// 4 s + l / 16 for both operands.
+__global__ __launch_bounds__(256) void k_gemm_tn16(int64_t M, int64_t N, int64_t K,
+                                                   double alpha, const double* __restrict__ A,
+                                                   int64_t lda, const double* __restrict__ B,
+                                                   int64_t ldb, const int32_t* __restrict__ brow,
+                                                   const int32_t* __restrict__ k_dev,
+                                                   double beta, double* __restrict__ C,
+                                                   int64_t ldc) {
+  __shared__ double part[4][256];
+  if (k_dev) K = min(K, (int64_t)*k_dev);
+  const int64_t i0 = (int64_t)blockIdx.y * 16, j0 = (int64_t)blockIdx.x * 16;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t ia = i0 + (lane & 15), jb = j0 + (lane & 15);
+  const bool va = ia < M, vb = jb < N;
+  const int kq = lane >> 4;
+  d4v acc = (d4v){0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+  for (int64_t k0 = 16 * w; k0 < K; k0 += 64) {
+    double a[4], b[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int64_t k = k0 + 4 * s + kq;
+      const bool kin = k < K;
+      a[s] = (va && kin) ? A[k * lda + ia] : 0.0;
+      b[s] = (vb && kin) ? B[(brow ? (int64_t)brow[k] : k) * ldb + jb] : 0.0;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) part[w][lane * 4 + q] = acc[q];
+  __syncthreads();
+  const int t = threadIdx.x;
+  const double sm = ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t];
+  const int ln = t >> 2, q = t & 3;
+  const int64_t row = i0 + (ln >> 4) + 4 * q, col = j0 + (ln & 15);
+  if (row < M && col < N) {
+    double v = alpha * sm;
+    if (beta != 0.0) v += beta * C[row * ldc + col];
+    C[row * ldc + col] = v;
+  }
+}
+
+hipError_t launch_gemm_tn_small(int64_t M, int64_t N, int64_t K, double alpha,
+                                const double* A, int64_t lda, const double* B, int64_t ldb,
+                                double beta, double* C, int64_t ldc, hipStream_t s,
+                                const int32_t* brow, const int32_t* k_dev) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  dim3 g((unsigned)ceil_div(N, 16), (unsigned)ceil_div(M, 16));
+  hipLaunchKernelGGL(k_gemm_tn16, g, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, brow,
+                     k_dev, beta, C, ldc);
+  return hipGetLastError();
+}
+
 }  // namespace rbrp
 
 namespace rbrp {

@@ -59,6 +59,7 @@ struct Work {
   double* R2raw;
   double* Mc;
   double* Mc2;
+  double* Rinv;
   double* Qtmp;
   double* Qt;
   void* fragB1;
@@ -129,6 +130,7 @@ size_t layout(const Plan& p, char* base, Work* w) {
   w->R2raw = cv.take<double>((size_t)p.b * p.b);
   w->Mc = cv.take<double>((size_t)p.b * p.b);
   w->Mc2 = cv.take<double>((size_t)p.b * p.b);
+  w->Rinv = cv.take<double>((size_t)p.b * p.b);
   w->Qtmp = cv.take<double>((size_t)p.b * p.ldr);
   w->Qt = cv.take<double>((size_t)p.k_max * p.ldr);
   w->fragB1 = cv.take<char>(frag_bytes(mode, p.ldr, p.b));
@@ -323,8 +325,8 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
       for (int pass = 0; pass < 2; ++pass) {
         RBRP_HIP(launch_gemm_nt_small(kS, bt, ldr, 1.0, w.Qt, ldr, w.Vt, ldr, 0.0, w.C, bt,
                                       nullptr, nullptr, s));
-        RBRP_HIP(launch_gemm_f64(1, 0, bt, ldr, kS, -1.0, w.C, 0, bt, w.Qt, ldr, 1.0, w.Vt,
-                                 ldr, nullptr, nullptr, 0, s));
+        RBRP_HIP(launch_gemm_tn_small(bt, ldr, kS, -1.0, w.C, bt, w.Qt, ldr, 1.0, w.Vt, ldr,
+                                      s));
       }
     }
     // robust blockwise filter: pivoted Cholesky of V^T V, then the kept columns'
@@ -333,13 +335,14 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
                                   nullptr, s));
     RBRP_HIP(launch_cpqr_piv(w.G, bt, bt, &w.sc->nt, tau_b, w.xs2, w.piv, w.Rraw, bt, w.Mc, bt,
                              &w.sc->bprime, &w.sc->tail1, &w.sc->stop_rank, s));
-    RBRP_HIP(launch_qsolve(w.Vt, ldr, w.piv, w.Mc, bt, &w.sc->bprime, bt, ldr, w.Qtmp, ldr, s));
+    RBRP_HIP(launch_qsolve(w.Vt, ldr, w.piv, w.Mc, bt, &w.sc->bprime, bt, ldr, w.Qtmp, ldr,
+                           w.Rinv, s));
     // second pass: project against the basis, then Cholesky QR
     if (kS > 0) {
       RBRP_HIP(launch_gemm_nt_small(kS, bt, ldr, 1.0, w.Qt, ldr, w.Qtmp, ldr, 0.0, w.C, bt,
                                     nullptr, nullptr, s));
-      RBRP_HIP(launch_gemm_f64(1, 0, bt, ldr, kS, -1.0, w.C, 0, bt, w.Qt, ldr, 1.0, w.Qtmp,
-                               ldr, nullptr, nullptr, 0, s));
+      RBRP_HIP(launch_gemm_tn_small(bt, ldr, kS, -1.0, w.C, bt, w.Qt, ldr, 1.0, w.Qtmp, ldr,
+                                    s));
     }
     RBRP_HIP(launch_gemm_nt_small(bt, bt, ldr, 1.0, w.Qtmp, ldr, w.Qtmp, ldr, 0.0, w.G, bt,
                                   nullptr, nullptr, s));
@@ -476,7 +479,7 @@ rbrp_status rbrp_sample_block(const double* d, const uint8_t* excluded, int64_t 
 
 size_t rbrp_block_cpqr_workspace_size(int64_t n, int32_t nb) {
   if (n <= 0 || nb < 1 || nb > kMaxB) return 0;
-  return 10 * kAlign + sizeof(DevScalars) + sizeof(double) * (5 * (size_t)nb * nb) +
+  return 11 * kAlign + sizeof(DevScalars) + sizeof(double) * (6 * (size_t)nb * nb) +
          sizeof(double) * (size_t)nb * n + sizeof(int32_t) * kMaxB;
 }
 
@@ -496,6 +499,7 @@ rbrp_status rbrp_block_cpqr(const double* Vt, int64_t n, int32_t nb, int64_t ldv
   double* R2 = cv.take<double>((size_t)nb * nb);
   double* Mc = cv.take<double>((size_t)nb * nb);
   double* Mc2 = cv.take<double>((size_t)nb * nb);
+  double* Rinv = cv.take<double>((size_t)nb * nb);
   double* Qtmp = cv.take<double>((size_t)nb * n);
   int32_t* piv2 = cv.take<int32_t>(kMaxB);
   hipStream_t s = (hipStream_t)stream;
@@ -506,7 +510,7 @@ rbrp_status rbrp_block_cpqr(const double* Vt, int64_t n, int32_t nb, int64_t ldv
                                 nullptr, s));
   RBRP_HIP(launch_cpqr_piv(G, nb, nb, nullptr, tau_b, nullptr, piv, Rraw, nb, R, nb,
                            &sc->bprime, &sc->tail1, nullptr, s));
-  RBRP_HIP(launch_qsolve(Vt, ldv, piv, R, nb, &sc->bprime, nb, n, Qtmp, n, s));
+  RBRP_HIP(launch_qsolve(Vt, ldv, piv, R, nb, &sc->bprime, nb, n, Qtmp, n, Rinv, s));
   RBRP_HIP(launch_gemm_nt_small(nb, nb, n, 1.0, Qtmp, n, Qtmp, n, 0.0, G, nb, nullptr,
                                 nullptr, s));
   RBRP_HIP(launch_ortho_first_order(G, nb, &sc->bprime, nb, Mc2, nb, &sc->need_exact, s));

@@ -134,7 +134,7 @@ hipError_t launch_cpqr_piv(const double* G, int64_t ldg, int32_t nb, const int32
 // rows b'..nb_host-1 zero.
 hipError_t launch_qsolve(const double* Vt, int64_t ldv, const int32_t* piv, const double* Rp,
                          int64_t ldp, const int32_t* bprime, int32_t nb_host, int64_t ncols,
-                         double* Qt, int64_t ldq, hipStream_t s);
+                         double* Qt, int64_t ldq, double* Rinv_ws, hipStream_t s);
 
 // First-order Cholesky-QR factor M2 = R2^{-T} of G2 = I + E when max|E| <=
 // 1e-8 (need_exact = 0), else need_exact = 1 and M2 is left to the exact path.
@@ -143,6 +143,12 @@ hipError_t launch_ortho_first_order(const double* G2, int64_t ldg, const int32_t
                                     int32_t* need_exact, hipStream_t s);
 
 // C = alpha A B^T + beta C for small M, N and long K (split over waves).
+// C[M x N] = alpha A^T B + beta C with A stored K x M and B K x N (small M).
+// B's row k is B[brow[k]] when brow is given; K <= *k_dev when k_dev is given.
+hipError_t launch_gemm_tn_small(int64_t M, int64_t N, int64_t K, double alpha,
+                                const double* A, int64_t lda, const double* B, int64_t ldb,
+                                double beta, double* C, int64_t ldc, hipStream_t s,
+                                const int32_t* brow = nullptr, const int32_t* k_dev = nullptr);
 hipError_t launch_gemm_nt_small(int64_t M, int64_t N, int64_t K, double alpha,
                                 const double* A, int64_t lda, const double* B, int64_t ldb,
                                 double beta, double* C, int64_t ldc, const int32_t* m_dev,
