@@ -323,8 +323,10 @@ __device__ __forceinline__ void wg_sample(
 }
 
 // LDS state of the pivoted Cholesky (besides the nb x (nb+1) Schur buffer).
+constexpr int kPivKB = 16;   // pivot rows per delayed Schur-complement update
+
 struct PivShared {
-  double rrow[kMaxB];
+  double rblk[kPivKB][kMaxB];  // pivot rows of the current block of steps
   int32_t chosen[kMaxB];
   int32_t pivs[kMaxB];
   double wbest[2], wtail[2];
@@ -335,11 +337,14 @@ constexpr int kPivThreads = 256;
 
 // Pivoted Cholesky of the block's Gram matrix for the filter (kPivThreads
 // threads).  The Schur complement S (nb x nb, row stride nb + 1) lives in
-// LDS (Ss); thread j < nb keeps the diagonal entry S[j][j] in a register.
-// Per pivot step: a fixed-order argmax / sum over the diagonal (waves 0-1),
-// the pivot row of R written to LDS, and the rank-one update of S spread
-// over all threads (each thread updates nb*nb/256 independent entries, so
-// LDS latency overlaps).  Outputs: pivots (kept ones first, the rest in
+// LDS (Ss); thread j < nb keeps the exact diagonal entry S[j][j] in a
+// register and downdates it at every step.  Per pivot step: a fixed-order
+// argmax / sum over the diagonal (waves 0-1), then the pivot row of R from
+// the pivot's row of S minus the contributions of the earlier pivots of the
+// current group of kPivKB steps; S itself is brought up to date once per
+// group by a rank-kPivKB update over its remaining rows and columns (the
+// delayed update of blocked pivoted QR / Cholesky), so each step costs two
+// barriers and O(kPivKB) LDS reads per thread.  Outputs: pivots (kept ones first, the rest in
 // increasing order), b', the pivot rows of R with unpermuted columns (Rraw),
 // R11 in pivoted order (Rp, nb x nb, zero outside the leading b' x b' upper
 // triangle), ||V||_F^2 and the rank-guard flag.  Ends past a barrier.
@@ -350,7 +355,6 @@ __device__ __forceinline__ void wg_piv_chol(
     double* __restrict__ Rraw, int64_t ldr, double* __restrict__ Rp, int64_t ldp,
     int32_t* __restrict__ bprime_out, double* __restrict__ tail1_out,
     int32_t* __restrict__ stop_out, double* Ss, PivShared& sh) {
-  double* rrow = sh.rrow;
   int32_t* chosen_s = sh.chosen;
   int32_t* pivs = sh.pivs;
   double* wbest = sh.wbest;
@@ -372,12 +376,23 @@ __device__ __forceinline__ void wg_piv_chol(
   bool chosen = !owner;
   double thr = 0.0;
   int bp = 0;
-  // update assignment: column c = tid % nb (or none), rows r0, r0 + rstep, ...
-  const int nb2 = nb > 0 ? nb : 1;
-  const int ucol = tid % nb2;
-  const int urow0 = tid / nb2;
-  const int rstep = kPivThreads / nb2;
   for (int p = 0; p <= nb; ++p) {
+    const int qb = p % kPivKB;
+    if (qb == 0 && p > 0) {
+      // delayed update of the remaining Schur complement by the last group
+      for (int e = tid; e < nb * nb; e += kPivThreads) {
+        const int i = e / nb, c = e - i * nb;
+        if (chosen_s[i] || chosen_s[c]) continue;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < kPivKB; q += 2) {
+          s0 += sh.rblk[q][i] * sh.rblk[q][c];
+          s1 += sh.rblk[q + 1][i] * sh.rblk[q + 1][c];
+        }
+        Ss[i * ld + c] -= s0 + s1;
+      }
+      __syncthreads();
+    }
     if (wv < 2) {
       double best = chosen ? -INFINITY : dj;
       int bi = chosen ? -1 : tid;
@@ -431,8 +446,12 @@ __device__ __forceinline__ void wg_piv_chol(
       double v;
       if (tid == jp) v = r;
       else if (chosen) v = 0.0;
-      else v = Ss[jp * ld + tid] / r;
-      rrow[tid] = v;
+      else {
+        double a = Ss[jp * ld + tid];
+        for (int q = 0; q < qb; ++q) a -= sh.rblk[q][jp] * sh.rblk[q][tid];
+        v = a / r;
+      }
+      sh.rblk[qb][tid] = v;
       Rraw[(int64_t)p * ldr + tid] = v;
       if (tid == jp) {
         chosen = true;
@@ -440,15 +459,6 @@ __device__ __forceinline__ void wg_piv_chol(
         pivs[p] = jp;
       }
       dj -= v * v;
-    }
-    __syncthreads();
-    // rank-one update of the remaining Schur complement
-    if (urow0 < rstep && tid < rstep * nb) {
-      const double rc = rrow[ucol];
-      if (rc != 0.0) {
-#pragma unroll 8
-        for (int i = urow0; i < nb; i += rstep) Ss[i * ld + ucol] -= rrow[i] * rc;
-      }
     }
     __syncthreads();
   }
