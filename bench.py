@@ -263,10 +263,13 @@ def main():
 
     def run_form(precision, steps, warmup):
         """Time `steps` decompositions in one precision form; returns the
-        per-step results, the wall time and the last step's FP64 error."""
-        def step(seed):
+        per-step results, the wall time, the last step's FP64 error and the
+        phase times of one extra untimed step.  Inside the timed loop only
+        the deflation launches are bracketed by HIP events (their durations
+        give the roofline figures)."""
+        def step(seed, profile="deflate"):
             return rb.rbrp_id(Xg, cfg["eps"], cfg["b"], seed, workspace=ws, out_S=S_buf,
-                              out_W=W_buf, precision=precision, profile=True)
+                              out_W=W_buf, precision=precision, profile=profile)
         for i in range(warmup):
             step(1000 + i)
             print(f"[bench] {precision} warmup {i + 1}/{warmup} done", file=sys.stderr,
@@ -287,7 +290,10 @@ def main():
         E = X64 - last.W @ X64[last.S]
         err = (torch.linalg.norm(E) / torch.linalg.norm(X64)).item()
         del E, X64
-        return results, total, err
+        phased = step(0, profile=True)
+        phases = {key: round(phased.profile[key], 4)
+                  for key in ("ms_init", "ms_select", "ms_filter", "ms_deflate", "ms_interp")}
+        return results, total, err, phases
 
     def deflation_roofline(results, dtype, s_r):
         flops = sum(r.profile["deflate_flops"] for r in results)
@@ -313,7 +319,7 @@ def main():
                     mfma=mfma, hbm=hbm)
 
     main_prec = "native"
-    results, total, err_last = run_form(main_prec, args.steps, args.warmup)
+    results, total, err_last, phases = run_form(main_prec, args.steps, args.warmup)
     errs = [err_last] + [r.resid_tracked for r in results]
     accurate = all(e <= cfg["eps"] * (1 + 1e-6) for e in errs)
     ms_per_step = 1e3 * total / args.steps
@@ -323,8 +329,6 @@ def main():
     roofline = deflation_roofline(results, dtype, s_r)
     roofline["traffic"] = _traffic(args.workload)
     roofline["kernel"] = "k_deflate (P = R Q', R -= P Q'^T, row norms)"
-    phases = {key: round(statistics.mean(r.profile[key] for r in results), 4)
-              for key in ("ms_init", "ms_select", "ms_filter", "ms_deflate", "ms_interp")}
     ks = [r.k for r in results]
     line = {
         "metric": METRIC, "value": value, "unit": "rows/s", "n_gpus": 1,
@@ -340,10 +344,10 @@ def main():
         "max_tracked_residual": max(r.resid_tracked for r in results),
         "k_median": statistics.median(ks), "k_range": [min(ks), max(ks)],
         "blocks_median": statistics.median(r.blocks for r in results),
-        "phases_ms_mean": phases,
+        "phases_ms": phases,
     }
     if dtype == "f32" and not args.no_bf16:
-        res16, tot16, err16 = run_form("bf16", args.steps, 1)
+        res16, tot16, err16, phases16 = run_form("bf16", args.steps, 1)
         errs16 = [err16] + [r.resid_tracked for r in res16]
         v16 = m * args.steps / tot16
         rf16 = deflation_roofline(res16, "bf16", 4)
@@ -356,9 +360,7 @@ def main():
             "blocks_split_median": statistics.median(r.blocks_split for r in res16),
             "theta": 25 * cfg["eps"],
             "deflation_roofline": rf16,
-            "phases_ms_mean": {key: round(statistics.mean(r.profile[key] for r in res16), 4)
-                               for key in ("ms_init", "ms_select", "ms_filter",
-                                           "ms_deflate", "ms_interp")},
+            "phases_ms": phases16,
         }
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)

@@ -69,7 +69,8 @@ typedef struct {
   int32_t w_refine;    /* refinement steps of the W solve; < 0 -> 1              */
   double theta;        /* BF16 mode: split/plain switch; <= 0 -> 25 * eps        */
   int32_t profile;     /* 1: time the phases with HIP events on ``stream`` and
-                          report them in rbrp_stats                             */
+                          report them in rbrp_stats; 2: time only the
+                          deflation launches (ms_deflate, deflate_launches)    */
   int32_t reserved0;
 } rbrp_options;
 
@@ -79,7 +80,8 @@ typedef struct {
   int32_t blocks_split;    /* BF16 mode: blocks deflated with hi+lo products  */
   double resid_tracked;    /* sqrt(||d||_1 / ||d^(0)||_1) at exit             */
   double norm_x_fro;       /* ||X||_F                                         */
-  /* filled when rbrp_options.profile = 1 (milliseconds, HIP events) */
+  /* filled when rbrp_options.profile = 1 (milliseconds, HIP events; with
+     profile = 2 only ms_deflate, deflate_flops and deflate_launches) */
   double ms_init;          /* copy X -> residual, initial norms               */
   double ms_select;        /* weights, CDF and sampling, all blocks           */
   double ms_filter;        /* gather, projection, block CPQR, basis, all blocks */
@@ -110,7 +112,9 @@ size_t rbrp_workspace_size(rbrp_dtype dtype, int64_t m, int64_t n, int32_t b,
  *
  * X      [m x n], ld ldx, dtype F32 or F64; read only.
  * eps    relative Frobenius tolerance, 0 < eps < 1 (ignored if fixed_rank).
- * b      block size, 1 <= b <= 128.
+ * b      block size, 1 <= b <= 256.  Blocks with b' > 128 kept rows are
+ *        deflated in two launches (columns 1..128, then the rest); for
+ *        b > 128 the host also reads b' once per block before deflating.
  * seed   key of the Philox4x64-10 stream: candidate j of block t draws word 0
  *        of Philox(counter = (j, t, 0, 0), key = (seed, 0)).
  * opt    NULL for defaults.
@@ -177,7 +181,7 @@ rbrp_status rbrp_sample_block(const double* d, const uint8_t* excluded,
  * the first b' rows of R_V in pivoted column order (upper triangular part),
  * Qt [nb x n] FP64 ld ldq: first b' rows = orthonormal basis of the kept
  * columns (Q_V(:,1:b')^T, signs with positive diagonal of R_V).
- * bprime_host: b'.  1 <= nb <= 128.
+ * bprime_host: b'.  1 <= nb <= 256.
  */
 size_t rbrp_block_cpqr_workspace_size(int64_t n, int32_t nb);
 rbrp_status rbrp_block_cpqr(const double* Vt, int64_t n, int32_t nb,

@@ -190,7 +190,7 @@ def make_options(k_max=0, tau_b=0.0, fixed_rank=False, greedy=False, precision="
     o.precision = PRECISIONS[precision]
     o.theta = float(theta)
     o.w_refine = int(w_refine)
-    o.profile = int(bool(profile))
+    o.profile = 2 if profile == "deflate" else int(bool(profile))
     return o
 
 

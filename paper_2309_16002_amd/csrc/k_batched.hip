@@ -233,8 +233,8 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
     int32_t* __restrict__ k_out, int32_t* __restrict__ status_out,
     double* __restrict__ resid_out) {
   extern __shared__ __align__(16) unsigned char dsm[];
-  __shared__ SampleShared<kBatchMaxTiles> ssh;
-  __shared__ PivShared psh;
+  __shared__ SampleShared<kBatchMaxTiles, kBatchMaxB> ssh;
+  __shared__ PivShared<kBatchMaxB> psh;
   __shared__ double red[kBT], red2[kBT];
   __shared__ uint64_t wsum[4];
   __shared__ int32_t wpos[4];
@@ -360,7 +360,7 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
       const int64_t ntl = ceil_div(m, kScanTile);
       for (int64_t tl = 0; tl < ntl; ++tl)
         wg_weights_scan_tile(d, sel, nullptr, m, dmax, tl, cdf, tsum, tpos, wsum, wpos);
-      wg_sample<kBatchMaxTiles>(cdf, tsum, tpos, m, bt, prm.seed, (uint64_t)t, (uint64_t)id,
+      wg_sample<kBatchMaxTiles, kBatchMaxB>(cdf, tsum, tpos, m, bt, prm.seed, (uint64_t)t, (uint64_t)id,
                                 idx, &s_nt, nullptr, ssh);
       const int nt = s_nt;
       if (nt <= 0) break;
@@ -384,8 +384,8 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
       lds_gram(As, nt, n8, G, bmax);
       if (tid == 0) s_stop = 0;
       __syncthreads();
-      wg_piv_chol(G, bmax, nt, nullptr, tau_b, xs2, piv, Rraw, bmax, Rp, bmax, &s_bp, &s_tail1,
-                  &s_stop, Ss, psh);
+      wg_piv_chol<kBatchMaxB, false, true>(G, bmax, nt, nullptr, tau_b, xs2, piv, Rraw, bmax,
+                                           Rp, bmax, &s_bp, &s_tail1, &s_stop, Ss, psh);
       const int bp = s_bp;
       if (s_stop || bp <= 0) break;
       // ---- Q' = V(:, piv(1:b')) R11^{-1}, in place in As (one thread per

@@ -24,265 +24,171 @@
 
 #include <math.h>
 
+// Robust blockwise filtering of Alg. 2 (local CPQR + truncation, Remark 4.2)
+// and the formation of the new orthonormal basis rows Q'^T.
+//
+// The column-pivoted QR of the block V (n x nb) is computed through its Gram
+// matrix G = V^T V: greedy pivoting on the columns of V (pick the column with
+// the largest residual norm, project it out of the others, eq. qr_update) is
+// pivoted Cholesky on G, step for step in exact arithmetic -- the residual
+// norm^2 of column j after p steps is the diagonal of the Schur complement,
+// and the pivot row is R_V(p, :).  This is the QR / Cholesky correspondence
+// the paper uses to relate random pivoting to RPCholesky.  One workgroup
+// runs the nb sequential pivot steps (wg_piv_chol); G sits in LDS up to
+// nb = 128 and is updated in place in global memory (L2) beyond that.  The
+// n-long columns of V are never touched here.
+//
+// Truncation: tail_i = ||R_V(i:nb, i:nb)||_F^2 is the sum of the remaining
+// Schur diagonal before pivot i, and b' is the last i with
+// tail_i >= tau_b tail_1 (1 - 4 nb 2^-53); tails are non-increasing, so the
+// pivoting stops at the first i below the threshold.
+//
+// Q' = V(:, piv(1:b')) R11^{-1}: R11^{-1} by a blocked triangular inverse
+// (FP64 MFMA on 16 x 16 blocks) and one MFMA product over all n columns.  A
+// second pass on the result (projection against the basis + Cholesky QR,
+// first order when the Gram matrix is within 1e-8 of the identity, exact
+// otherwise) restores orthonormality to working precision.
+#include "rbrp_wg.h"
+
+#include <math.h>
+
 namespace rbrp {
 
-// One thread per column j of the block (nb <= 128, one or two waves).  Thread
-// j keeps the Schur-complement diagonal entry of its column in a register and
-// updates its own column of G (in LDS) at every pivot step, so the only
-// cross-thread traffic per step is the argmax/sum reduction and the pivot row.
-//
-// After pivoting, the kernel also forms M = R11^{-T} (b' x b', lower
-// triangular) by forward substitution over rows, in the same LDS array: the
-// strict upper triangle keeps R11, the strict lower triangle receives M and
-// the two diagonals live in separate vectors.  M is written scattered back to
-// the sampled order, Mout[p][piv[c]] = M[p][c], so that the new basis rows
-// are the plain product Q'^T = Mout V^T.
-__global__ __launch_bounds__(128) void k_cpqr_gram(
-    const double* __restrict__ G, int64_t ldg, int32_t nb_host,
-    const int32_t* __restrict__ nb_dev, double tau_b, int pivoted,
-    const double* __restrict__ xs2_rows, int32_t* __restrict__ piv,
-    double* __restrict__ Rraw, int64_t ldr, double* __restrict__ Rperm,
-    double* __restrict__ Mout, int64_t ldm, int32_t* __restrict__ bprime_out,
-    double* __restrict__ tail1_out, int32_t* __restrict__ stop_out,
-    const int32_t* __restrict__ run_flag) {
-  extern __shared__ double Gs[];
-  if (run_flag && *run_flag == 0) {
-    if (threadIdx.x == 0 && nb_dev) *bprime_out = *nb_dev;
-    return;
-  }
-  __shared__ double rrow[2][kMaxB];
-  __shared__ double rdiag[kMaxB];
-  __shared__ double mdiag[kMaxB];
-  __shared__ int32_t pivs[kMaxB];
-  __shared__ int32_t chosen_s[kMaxB];
-  __shared__ double wbest[2], wtail[2];
-  __shared__ int32_t wbi[2];
-  const int j = threadIdx.x;
-  const int lane = j & 63, wv = j >> 6;
-  const int nwave = blockDim.x >> 6;
-  int nb = nb_host;
-  if (nb_dev) nb = min(nb, *nb_dev);
-  const int ld = nb + 1;
-  const bool active = j < nb;
-  for (int e = j; e < nb * nb; e += blockDim.x) {
-    const int r = e / nb, c = e - r * nb;
-    Gs[r * ld + c] = G[(int64_t)r * ldg + c];
-  }
-  __syncthreads();
-  double dj = active ? Gs[j * ld + j] : 0.0;
-  bool chosen = !active;
-  double thr = 0.0;
-  int bp = 0;
-  for (int p = 0; p <= nb; ++p) {
-    double best = chosen ? -INFINITY : dj;
-    int bi = chosen ? -1 : j;
-    double tail = chosen ? 0.0 : fmax(dj, 0.0);
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ob = __shfl_xor(best, off, kWave);
-      const int oi = __shfl_xor(bi, off, kWave);
-      tail += __shfl_xor(tail, off, kWave);
-      if (oi >= 0 && (bi < 0 || ob > best || (ob == best && oi < bi))) {
-        best = ob;
-        bi = oi;
-      }
-    }
-    if (nwave > 1) {
-      if (lane == 0) {
-        wbest[wv] = best;
-        wbi[wv] = bi;
-        wtail[wv] = tail;
-      }
-      __syncthreads();
-      best = wbest[0];
-      bi = wbi[0];
-      tail = wtail[0] + wtail[1];
-      if (wbi[1] >= 0 && (bi < 0 || wbest[1] > best || (wbest[1] == best && wbi[1] < bi))) {
-        best = wbest[1];
-        bi = wbi[1];
-      }
-    }
-    // every thread now holds the same best / bi / tail
-    bool done = false;
-    if (p == 0) {
-      if (tail1_out && j == 0) *tail1_out = tail;
-      thr = tau_b * tail * (1.0 - 4.0 * nb * 1.1102230246251565e-16);
-      if (xs2_rows) {
-        double xs2 = 0.0;
-        for (int q = 0; q < nb; ++q) xs2 += xs2_rows[q];
-        if (!(tail > 1e-26 * xs2)) {
-          done = true;
-          if (stop_out && j == 0) *stop_out = 1;
-        }
-      }
-    }
-    int jp = bi;
-    double g = best;
-    if (!pivoted && p < nb) {
-      jp = p;
-      g = Gs[p * ld + p];
-    }
-    if (p == nb || jp < 0 || !(g > 0.0)) done = true;
-    if (pivoted && p > 0 && tail < thr) done = true;
-    if (done) {
-      bp = p;
-      break;
-    }
-    const double r = sqrt(g);
-    const int buf = p & 1;
-    if (active) {
-      double v;
-      if (j == jp) v = r;
-      else if (chosen) v = 0.0;
-      else v = Gs[jp * ld + j] / r;
-      rrow[buf][j] = v;
-      Rraw[(int64_t)p * ldr + j] = v;
-    }
-    if (j == jp) chosen = true;
-    if (j == 0) pivs[p] = jp;
-    __syncthreads();
-    if (active) {
-      // G[:, j] -= rrow * rrow[j]; the pivot row and chosen columns end at zero
-      const double rj = rrow[buf][j];
-      if (rj != 0.0)
-        for (int i = 0; i < nb; ++i) Gs[i * ld + j] -= rrow[buf][i] * rj;
-      dj = Gs[j * ld + j];
-    }
-    __syncthreads();
-  }
-  if (active) chosen_s[j] = chosen ? 1 : 0;
-  __syncthreads();
-  if (j == 0) {
-    int q = bp;
-    for (int c = 0; c < nb; ++c)
-      if (!chosen_s[c]) pivs[q++] = c;
-    *bprime_out = bp;
-  }
-  __syncthreads();
-  if (active) piv[j] = pivs[j];
-  if (Rperm) {
-    for (int e = j; e < nb * nb; e += blockDim.x) {
-      const int a = e / nb, c = e - a * nb;
-      Rperm[(int64_t)a * nb + c] = (a < bp && c >= a) ? Rraw[(int64_t)a * ldr + pivs[c]] : 0.0;
-    }
-  }
-  if (!Mout) return;
-  // R11[a][c] = Rraw[a][piv[c]] for a <= c < bp: strict upper part into Gs,
-  // diagonal into rdiag
-  __syncthreads();
-  for (int e = j; e < bp * bp; e += blockDim.x) {
-    const int a = e / bp, c = e - a * bp;
-    if (c > a) Gs[a * ld + c] = Rraw[(int64_t)a * ldr + pivs[c]];
-    else if (c == a) rdiag[a] = Rraw[(int64_t)a * ldr + pivs[a]];
-  }
-  __syncthreads();
-  // M = R11^{-T}: M[p][c] = (delta_pc - sum_{c <= q < p} R11[q][p] M[q][c]) / R11[p][p]
-  for (int p = 0; p < bp; ++p) {
-    if (j <= p && j < bp) {
-      double v = (j == p) ? 1.0 : 0.0;
-      for (int q = j; q < p; ++q) {
-        const double mq = (q == j) ? mdiag[j] : Gs[q * ld + j];
-        v -= Gs[q * ld + p] * mq;
-      }
-      v /= rdiag[p];
-      if (j == p) mdiag[p] = v;
-      else Gs[p * ld + j] = v;
-    }
-    __syncthreads();
-  }
-  // scatter to the sampled order: Mout[p][pivs[c]] = M[p][c]; the whole
-  // nb_host x nb_host block is cleared first so that rows and columns past b'
-  // are exact zeros for the products that follow
-  for (int e = j; e < nb_host * nb_host; e += blockDim.x) {
-    const int a = e / nb_host, c = e - a * nb_host;
-    Mout[(int64_t)a * ldm + c] = 0.0;
-  }
-  __syncthreads();
-  for (int e = j; e < bp * bp; e += blockDim.x) {
-    const int a = e / bp, c = e - a * bp;
-    if (c <= a) Mout[(int64_t)a * ldm + pivs[c]] = (c == a) ? mdiag[a] : Gs[a * ld + c];
-  }
-}
+typedef double d4v_t __attribute__((ext_vector_type(4)));
 
-// ---------------------------------------------------------------------------
-// Pivoted Cholesky of the block's Gram matrix for the filter (256 threads).
-// The Schur complement S (nb x nb) lives in LDS; thread j < nb keeps the
-// diagonal entry S[j][j] in a register.  Per pivot step: a fixed-order
-// argmax / sum over the diagonal (waves 0-1), the pivot row of R written to
-// LDS, and the rank-one update of S spread over all 256 threads (each thread
-// updates nb*nb/256 independent entries, so LDS latency overlaps).
-// Outputs: pivots (kept ones first, the rest in increasing order), b', the
-// pivot rows of R with unpermuted columns (Rraw), R11 in pivoted order
-// (Rp, nb x nb, zero outside the leading b' x b' upper triangle), ||V||_F^2
-// and the rank-guard flag.
+// Filter: pivoted Cholesky of G (nb <= NBMAX), see wg_piv_chol.  GS: G is the
+// Schur complement itself (global memory, overwritten); otherwise it is
+// copied into dynamic LDS (nb (nb + 1) doubles).
+template <int NBMAX, bool GS>
 __global__ __launch_bounds__(kPivThreads) void k_cpqr_piv(
-    const double* __restrict__ G, int64_t ldg, int32_t nb_host,
+    double* __restrict__ G, int64_t ldg, int32_t nb_host,
     const int32_t* __restrict__ nb_dev, double tau_b,
     const double* __restrict__ xs2_rows, int32_t* __restrict__ piv,
     double* __restrict__ Rraw, int64_t ldr, double* __restrict__ Rp, int64_t ldp,
     int32_t* __restrict__ bprime_out, double* __restrict__ tail1_out,
     int32_t* __restrict__ stop_out) {
   extern __shared__ double Ss[];
-  __shared__ PivShared sh;
-  wg_piv_chol(G, ldg, nb_host, nb_dev, tau_b, xs2_rows, piv, Rraw, ldr, Rp, ldp, bprime_out,
-              tail1_out, stop_out, Ss, sh);
+  __shared__ PivShared<NBMAX> sh;
+  wg_piv_chol<NBMAX, GS, true>(G, ldg, nb_host, nb_dev, tau_b, xs2_rows, piv, Rraw, ldr, Rp,
+                               ldp, bprime_out, tail1_out, stop_out, GS ? G : Ss, sh);
 }
 
-// Q' = V(:, piv(1:b')) R11^{-1} (the orthonormal basis of the kept columns),
-// as rows of Qtmp: first R11^{-1} by back substitution in one workgroup
-// (thread j < b' solves column j; R11 and the inverse live in LDS as packed
-// upper triangles), then
-// Qtmp = (R11^{-1})^T-weighted sums of the pivoted rows of V^T on MFMA
-// (k_gemm_tn16: 16 x 16 output tiles over all columns).  Rows b'..nb_host-1
-// of Qtmp come out zero (R11^{-1} is zero outside its leading b' x b' block).
-// Upper triangles packed row by row: element (i, j), i <= j < nb, at
-// i nb - i (i - 1) / 2 + (j - i).
-__device__ __forceinline__ int tri_off(int i, int j, int nb) {
-  return i * nb - (i * (i - 1)) / 2 + (j - i);
+// Exact reorthogonalisation factor: Cholesky in natural order of the Gram
+// matrix of the new basis rows (b' = *nb_dev), R2 into Rp.  Runs only when
+// *run_flag != 0; otherwise reports b' steps done.
+template <int NBMAX, bool GS>
+__global__ __launch_bounds__(kPivThreads) void k_chol_reorth(
+    double* __restrict__ G, int64_t ldg, int32_t nb_host, const int32_t* __restrict__ nb_dev,
+    int32_t* __restrict__ piv2, double* __restrict__ Rraw, int64_t ldr,
+    double* __restrict__ Rp, int64_t ldp, int32_t* __restrict__ steps_out,
+    const int32_t* __restrict__ run_flag) {
+  if (*run_flag == 0) {
+    if (threadIdx.x == 0) *steps_out = *nb_dev;
+    return;
+  }
+  extern __shared__ double Ss[];
+  __shared__ PivShared<NBMAX> sh;
+  wg_piv_chol<NBMAX, GS, false>(G, ldg, nb_host, nb_dev, 0.0, nullptr, piv2, Rraw, ldr, Rp,
+                                ldp, steps_out, nullptr, nullptr, GS ? G : Ss, sh);
 }
 
-__global__ __launch_bounds__(256) void k_tri_inv_upper(const double* __restrict__ Rp,
-                                                       int64_t ldp,
-                                                       const int32_t* __restrict__ bprime,
-                                                       int32_t nb_host,
-                                                       double* __restrict__ Rinv,
-                                                       int64_t ldi) {
-  // R11 and its inverse, upper triangles packed in LDS (2 x nb (nb + 1) / 2)
-  extern __shared__ double tri[];
-  const int bp = *bprime;
-  const int nb = bp;
-  double* Rs = tri;
-  double* Xs = tri + (nb * (nb + 1)) / 2;
-  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-    const int i = e / nb, c = e - i * nb;
-    if (c >= i) Rs[tri_off(i, c, nb)] = Rp[(int64_t)i * ldp + c];
+// X = R^{-1} for the upper triangular R (b' x b', b' = *bcount <= 256,
+// row-major, stride ldr; entries past b' are read as zero), by 16 x 16
+// blocks in one workgroup of 256 threads:
+//   1. diagonal blocks: thread (k, j) forms column j of R_kk^{-1} by back
+//      substitution;
+//   2. off-diagonal blocks by increasing distance d = j - i from the
+//      diagonal, X_ij = -X_ii sum_{l=i+1..j} R_il X_lj, one wave per block
+//      and the products on FP64 MFMA (16x16x4: the accumulator of one 16 x 16
+//      product is already laid out as the B operand of the next).
+// Indices >= b' are padded with the identity, so the padded inverse is block
+// diagonal and its leading b' x b' part is R^{-1}.  Output (nb_host x
+// nb_host, stride ldx): X, or X^T with trans, there and zero elsewhere.
+// With run_flag the kernel does nothing unless *run_flag != 0.
+__global__ __launch_bounds__(256) void k_tri_inv_blocked(
+    const double* __restrict__ R, int64_t ldr, const int32_t* __restrict__ bcount,
+    int32_t nb_host, double* __restrict__ X, int64_t ldx, int trans,
+    const int32_t* __restrict__ run_flag) {
+  if (run_flag && *run_flag == 0) return;
+  __shared__ double Bd[16][16][17];  // diagonal blocks of R, then their inverses
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int l16 = lane & 15, lhi = lane >> 4;
+  const int bp = min(*bcount, nb_host);
+  const int nbk = (bp + 15) >> 4;
+  auto xoff = [&](int r, int c) -> int64_t {
+    return trans ? (int64_t)c * ldx + r : (int64_t)r * ldx + c;
+  };
+  for (int e = tid; e < nb_host * nb_host; e += 256) {
+    const int r = e / nb_host, c = e - r * nb_host;
+    if (!((r >> 4) <= (c >> 4) && (c >> 4) < nbk)) X[xoff(r, c)] = 0.0;
+  }
+  for (int e = tid; e < nbk * 256; e += 256) {
+    const int k = e >> 8, r = (e >> 4) & 15, c = e & 15;
+    const int gr = 16 * k + r, gc = 16 * k + c;
+    double v;
+    if (gr < bp && gc < bp) v = c >= r ? R[(int64_t)gr * ldr + gc] : 0.0;
+    else v = r == c ? 1.0 : 0.0;
+    Bd[k][r][c] = v;
   }
   __syncthreads();
-  const int j = threadIdx.x;
-  if (j < bp) {
-    // column j: X[j][j] = 1 / R[j][j]; X[i][j] = -(sum_{p=i+1..j} R[i][p] X[p][j]) / R[i][i]
-    Xs[tri_off(j, j, nb)] = 1.0 / Rs[tri_off(j, j, nb)];
-    for (int i = j - 1; i >= 0; --i) {
-      const double* ri = Rs + tri_off(i, 0, nb);  // ri[p] = R[i][p] for p >= i
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      int p = i + 1;
-      for (; p + 3 <= j; p += 4) {
-        s0 += ri[p] * Xs[tri_off(p, j, nb)];
-        s1 += ri[p + 1] * Xs[tri_off(p + 1, j, nb)];
-        s2 += ri[p + 2] * Xs[tri_off(p + 2, j, nb)];
-        s3 += ri[p + 3] * Xs[tri_off(p + 3, j, nb)];
-      }
-      for (; p <= j; ++p) s0 += ri[p] * Xs[tri_off(p, j, nb)];
-      Xs[tri_off(i, j, nb)] = -((s0 + s1) + (s2 + s3)) / ri[i];
+  const int kd = tid >> 4, jd = tid & 15;
+  double x[16];
+  if (kd < nbk) {
+#pragma unroll
+    for (int i = 15; i >= 0; --i) {
+      double sacc = 0.0;
+#pragma unroll
+      for (int l = i + 1; l < 16; ++l) sacc += Bd[kd][i][l] * x[l];
+      const double num = (i == jd) ? 1.0 : -sacc;
+      x[i] = (i <= jd) ? num / Bd[kd][i][i] : 0.0;
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < nb_host * nb_host; e += blockDim.x) {
-    const int i = e / nb_host, c = e - i * nb_host;
-    Rinv[(int64_t)i * ldi + c] = (i < bp && c < bp && i <= c) ? Xs[tri_off(i, c, nb)] : 0.0;
+  if (kd < nbk) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      Bd[kd][i][jd] = x[i];
+      const int gr = 16 * kd + i, gc = 16 * kd + jd;
+      if (gr < nb_host && gc < nb_host) X[xoff(gr, gc)] = (gr < bp && gc < bp) ? x[i] : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int dd = 1; dd < nbk; ++dd) {
+    for (int i = wv; i + dd < nbk; i += 4) {
+      const int j = i + dd;
+      d4v_t acc = {0.0, 0.0, 0.0, 0.0};
+      for (int l = i + 1; l <= j; ++l) {
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int kk = 4 * s4 + lhi;
+          const int ac = 16 * l + kk;
+          const double a = ac < bp ? R[(int64_t)(16 * i + l16) * ldr + ac] : 0.0;
+          const int bc = 16 * j + l16;
+          double b;
+          if (l == j) b = Bd[j][kk][l16];
+          else b = bc < bp ? X[xoff(16 * l + kk, bc)] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+      }
+      d4v_t out = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+        out = __builtin_amdgcn_mfma_f64_16x16x4f64(Bd[i][l16][4 * s4 + lhi], acc[s4], out, 0,
+                                                   0, 0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int gr = 16 * i + lhi + 4 * q, gc = 16 * j + l16;
+        if (gc < nb_host) X[xoff(gr, gc)] = gc < bp ? -out[q] : 0.0;
+      }
+    }
+    __syncthreads();
   }
 }
 
+// M2^T, the transpose of the first-order inverse Cholesky factor of
+// G2 = I + E when max|E| <= 1e-8 (R2^{-T} ~ I - strict_lower(E) - diag(E) / 2,
+// so M2^T is upper triangular); otherwise sets *need_exact and leaves M2^T to
+// the exact path.
 __global__ __launch_bounds__(256) void k_ortho_first_order(const double* __restrict__ G2,
                                                            int64_t ldg,
                                                            const int32_t* __restrict__ bprime,
@@ -311,30 +217,53 @@ __global__ __launch_bounds__(256) void k_ortho_first_order(const double* __restr
     const int a = e / nb_host, c = e - a * nb_host;
     double v = 0.0;
     if (a < bp && c < bp) {
-      const double E = G2[(int64_t)a * ldg + c] - (a == c ? 1.0 : 0.0);
-      if (a == c) v = 1.0 - 0.5 * E;
-      else if (c < a) v = -E;
+      // (M2^T)[a][c] = M2[c][a]: 1 - E[a][a] / 2 on the diagonal, -E[c][a] above
+      if (a == c) v = 1.0 - 0.5 * (G2[(int64_t)a * ldg + a] - 1.0);
+      else if (c > a) v = -G2[(int64_t)c * ldg + a];
     }
     M2[(int64_t)a * ldm + c] = v;
   }
 }
 
-hipError_t launch_cpqr_piv(const double* G, int64_t ldg, int32_t nb, const int32_t* nb_dev,
+static size_t chol_lds_bytes(int32_t nb) { return (size_t)nb * (nb + 1) * sizeof(double); }
+constexpr int kLdsCholMax = 128;   // largest nb whose Schur complement sits in LDS
+
+template <typename K>
+static hipError_t set_chol_lds(K kernel, bool* done) {
+  if (*done) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void*)kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)chol_lds_bytes(kLdsCholMax));
+  if (e == hipSuccess) *done = true;
+  return e;
+}
+
+hipError_t launch_cpqr_piv(double* G, int64_t ldg, int32_t nb, const int32_t* nb_dev,
                            double tau_b, const double* xs2_rows, int32_t* piv, double* Rraw,
                            int64_t ldr, double* Rp, int64_t ldp, int32_t* bprime_out,
                            double* tail1_out, int32_t* stop_out, hipStream_t s) {
   if (nb <= 0 || nb > kMaxB) return hipErrorInvalidValue;
-  static bool attr_set = false;
-  const size_t lds = (size_t)kMaxB * (kMaxB + 1) * sizeof(double);
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_cpqr_piv,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (nb <= kLdsCholMax) {
+    static bool attr = false;
+    hipError_t e = set_chol_lds(k_cpqr_piv<kLdsCholMax, false>, &attr);
     if (e != hipSuccess) return e;
-    attr_set = true;
+    hipLaunchKernelGGL((k_cpqr_piv<kLdsCholMax, false>), dim3(1), dim3(kPivThreads),
+                       chol_lds_bytes(nb), s, G, ldg, nb, nb_dev, tau_b, xs2_rows, piv, Rraw,
+                       ldr, Rp, ldp, bprime_out, tail1_out, stop_out);
+  } else {
+    hipLaunchKernelGGL((k_cpqr_piv<kMaxB, true>), dim3(1), dim3(kPivThreads), 0, s, G, ldg,
+                       nb, nb_dev, tau_b, xs2_rows, piv, Rraw, ldr, Rp, ldp, bprime_out,
+                       tail1_out, stop_out);
   }
-  hipLaunchKernelGGL(k_cpqr_piv, dim3(1), dim3(kPivThreads),
-                     (size_t)nb * (nb + 1) * sizeof(double), s, G, ldg, nb, nb_dev, tau_b,
-                     xs2_rows, piv, Rraw, ldr, Rp, ldp, bprime_out, tail1_out, stop_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_tri_inv(const double* R, int64_t ldr, const int32_t* bcount, int32_t nb_host,
+                          double* X, int64_t ldx, int trans, const int32_t* run_flag,
+                          hipStream_t s) {
+  if (nb_host <= 0 || nb_host > kMaxB) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_tri_inv_blocked, dim3(1), dim3(256), 0, s, R, ldr, bcount, nb_host, X,
+                     ldx, trans, run_flag);
   return hipGetLastError();
 }
 
@@ -342,19 +271,7 @@ hipError_t launch_qsolve(const double* Vt, int64_t ldv, const int32_t* piv, cons
                          int64_t ldp, const int32_t* bprime, int32_t nb_host, int64_t ncols,
                          double* Qt, int64_t ldq, double* Rinv_ws, hipStream_t s) {
   if (ncols <= 0) return hipSuccess;
-  if (nb_host <= 0 || nb_host > kMaxB) return hipErrorInvalidValue;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_tri_inv_upper,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(kMaxB * (kMaxB + 1) * sizeof(double)));
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  hipLaunchKernelGGL(k_tri_inv_upper, dim3(1), dim3(kMaxB < 256 ? 256 : kMaxB),
-                     (size_t)nb_host * (nb_host + 1) * sizeof(double), s, Rp, ldp, bprime,
-                     nb_host, Rinv_ws, (int64_t)nb_host);
-  hipError_t e = hipGetLastError();
+  hipError_t e = launch_tri_inv(Rp, ldp, bprime, nb_host, Rinv_ws, nb_host, 0, nullptr, s);
   if (e != hipSuccess) return e;
   return launch_gemm_tn_small(nb_host, ncols, nb_host, 1.0, Rinv_ws, nb_host, Vt, ldv, 0.0, Qt,
                               ldq, s, piv, bprime);
@@ -368,71 +285,40 @@ hipError_t launch_ortho_first_order(const double* G2, int64_t ldg, const int32_t
   return hipGetLastError();
 }
 
-size_t cpqr_lds_bytes(int32_t nb) { return (size_t)nb * (nb + 1) * sizeof(double); }
-
-hipError_t launch_cpqr_gram_ex(const double* G, int64_t ldg, int32_t nb,
-                               const int32_t* nb_dev, double tau_b, int pivoted,
-                               const double* xs2_rows, int32_t* piv,
-                               double* Rraw, int64_t ldr, double* Rperm, double* Mout,
-                               int64_t ldm, int32_t* bprime_out, double* tail1_out,
-                               int32_t* stop_out, hipStream_t s, const int32_t* run_flag) {
-  if (nb <= 0 || nb > kMaxB) return hipErrorInvalidValue;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_cpqr_gram,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)cpqr_lds_bytes(kMaxB));
+hipError_t launch_ortho_exact(double* G2, int64_t ldg, const int32_t* bprime, int32_t nb_host,
+                              int32_t* piv2, double* R2raw, double* R2, double* M2,
+                              int64_t ldm, int32_t* steps_out, const int32_t* need_exact,
+                              hipStream_t s) {
+  if (nb_host <= 0 || nb_host > kMaxB) return hipErrorInvalidValue;
+  if (nb_host <= kLdsCholMax) {
+    static bool attr = false;
+    hipError_t e = set_chol_lds(k_chol_reorth<kLdsCholMax, false>, &attr);
     if (e != hipSuccess) return e;
-    attr_set = true;
+    hipLaunchKernelGGL((k_chol_reorth<kLdsCholMax, false>), dim3(1), dim3(kPivThreads),
+                       chol_lds_bytes(nb_host), s, G2, ldg, nb_host, bprime, piv2, R2raw,
+                       (int64_t)nb_host, R2, (int64_t)nb_host, steps_out, need_exact);
+  } else {
+    hipLaunchKernelGGL((k_chol_reorth<kMaxB, true>), dim3(1), dim3(kPivThreads), 0, s, G2, ldg,
+                       nb_host, bprime, piv2, R2raw, (int64_t)nb_host, R2, (int64_t)nb_host,
+                       steps_out, need_exact);
   }
-  const int threads = nb <= 64 ? 64 : 128;
-  hipLaunchKernelGGL(k_cpqr_gram, dim3(1), dim3(threads), cpqr_lds_bytes(nb), s, G, ldg, nb,
-                     nb_dev, tau_b, pivoted, xs2_rows, piv, Rraw, ldr, Rperm, Mout, ldm,
-                     bprime_out, tail1_out, stop_out, run_flag);
-  return hipGetLastError();
-}
-
-// Row-wise forward substitution Qt[p,:] = (Vt[piv[p],:] - sum_{q<p}
-// R[q][piv[p]] Qt[q,:]) / R[p][piv[p]], one thread per column.  Works in
-// place (Vt == Qt with piv == NULL).
-__global__ __launch_bounds__(256) void k_qform(const double* Vt, int64_t ldv,
-                                               const int32_t* __restrict__ piv,
-                                               const double* __restrict__ R,
-                                               int64_t ldr,
-                                               const int32_t* __restrict__ bprime,
-                                               int64_t n, double* Qt, int64_t ldq) {
-  __shared__ double rc[kMaxB];
-  const int bp = *bprime;
-  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  for (int p = 0; p < bp; ++p) {
-    const int jp = piv ? piv[p] : p;
-    for (int q = threadIdx.x; q <= p; q += 256) rc[q] = R[(int64_t)q * ldr + jp];
-    __syncthreads();
-    if (c < n) {
-      double v = Vt[(int64_t)jp * ldv + c];
-      for (int q = 0; q < p; ++q) v -= rc[q] * Qt[(int64_t)q * ldq + c];
-      Qt[(int64_t)p * ldq + c] = v / rc[p];
-    }
-    __syncthreads();
-  }
-}
-
-hipError_t launch_qform(const double* Vt, int64_t ldv, const int32_t* piv,
-                        const double* R, int64_t ldr, const int32_t* bprime,
-                        int32_t bmax, int64_t n, double* Qt, int64_t ldq,
-                        hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_qform, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, Vt,
-                     ldv, piv, R, ldr, bprime, n, Qt, ldq);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // M2^T = R2^{-1}
+  return launch_tri_inv(R2, nb_host, steps_out, nb_host, M2, ldm, 0, need_exact, s);
 }
 
 __global__ void k_append(const int64_t* __restrict__ idx,
                          const int32_t* __restrict__ piv,
                          const int32_t* __restrict__ bprime, int64_t kS,
                          int32_t t, int64_t* __restrict__ S,
-                         int32_t* __restrict__ sel_block) {
+                         int32_t* __restrict__ sel_block, int32_t* __restrict__ bchunk) {
   const int p = threadIdx.x;
+  if (bchunk && p == 0) {
+    const int bp = *bprime;
+    bchunk[0] = min(bp, kDeflateMaxB);
+    bchunk[1] = max(bp - kDeflateMaxB, 0);
+  }
   if (p < *bprime) {
     const int64_t row = idx[piv[p]];
     S[kS + p] = row;
@@ -442,9 +328,9 @@ __global__ void k_append(const int64_t* __restrict__ idx,
 
 hipError_t launch_append(const int64_t* idx, const int32_t* piv,
                          const int32_t* bprime, int64_t kS, int32_t t,
-                         int64_t* S, int32_t* sel_block, hipStream_t s) {
+                         int64_t* S, int32_t* sel_block, int32_t* bchunk, hipStream_t s) {
   hipLaunchKernelGGL(k_append, dim3(1), dim3(kMaxB), 0, s, idx, piv, bprime, kS, t,
-                     S, sel_block);
+                     S, sel_block, bchunk);
   return hipGetLastError();
 }
 

@@ -101,6 +101,30 @@ __device__ __forceinline__ int slot_off(int tile, int ln, int q) {
 // b' tiles, is a compile-time constant of each instantiated body.
 constexpr int kDepth = 3;   // default prefetch depth (chunks of 16 columns)
 
+// Scheduling fence: keeps the loads issued for later chunks ahead of the
+// MFMAs that follow (the compiler's scheduler would otherwise sink them next
+// to their first use, leaving about one chunk in flight instead of DEPTH).
+// Holding DEPTH chunks really in flight costs registers, so a body is fenced
+// only when its estimated footprint (the R slice, the prefetch ring and the
+// P accumulators, in VGPRs) fits the 256 of two waves per SIMD and at most
+// four b' tiles are active (wider bodies need the registers for phase 2);
+// the others keep the compiler's schedule rather than spill.
+template <int MODE, int RT, int CT, int NB, int DEPTH>
+constexpr bool fence_fits() {
+  constexpr bool bf = (MODE == kModeBF16x3 || MODE == kModeBF16);
+  constexpr int s = (MODE == kModeF64) ? 2 : 1;
+  constexpr int r = RT * CT * 4 * s;
+  constexpr int ring = bf ? DEPTH * (2 * RT * 4 + NB * 4 * (MODE == kModeBF16x3 ? 2 : 1))
+                          : DEPTH * (RT * 4 * s + NB * 4 * s);
+  constexpr int pacc = RT * NB * 4 * s;
+  return NB <= 4 && r + ring + pacc <= 256;
+}
+
+template <bool ON>
+__device__ __forceinline__ void sched_fence() {
+  if constexpr (ON) __builtin_amdgcn_sched_barrier(0);
+}
+
 template <int MODE, int RT, int CT, int BT, int NB, int DEPTH>
 __device__ __forceinline__ void deflate_body(
     typename DT<MODE>::T* __restrict__ Rw, uint32_t ldr32, int64_t m, int nw, int w, int lane,
@@ -115,6 +139,7 @@ __device__ __forceinline__ void deflate_body(
   constexpr bool BF = (MODE == kModeBF16x3 || MODE == kModeBF16);
   constexpr bool SPLIT = (MODE == kModeBF16x3);
   constexpr int SLOT = RT * BT * kTileElems;
+  constexpr bool FENCE = fence_fits<MODE, RT, CT, NB, DEPTH>();
   const int l16 = lane & 15, lhi = lane >> 4;
 
   V Rreg[RT][CT];
@@ -145,6 +170,7 @@ __device__ __forceinline__ void deflate_body(
         for (int bt = 0; bt < NB; ++bt) fr[k][bt] = fb[(uint32_t)((k * BT + bt) * 64) + lane];
       }
     }
+    sched_fence<FENCE>();
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
       const int sl = ct % DEPTH;
@@ -161,6 +187,7 @@ __device__ __forceinline__ void deflate_body(
         for (int bt = 0; bt < NB; ++bt)
           fr[sl][bt] = fb[(uint32_t)(((ct + DEPTH) * BT + bt) * 64) + lane];
       }
+      sched_fence<FENCE>();
     }
   } else {
     constexpr int C2 = CT / 2;
@@ -180,6 +207,7 @@ __device__ __forceinline__ void deflate_body(
         }
       }
     }
+    sched_fence<FENCE>();
 #pragma unroll
     for (int c2 = 0; c2 < C2; ++c2) {
       const int sl = c2 % DEPTH;
@@ -216,6 +244,7 @@ __device__ __forceinline__ void deflate_body(
           if constexpr (SPLIT) frl[sl][bt] = fbl[o];
         }
       }
+      sched_fence<FENCE>();
     }
   }
 
@@ -314,6 +343,7 @@ __device__ __forceinline__ void deflate_body(
           for (int kb = 0; kb < NB; ++kb)
             fr[sl * PW + p][kb] = fa[(uint32_t)(((c0 + p + 2 * PW) * BT + kb) * 64) + lane];
         }
+      sched_fence<FENCE>();
 #pragma unroll
       for (int p = 0; p < PW; ++p) finish_chunk(c0 + p);
     }
@@ -369,6 +399,7 @@ __device__ __forceinline__ void deflate_body(
           if constexpr (SPLIT) frl[sl][ks] = fal[o];
         }
       }
+      sched_fence<FENCE>();
       finish_chunk(ct);
     }
   }
@@ -612,9 +643,10 @@ static hipError_t run_deflate(const DeflateCfg& c, int64_t grid, hipStream_t s,
                               void* L, int64_t ldl, int64_t kS, const int32_t* sel,
                               int32_t t, double* d, double* ps, double* pm) {
   typedef typename DT<MODE>::T T;
-  // FP32 panels of 16 column tiles keep all their R loads in flight (measured
-  // 5-9% faster than three chunks ahead); the other shapes are register-bound
-  constexpr int DP = (MODE == kModeF32 && CT == 16 && RT == 2) ? 8 : kDepth;
+  // FP32 panels of 16 column tiles keep four chunks in flight (with the
+  // scheduling fences, measured 8-16% faster than three); the other shapes
+  // are register-bound
+  constexpr int DP = (MODE == kModeF32 && CT == 16 && RT == 2) ? 4 : kDepth;
   const size_t slot = (size_t)RT * BT * kTileElems * sizeof(T);
   const size_t lds = c.nw * slot + (size_t)c.nw * 16 * RT * sizeof(double);
   static bool attr = false;

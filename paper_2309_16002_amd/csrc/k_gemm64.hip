@@ -12,6 +12,7 @@
 
 namespace rbrp {
 
+typedef double d2v __attribute__((ext_vector_type(2)));
 typedef double d4v __attribute__((ext_vector_type(4)));
 
 constexpr int GB_M = 64, GB_N = 64, GB_K = 32;
@@ -192,20 +193,21 @@ namespace rbrp {
 
 // C[M x N] = alpha A[M x K] B[N x K]^T + beta C for small M, N and long K
 // (the projections Q^T V and the Gram matrices of the block filter).  One
-// workgroup per 16 x 16 output tile; its four waves take interleaved 16-wide
+// workgroup per 16 x 16 output tile; its NW waves take interleaved 16-wide
 // K chunks straight from global memory into MFMA operands (no LDS staging,
-// no barriers in the K loop), and the four partial tiles are summed in LDS in
+// no barriers in the K loop), and the NW partial tiles are summed in LDS in
 // wave order.  Within a chunk, lane l loads the 4 consecutive k of row l%16
 // starting at 4(l/16); MFMA s then uses k = 4(l/16) + s as its K index for
 // both operands, which is a permutation of the chunk's K range.
-__global__ __launch_bounds__(256) void k_gemm_nt16(int64_t M, int64_t N, int64_t K,
-                                                   double alpha, const double* __restrict__ A,
-                                                   int64_t lda, const double* __restrict__ B,
-                                                   int64_t ldb, double beta,
-                                                   double* __restrict__ C, int64_t ldc,
-                                                   const int32_t* m_dev,
-                                                   const int32_t* n_dev) {
-  __shared__ double part[4][256];
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_gemm_nt16(int64_t M, int64_t N, int64_t K,
+                                                      double alpha,
+                                                      const double* __restrict__ A, int64_t lda,
+                                                      const double* __restrict__ B, int64_t ldb,
+                                                      double beta, double* __restrict__ C,
+                                                      int64_t ldc, const int32_t* m_dev,
+                                                      const int32_t* n_dev) {
+  __shared__ double part[NW][256];
   if (m_dev) M = min(M, (int64_t)*m_dev);
   if (n_dev) N = min(N, (int64_t)*n_dev);
   const int64_t i0 = (int64_t)blockIdx.y * 16, j0 = (int64_t)blockIdx.x * 16;
@@ -216,15 +218,80 @@ __global__ __launch_bounds__(256) void k_gemm_nt16(int64_t M, int64_t N, int64_t
   const double* ap = A + (va ? ia : 0) * lda;
   const double* bp = B + (vb ? jb : 0) * ldb;
   d4v acc = (d4v){0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
+  // groups of four 16-wide chunks per wave: every load of a group is issued
+  // before its MFMAs.  Chunk bases past K are clamped to the last chunk (K is
+  // a multiple of 16) and their products masked, so no load is conditional.
+  const int64_t kstep = 16 * NW;
+  const int64_t klast = K - 16;
+  const int koff = 4 * (lane >> 4);
+  for (int64_t k0 = 16 * w; k0 < K; k0 += 4 * kstep) {
+    d2v a[4][2], b[4][2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t kb = min(k0 + u * kstep, klast) + koff;
+      a[u][0] = *reinterpret_cast<const d2v*>(ap + kb);
+      a[u][1] = *reinterpret_cast<const d2v*>(ap + kb + 2);
+      b[u][0] = *reinterpret_cast<const d2v*>(bp + kb);
+      b[u][1] = *reinterpret_cast<const d2v*>(bp + kb + 2);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool live = k0 + u * kstep < K;
+      const bool la = live && va, lb = live && vb;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double x = la ? a[u][s >> 1][s & 1] : 0.0;
+        const double y = lb ? b[u][s >> 1][s & 1] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) part[w][lane * 4 + q] = acc[q];
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < 256) {
+    double s = part[0][t];
+#pragma unroll
+    for (int v = 1; v < NW; ++v) s += part[v][t];
+    const int ln = t >> 2, q = t & 3;
+    const int64_t row = i0 + (ln >> 4) + 4 * q, col = j0 + (ln & 15);
+    if (row < M && col < N) {
+      double v = alpha * s;
+      if (beta != 0.0) v += beta * C[row * ldc + col];
+      C[row * ldc + col] = v;
+    }
+  }
+}
+
+// Any K (rows of A and B need no padding): per-element loads with the K
+// tail masked, four waves.
+__global__ __launch_bounds__(256) void k_gemm_nt16_any(int64_t M, int64_t N, int64_t K,
+                                                       double alpha,
+                                                       const double* __restrict__ A,
+                                                       int64_t lda,
+                                                       const double* __restrict__ B,
+                                                       int64_t ldb, double beta,
+                                                       double* __restrict__ C, int64_t ldc) {
+  __shared__ double part[4][256];
+  const int64_t i0 = (int64_t)blockIdx.y * 16, j0 = (int64_t)blockIdx.x * 16;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t ia = i0 + (lane & 15), jb = j0 + (lane & 15);
+  const bool va = ia < M, vb = jb < N;
+  const double* ap = A + (va ? ia : 0) * lda;
+  const double* bp = B + (vb ? jb : 0) * ldb;
+  d4v acc = (d4v){0.0, 0.0, 0.0, 0.0};
   for (int64_t k0 = 16 * w; k0 < K; k0 += 64) {
     const int64_t kk = k0 + 4 * (lane >> 4);
     double a[4], b[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
+      const int64_t kc = min(kk + s, K - 1);
       const bool kin = kk + s < K;
-      a[s] = (va && kin) ? ap[kk + s] : 0.0;
-      b[s] = (vb && kin) ? bp[kk + s] : 0.0;
+      a[s] = ap[kc];
+      b[s] = bp[kc];
+      a[s] = (va && kin) ? a[s] : 0.0;
+      b[s] = (vb && kin) ? b[s] : 0.0;
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc, 0, 0, 0);
@@ -233,24 +300,35 @@ __global__ __launch_bounds__(256) void k_gemm_nt16(int64_t M, int64_t N, int64_t
   for (int q = 0; q < 4; ++q) part[w][lane * 4 + q] = acc[q];
   __syncthreads();
   const int t = threadIdx.x;
-  const double s = ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t];
+  const double sm = ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t];
   const int ln = t >> 2, q = t & 3;
   const int64_t row = i0 + (ln >> 4) + 4 * q, col = j0 + (ln & 15);
   if (row < M && col < N) {
-    double v = alpha * s;
+    double v = alpha * sm;
     if (beta != 0.0) v += beta * C[row * ldc + col];
     C[row * ldc + col] = v;
   }
 }
 
+// K a multiple of 16 (the padded row length) with 16-byte aligned rows: the
+// batched-load kernel, sixteen waves splitting K when K >= 512; otherwise the
+// per-element kernel.  Partial tiles are summed in wave order (deterministic).
 hipError_t launch_gemm_nt_small(int64_t M, int64_t N, int64_t K, double alpha,
                                 const double* A, int64_t lda, const double* B, int64_t ldb,
                                 double beta, double* C, int64_t ldc, const int32_t* m_dev,
                                 const int32_t* n_dev, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
   dim3 g((unsigned)ceil_div(N, 16), (unsigned)ceil_div(M, 16));
-  hipLaunchKernelGGL(k_gemm_nt16, g, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta,
-                     C, ldc, m_dev, n_dev);
+  if (K < 16 || K % 16 || lda % 2 || ldb % 2 || ((uintptr_t)A | (uintptr_t)B) % 16) {
+    if (m_dev || n_dev) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gemm_nt16_any, g, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb,
+                       beta, C, ldc);
+  } else if (K >= 512)
+    hipLaunchKernelGGL(k_gemm_nt16<16>, g, dim3(1024), 0, s, M, N, K, alpha, A, lda, B, ldb,
+                       beta, C, ldc, m_dev, n_dev);
+  else
+    hipLaunchKernelGGL(k_gemm_nt16<4>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb,
+                       beta, C, ldc, m_dev, n_dev);
   return hipGetLastError();
 }
 
@@ -263,6 +341,7 @@ hipError_t launch_gemm_nt_small(int64_t M, int64_t N, int64_t K, double alpha,
 // elements of a row of A or B per quarter-wave), and the partial tiles are
 // summed in LDS in wave order.  MFMA step s of a chunk uses K index
 // 4 s + l / 16 for both operands.
+template <bool GATHER>
 __global__ __launch_bounds__(256) void k_gemm_tn16(int64_t M, int64_t N, int64_t K,
                                                    double alpha, const double* __restrict__ A,
                                                    int64_t lda, const double* __restrict__ B,
@@ -277,19 +356,27 @@ __global__ __launch_bounds__(256) void k_gemm_tn16(int64_t M, int64_t N, int64_t
   const int64_t ia = i0 + (lane & 15), jb = j0 + (lane & 15);
   const bool va = ia < M, vb = jb < N;
   const int kq = lane >> 4;
+  const int64_t iac = va ? ia : 0, jbc = vb ? jb : 0;
   d4v acc = (d4v){0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
-  for (int64_t k0 = 16 * w; k0 < K; k0 += 64) {
-    double a[4], b[4];
+  // groups of two 16-deep chunks per wave, every load of a group issued before
+  // its MFMAs; k past K is clamped to K - 1 (always a valid row) and masked
+  for (int64_t k0 = 16 * w; k0 < K; k0 += 128) {
+    double a[8], b[8];
+    int64_t kr[8];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int64_t k = k0 + 4 * s + kq;
-      const bool kin = k < K;
-      a[s] = (va && kin) ? A[k * lda + ia] : 0.0;
-      b[s] = (vb && kin) ? B[(brow ? (int64_t)brow[k] : k) * ldb + jb] : 0.0;
+    for (int s = 0; s < 8; ++s) {
+      const int64_t k = min(k0 + 64 * (s >> 2) + 4 * (s & 3) + kq, K - 1);
+      kr[s] = GATHER ? (int64_t)brow[k] : k;
+      a[s] = A[k * lda + iac];
     }
 #pragma unroll
-    for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc, 0, 0, 0);
+    for (int s = 0; s < 8; ++s) b[s] = B[kr[s] * ldb + jbc];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const bool kin = k0 + 64 * (s >> 2) + 4 * (s & 3) + kq < K;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64((va && kin) ? a[s] : 0.0,
+                                                 (vb && kin) ? b[s] : 0.0, acc, 0, 0, 0);
+    }
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) part[w][lane * 4 + q] = acc[q];
@@ -311,8 +398,12 @@ hipError_t launch_gemm_tn_small(int64_t M, int64_t N, int64_t K, double alpha,
                                 const int32_t* brow, const int32_t* k_dev) {
   if (M <= 0 || N <= 0) return hipSuccess;
   dim3 g((unsigned)ceil_div(N, 16), (unsigned)ceil_div(M, 16));
-  hipLaunchKernelGGL(k_gemm_tn16, g, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, brow,
-                     k_dev, beta, C, ldc);
+  if (brow)
+    hipLaunchKernelGGL(k_gemm_tn16<true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb,
+                       brow, k_dev, beta, C, ldc);
+  else
+    hipLaunchKernelGGL(k_gemm_tn16<false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb,
+                       brow, k_dev, beta, C, ldc);
   return hipGetLastError();
 }
 
@@ -468,21 +559,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
       stash(s0, 0, kbeg);
       __syncthreads();
       int64_t t = 0;
+      // The scheduling barriers keep every MFMA of a step ahead of the wait
+      // for the registers it stashes, so that each fetch has two steps of
+      // MFMA work to arrive in.
       for (; t + 2 <= nt; t += 2) {
         // even step t: LDS 0, registers s1 = step t+1; s0 is free
         fetch(s0, kstep(t + 2));
         mma(0);
+        __builtin_amdgcn_sched_barrier(0);
         stash(s1, 1, kstep(t + 1));
         __syncthreads();
         // odd step t+1: LDS 1, registers s0 = step t+2; s1 is free
         fetch(s1, kstep(t + 3));
         mma(1);
+        __builtin_amdgcn_sched_barrier(0);
         stash(s0, 0, kstep(t + 2));
         __syncthreads();
       }
       if (t < nt) mma(0);  // nt odd: the last step sits in LDS 0
     }
 
+    // epilogue: all C-input loads first (clamped, unconditional), then the
+    // stores, so that the loads of a lane overlap instead of each waiting
+    // for the previous one
+    double cin[4][4][2];
+    if (beta != 0.0) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t gi = min(i0 + 64 * wy + 16 * a + (lane >> 4) + 4 * q, M - 1);
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            const int64_t gj = min(j0 + 32 * wx + 16 * b + (lane & 15), N - 1);
+            cin[a][q][b] = Cin ? (double)Cin[gi * ldcin + gj] : C[gi * ldc + gj];
+          }
+        }
+    }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -494,10 +607,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
           const int64_t gj = j0 + 32 * wx + 16 * b + (lane & 15);
           if (gj < N) {
             double v = alpha * acc[a][b][q];
-            if (beta != 0.0) {
-              if (Cin) v += beta * (double)Cin[gi * ldcin + gj];
-              else v += beta * C[gi * ldc + gj];
-            }
+            if (beta != 0.0) v += beta * cin[a][q][b];
             C[gi * ldc + gj] = v;
           }
         }

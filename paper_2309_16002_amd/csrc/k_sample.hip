@@ -53,8 +53,8 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample(
     const uint64_t* __restrict__ cdf_local, const uint64_t* __restrict__ tile_sum,
     const int32_t* __restrict__ tile_pos, int64_t m, int32_t b, uint64_t seed,
     uint64_t t, uint64_t ident, int64_t* __restrict__ idx, DevScalars* sc) {
-  __shared__ SampleShared<kMaxTiles> sh;
-  wg_sample<kMaxTiles>(cdf_local, tile_sum, tile_pos, m, b, seed, t, ident, idx, &sc->nt,
+  __shared__ SampleShared<kMaxTiles, kMaxB> sh;
+  wg_sample<kMaxTiles, kMaxB>(cdf_local, tile_sum, tile_pos, m, b, seed, t, ident, idx, &sc->nt,
                        &sc->npos, sh);
 }
 

@@ -33,6 +33,7 @@ struct Plan {
   rbrp_dtype dt;
   int64_t m, n, mr, ldr, k_max, ldl, ntiles, nparts;
   int32_t b;
+  int32_t bdef;      // columns of one deflation launch: min(b, kDeflateMaxB)
   int native_mode;   // deflation mode of the NATIVE precision
   bool bf16;
   bool r_f64;
@@ -90,6 +91,7 @@ bool make_plan(rbrp_dtype dt, int64_t m, int64_t n, int32_t b, const rbrp_option
   p->m = m;
   p->n = n;
   p->b = b;
+  p->bdef = b < kDeflateMaxB ? b : kDeflateMaxB;
   p->mr = round_up(m, kRowPad);
   p->ldr = deflate_pad_cols(n);
   if (p->ldr <= 0) return false;
@@ -133,8 +135,8 @@ size_t layout(const Plan& p, char* base, Work* w) {
   w->Rinv = cv.take<double>((size_t)p.b * p.b);
   w->Qtmp = cv.take<double>((size_t)p.b * p.ldr);
   w->Qt = cv.take<double>((size_t)p.k_max * p.ldr);
-  w->fragB1 = cv.take<char>(frag_bytes(mode, p.ldr, p.b));
-  w->fragA2 = cv.take<char>(frag_bytes(mode, p.ldr, p.b));
+  w->fragB1 = cv.take<char>(frag_bytes(mode, p.ldr, p.bdef));
+  w->fragA2 = cv.take<char>(frag_bytes(mode, p.ldr, p.bdef));
   w->L = cv.take<char>((size_t)p.m * p.ldl * rs);
   w->interp = cv.take<double>(interp_workspace_doubles(p.m, p.k_max));
   return cv.off + kAlign;
@@ -161,33 +163,43 @@ DevScalars* host_scalars() {
     }                                              \
   } while (0)
 
-// Phase timing with HIP events recorded on the caller's stream.
+// Phase timing with HIP events recorded on the caller's stream.  Events come
+// from a per-thread pool that is created once and reused by later calls.
+// level 1 times every phase; level 2 only the deflation launches (phase 3),
+// the least intrusive way to measure the dominant kernel inside a timed loop.
 struct Profiler {
-  bool on = false;
+  int level = 0;
   hipStream_t s = nullptr;
   struct Span { hipEvent_t a, b; int phase; };
-  Span spans[1100];
+  static constexpr int kMaxSpans = 1100;
+  Span spans[kMaxSpans];
   int n = 0;
-  hipEvent_t cur_a = nullptr;
-  int cur_phase = -1;
-  ~Profiler() {
-    for (int i = 0; i < n; ++i) {
-      hipEventDestroy(spans[i].a);
-      hipEventDestroy(spans[i].b);
+  bool open = false;
+  static hipEvent_t pool_event(int i) {
+    static thread_local std::vector<hipEvent_t> pool;
+    while ((int)pool.size() <= i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
     }
+    return pool[i];
   }
   void begin(int phase) {
-    if (!on || n >= 1100) return;
+    open = false;
+    if (level == 0 || n >= kMaxSpans || (level == 2 && phase != 3)) return;
     Span& sp = spans[n];
-    if (hipEventCreate(&sp.a) != hipSuccess) { on = false; return; }
-    if (hipEventCreate(&sp.b) != hipSuccess) { hipEventDestroy(sp.a); on = false; return; }
+    sp.a = pool_event(2 * n);
+    sp.b = pool_event(2 * n + 1);
+    if (!sp.a || !sp.b) { level = 0; return; }
     sp.phase = phase;
     hipEventRecord(sp.a, s);
+    open = true;
   }
   void end() {
-    if (!on || n >= 1100) return;
+    if (!open) return;
     hipEventRecord(spans[n].b, s);
     ++n;
+    open = false;
   }
   // phases: 0 init, 1 select, 2 filter, 3 deflate, 4 interp
   void collect(double* ms5, int* ndeflate) {
@@ -252,7 +264,7 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
   if (p.bf16 && dtype != RBRP_F32) return RBRP_E_UNSUPPORTED;
   const int mode_hi = p.bf16 ? kModeBF16x3 : p.native_mode;
   const int mode_lo = p.bf16 ? kModeBF16 : p.native_mode;
-  if (!deflate_supported(mode_hi, p.ldr, b) || !deflate_supported(mode_lo, p.ldr, b))
+  if (!deflate_supported(mode_hi, p.ldr, p.bdef) || !deflate_supported(mode_lo, p.ldr, p.bdef))
     return RBRP_E_UNSUPPORTED;
   Work w;
   const size_t need = layout(p, nullptr, &w);
@@ -271,7 +283,7 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
   rbrp_stats st;
   memset(&st, 0, sizeof(st));
   Profiler prof;
-  prof.on = o.profile != 0;
+  prof.level = (o.profile == 1 || o.profile == 2) ? o.profile : 0;
   prof.s = s;
   double flops = 0.0;
 
@@ -299,6 +311,24 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
   rbrp_status final_status = RBRP_OK;
   double sum_d = h->sum_d;
   const int def_rows = deflate_rows_per_wg(mode_hi, ldr);
+  auto select_block = [&](int32_t tt, int32_t bsz) -> hipError_t {
+    prof.begin(1);
+    hipError_t e;
+    if (o.greedy) {
+      e = launch_topb(w.d, w.sel_block, m, bsz, w.idx, w.sc, s);
+    } else {
+      e = launch_weights_scan(w.d, w.sel_block, nullptr, m, w.sc, w.cdf, w.tile_sum,
+                              w.tile_pos, s);
+      if (e == hipSuccess)
+        e = launch_sample(w.cdf, w.tile_sum, w.tile_pos, m, bsz, seed, (uint64_t)tt, 0, w.idx,
+                          w.sc, s);
+    }
+    if (e == hipSuccess) e = launch_gather_rows(X, dtype, n, ldx, w.idx, w.sc, bsz, w.Vt, ldr,
+                                                w.xs2, s);
+    prof.end();
+    return e;
+  };
+  bool preselected = false;
   while (true) {
     if (kS >= k_max) {
       if (!o.fixed_rank && sum_d > tau * D0) final_status = RBRP_E_CAPACITY;
@@ -307,20 +337,13 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     if (!o.fixed_rank && !(sum_d > tau * D0)) break;
     ++t;
     const int32_t bt = (int32_t)((int64_t)b < k_max - kS ? b : k_max - kS);
-    // sampling (or greedy top-b)
-    prof.begin(1);
-    if (o.greedy) {
-      RBRP_HIP(launch_topb(w.d, w.sel_block, m, bt, w.idx, w.sc, s));
-    } else {
-      RBRP_HIP(launch_weights_scan(w.d, w.sel_block, nullptr, m, w.sc, w.cdf, w.tile_sum,
-                                   w.tile_pos, s));
-      RBRP_HIP(launch_sample(w.cdf, w.tile_sum, w.tile_pos, m, bt, seed, (uint64_t)t, 0,
-                             w.idx, w.sc, s));
-    }
-    prof.end();
-    // V^T: sampled rows of X in FP64, projected twice against the basis
+    // sampling (or greedy top-b) and V^T, the sampled rows of X in FP64 --
+    // already queued behind the previous block's deflation when its size
+    // was certain
+    if (!preselected) RBRP_HIP(select_block(t, bt));
+    preselected = false;
+    // project twice against the basis
     prof.begin(2);
-    RBRP_HIP(launch_gather_rows(X, dtype, n, ldx, w.idx, w.sc, bt, w.Vt, ldr, w.xs2, s));
     if (kS > 0) {
       for (int pass = 0; pass < 2; ++pass) {
         RBRP_HIP(launch_gemm_nt_small(kS, bt, ldr, 1.0, w.Qt, ldr, w.Vt, ldr, 0.0, w.C, bt,
@@ -348,27 +371,48 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
                                   nullptr, nullptr, s));
     RBRP_HIP(launch_ortho_first_order(w.G, bt, &w.sc->bprime, bt, w.Mc2, bt,
                                       &w.sc->need_exact, s));
-    RBRP_HIP(launch_cpqr_gram_ex(w.G, bt, bt, &w.sc->bprime, 0.0, 0, nullptr, w.piv2, w.R2raw,
-                                 bt, nullptr, w.Mc2, bt, &w.sc->b2, nullptr, nullptr, s,
-                                 &w.sc->need_exact));
+    RBRP_HIP(launch_ortho_exact(w.G, bt, &w.sc->bprime, bt, w.piv2, w.R2raw, w.Mc, w.Mc2, bt,
+                                &w.sc->b2, &w.sc->need_exact, s));
     double* Qn = w.Qt + kS * ldr;
-    RBRP_HIP(launch_gemm_f64(0, 0, bt, ldr, bt, 1.0, w.Mc2, 0, bt, w.Qtmp, ldr, 0.0, Qn, ldr,
-                             nullptr, nullptr, 0, s));
-    RBRP_HIP(launch_append(w.idx, w.piv, &w.sc->bprime, kS, t, S, w.sel_block, s));
-    // deflation of the residual
+    RBRP_HIP(launch_gemm_tn_small(bt, ldr, bt, 1.0, w.Mc2, bt, w.Qtmp, ldr, 0.0, Qn, ldr, s,
+                                  nullptr, &w.sc->bprime));
+    RBRP_HIP(launch_append(w.idx, w.piv, &w.sc->bprime, kS, t, S, w.sel_block, w.sc->bchunk,
+                           s));
+    // deflation of the residual, in launches of at most kDeflateMaxB columns
     int mode = p.native_mode;
     if (p.bf16) {
       const double rho = sqrt(sum_d / D0);
       mode = rho > theta ? kModeBF16x3 : kModeBF16;
       if (mode == kModeBF16x3) st.blocks_split++;
     }
-    RBRP_HIP(launch_make_frags(Qn, ldr, &w.sc->bprime, ldr, b, mode, w.fragB1, w.fragA2, s));
+    int nchunk = 1;
+    if (b > kDeflateMaxB) {
+      rs = fetch(h, w.sc, s);
+      if (rs != RBRP_OK) return rs;
+      nchunk = h->bprime > kDeflateMaxB ? 2 : 1;
+    }
     prof.end();
-    prof.begin(3);
-    RBRP_HIP(launch_deflate(mode, w.R, p.mr, ldr, m, w.fragB1, w.fragA2, &w.sc->bprime, b,
-                            w.L, p.ldl, kS, w.sel_block, t, w.d, w.part_sum, w.part_max, s));
-    prof.end();
+    for (int c = 0; c < nchunk; ++c) {
+      const int32_t* bcnt = b > kDeflateMaxB ? &w.sc->bchunk[c] : &w.sc->bprime;
+      prof.begin(2);
+      RBRP_HIP(launch_make_frags(Qn + (int64_t)c * kDeflateMaxB * ldr, ldr, bcnt, ldr, p.bdef,
+                                 mode, w.fragB1, w.fragA2, s));
+      prof.end();
+      prof.begin(3);
+      RBRP_HIP(launch_deflate(mode, w.R, p.mr, ldr, m, w.fragB1, w.fragA2, bcnt, p.bdef, w.L,
+                              p.ldl, kS + (int64_t)c * kDeflateMaxB, w.sel_block, t, w.d,
+                              w.part_sum, w.part_max, s));
+      prof.end();
+    }
     RBRP_HIP(launch_reduce(w.part_sum, w.part_max, p.mr / def_rows, w.sc, 0, s));
+    // The next block's selection needs only d, S and the block size; when the
+    // size is certain (b rows, whatever b' turns out to be) it is queued now,
+    // so that the GPU samples while the host waits for this block's scalars.
+    // If the loop stops instead, the queued work is simply not used.
+    if (k_max - kS - bt >= b) {
+      RBRP_HIP(select_block(t + 1, b));
+      preselected = true;
+    }
     rs = fetch(h, w.sc, s);
     if (rs != RBRP_OK) return rs;
     const int bp = h->bprime;
@@ -388,7 +432,7 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     prof.end();
   }
   RBRP_HIP(hipStreamSynchronize(s));
-  if (prof.on) {
+  if (prof.level) {
     double ms5[5];
     int nd = 0;
     prof.collect(ms5, &nd);
@@ -514,11 +558,10 @@ rbrp_status rbrp_block_cpqr(const double* Vt, int64_t n, int32_t nb, int64_t ldv
   RBRP_HIP(launch_gemm_nt_small(nb, nb, n, 1.0, Qtmp, n, Qtmp, n, 0.0, G, nb, nullptr,
                                 nullptr, s));
   RBRP_HIP(launch_ortho_first_order(G, nb, &sc->bprime, nb, Mc2, nb, &sc->need_exact, s));
-  RBRP_HIP(launch_cpqr_gram_ex(G, nb, nb, &sc->bprime, 0.0, 0, nullptr, piv2, R2, nb,
-                               nullptr, Mc2, nb, &sc->b2, nullptr, nullptr, s,
-                               &sc->need_exact));
-  RBRP_HIP(launch_gemm_f64(0, 0, nb, n, nb, 1.0, Mc2, 0, nb, Qtmp, n, 0.0, Qt, ldq, nullptr,
-                           nullptr, 0, s));
+  RBRP_HIP(launch_ortho_exact(G, nb, &sc->bprime, nb, piv2, R2, Mc, Mc2, nb, &sc->b2,
+                              &sc->need_exact, s));
+  RBRP_HIP(launch_gemm_tn_small(nb, n, nb, 1.0, Mc2, nb, Qtmp, n, 0.0, Qt, ldq, s, nullptr,
+                                &sc->bprime));
   rbrp_status rs = fetch(h, sc, s);
   if (rs != RBRP_OK) return rs;
   *bprime_host = h->bprime;

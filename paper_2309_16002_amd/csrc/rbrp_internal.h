@@ -17,7 +17,8 @@ constexpr int kRowPad = 64;
 // Rows per workgroup of the norm / weight kernels.
 constexpr int kNormRowsPerWG = 64;
 constexpr int kScanTile = 2048;   // rows per tile of the fixed-point CDF
-constexpr int kMaxB = 128;        // largest block size
+constexpr int kMaxB = 256;        // largest block size
+constexpr int kDeflateMaxB = 128; // largest b' of one deflation launch
 constexpr int kRejectionFactor = 32;
 
 __host__ __device__ inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
@@ -38,6 +39,7 @@ struct DevScalars {
   int32_t npos;        // rows with positive weight
   int32_t b2;          // steps completed by the reorthogonalisation Cholesky
   int32_t need_exact;  // reorthogonalisation needs the exact Cholesky
+  int32_t bchunk[2];   // b' of the two deflation launches when b > kDeflateMaxB
   int32_t pad[1];
 };
 
@@ -107,37 +109,40 @@ hipError_t launch_gemm_tall(int64_t M, int64_t N, int64_t K, double alpha, const
                             int a_f32, int64_t lda, const double* B, int64_t ldb, double beta,
                             const void* Cin, int cin_f32, int64_t ldcin, double* C,
                             int64_t ldc, int b_lower_tri, hipStream_t s);
-// Pivoted Cholesky of the nb x nb Gram matrix G (FP64) in one workgroup:
-// pivots, pivot rows of R with unpermuted columns (Rraw, row p = R_V(p,:)),
-// optionally the pivoted-order R (Rperm, nb x nb), b' by the truncation rule,
-// tail_1 = ||V||_F^2 and the rank-guard flag.  pivoted = 0 gives plain
-// Cholesky (for the reorthogonalisation pass).  nb <= kMaxB.
-// Mout (nb x nb, ld ldm, optional) receives R11^{-T} scattered to the
-// sampled order (zero outside the first b' rows), so that the orthonormal
-// basis rows of the kept columns are Q'^T = Mout V^T.
-hipError_t launch_cpqr_gram_ex(const double* G, int64_t ldg, int32_t nb,
-                               const int32_t* nb_dev, double tau_b, int pivoted,
-                               const double* xs2_rows, int32_t* piv,
-                               double* Rraw, int64_t ldr, double* Rperm, double* Mout,
-                               int64_t ldm, int32_t* bprime_out, double* tail1_out,
-                               int32_t* stop_out, hipStream_t s,
-                               const int32_t* run_flag = nullptr);
-
-// Fast pivoted Cholesky for the filter (256 threads): pivots, b', pivot rows
-// Rraw (unpermuted columns), R11 in pivoted order (Rp, zero-padded to nb).
-hipError_t launch_cpqr_piv(const double* G, int64_t ldg, int32_t nb, const int32_t* nb_dev,
+// Pivoted Cholesky of the filter (one workgroup of 256 threads, nb <= kMaxB):
+// pivots, b' by the truncation rule, pivot rows Rraw (unpermuted columns),
+// R11 in pivoted order (Rp, zero-padded to nb), tail_1 = ||V||_F^2 and the
+// rank-guard flag.  G is overwritten when nb > 128.
+hipError_t launch_cpqr_piv(double* G, int64_t ldg, int32_t nb, const int32_t* nb_dev,
                            double tau_b, const double* xs2_rows, int32_t* piv, double* Rraw,
                            int64_t ldr, double* Rp, int64_t ldp, int32_t* bprime_out,
                            double* tail1_out, int32_t* stop_out, hipStream_t s);
 
-// Qt[p,:] = (Vt[piv[p],:] - sum_{q<p} Rp[q][p] Qt[q,:]) / Rp[p][p], p < b';
-// rows b'..nb_host-1 zero.
+// X = R^{-1} (or X^T with trans) of the upper triangular R (*bcount x
+// *bcount), zero elsewhere in the nb_host x nb_host output; skipped when
+// run_flag is given and *run_flag == 0.
+hipError_t launch_tri_inv(const double* R, int64_t ldr, const int32_t* bcount, int32_t nb_host,
+                          double* X, int64_t ldx, int trans, const int32_t* run_flag,
+                          hipStream_t s);
+
+// Qt = (R11^{-1})^T V(:, piv)^T: the orthonormal basis rows of the kept
+// columns, p < b'; rows b'..nb_host-1 zero.  Rinv_ws: nb_host^2 doubles.
 hipError_t launch_qsolve(const double* Vt, int64_t ldv, const int32_t* piv, const double* Rp,
                          int64_t ldp, const int32_t* bprime, int32_t nb_host, int64_t ncols,
                          double* Qt, int64_t ldq, double* Rinv_ws, hipStream_t s);
 
-// First-order Cholesky-QR factor M2 = R2^{-T} of G2 = I + E when max|E| <=
-// 1e-8 (need_exact = 0), else need_exact = 1 and M2 is left to the exact path.
+// Exact Cholesky-QR factor of G2 (overwritten when nb_host > 128) when
+// *need_exact: R2 by Cholesky in natural order (steps done to *steps_out),
+// M2t = R2^{-1}; otherwise only *steps_out = *bprime.
+hipError_t launch_ortho_exact(double* G2, int64_t ldg, const int32_t* bprime, int32_t nb_host,
+                              int32_t* piv2, double* R2raw, double* R2, double* M2,
+                              int64_t ldm, int32_t* steps_out, const int32_t* need_exact,
+                              hipStream_t s);
+
+// First-order Cholesky-QR factor of G2 = I + E, stored transposed
+// (M2t = R2^{-1}), when max|E| <= 1e-8 (need_exact = 0), else need_exact = 1
+// and M2t is left to the exact path.  The new basis rows are then
+// Qn = M2t^T Qtmp.
 hipError_t launch_ortho_first_order(const double* G2, int64_t ldg, const int32_t* bprime,
                                     int32_t nb_host, double* M2, int64_t ldm,
                                     int32_t* need_exact, hipStream_t s);
@@ -154,18 +159,12 @@ hipError_t launch_gemm_nt_small(int64_t M, int64_t N, int64_t K, double alpha,
                                 double beta, double* C, int64_t ldc, const int32_t* m_dev,
                                 const int32_t* n_dev, hipStream_t s);
 
-// Qt_out[p,:] = (Vt[piv[p],:] - sum_{q<p} R[q][p] Qt_out[q,:]) / R[p][p]
-// for p < b' (row-oriented forward substitution with R^T).
-hipError_t launch_qform(const double* Vt, int64_t ldv, const int32_t* piv,
-                        const double* R, int64_t ldr, const int32_t* bprime,
-                        int32_t bmax, int64_t n, double* Qt, int64_t ldq,
-                        hipStream_t s);
-
 // Skeleton bookkeeping after the filter: S[kS + p] = idx[piv[p]],
-// sel_block[S[kS+p]] = t.
+// sel_block[S[kS+p]] = t; bchunk (optional) = b' split into deflation
+// launches of at most kDeflateMaxB columns.
 hipError_t launch_append(const int64_t* idx, const int32_t* piv,
                          const int32_t* bprime, int64_t kS, int32_t t,
-                         int64_t* S, int32_t* sel_block, hipStream_t s);
+                         int64_t* S, int32_t* sel_block, int32_t* bchunk, hipStream_t s);
 
 // Low-precision MFMA fragment copies of Q' (rows kS.. kS+b' of Qt).
 hipError_t launch_make_frags(const double* Qt_new, int64_t ldq,

@@ -126,11 +126,11 @@ __device__ __forceinline__ void wg_weights_scan_tile(
 }
 
 // LDS state of the block sampler (one workgroup of kSampleThreads threads).
-template <int MAXTILES>
+template <int MAXTILES, int MAXB>
 struct SampleShared {
   uint64_t tile_excl[MAXTILES + 1];
-  int64_t acc_idx[kMaxB];
-  uint64_t acc_w[kMaxB];
+  int64_t acc_idx[MAXB];
+  uint64_t acc_w[MAXB];
   int64_t cand[kSampleThreads];
   int32_t flag[kSampleThreads];
   uint64_t red[kSampleThreads];
@@ -142,13 +142,13 @@ struct SampleShared {
 // per-tile prefixes from wg_weights_scan_tile), candidates counted from 0
 // with Philox counter (j, t, ident, 0) and key (seed, 0).  Writes idx[0..nt)
 // and *nt_out (and *npos_out, the number of positive weights).  Called by all
-// kSampleThreads threads of the workgroup; ends past a barrier.
-template <int MAXTILES>
+// kSampleThreads threads of the workgroup; ends past a barrier.  b <= MAXB.
+template <int MAXTILES, int MAXB>
 __device__ __forceinline__ void wg_sample(
     const uint64_t* __restrict__ cdf_local, const uint64_t* __restrict__ tile_sum,
     const int32_t* __restrict__ tile_pos, int64_t m, int32_t b, uint64_t seed,
     uint64_t t, uint64_t ident, int64_t* __restrict__ idx, int32_t* nt_out,
-    int32_t* npos_out, SampleShared<MAXTILES>& sh) {
+    int32_t* npos_out, SampleShared<MAXTILES, MAXB>& sh) {
   int32_t& s_nacc = sh.nacc;
   int32_t& s_npos = sh.npos;
   int32_t& s_total_new = sh.total_new;
@@ -322,159 +322,267 @@ __device__ __forceinline__ void wg_sample(
   __syncthreads();
 }
 
-// LDS state of the pivoted Cholesky (besides the nb x (nb+1) Schur buffer).
+// ---- wave-level argmax / sum without LDS traffic ----
+// (value, index) pairs are ordered by value, then by the lower index; an
+// index < 0 marks "no candidate".
+__device__ __forceinline__ bool piv_better(double ob, int oi, double best, int bi) {
+  return oi >= 0 && (bi < 0 || ob > best || (ob == best && oi < bi));
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int x) {
+  return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = dpp_i32<CTRL>((int)b);
+  const int hi = dpp_i32<CTRL>((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int LANE>
+__device__ __forceinline__ double readlane_f64(double x) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_readlane((int)b, LANE);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), LANE);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ void argmax_sum_step(double& best, int& bi, double& sum) {
+  const double ob = dpp_f64<CTRL>(best);
+  const int oi = dpp_i32<CTRL>(bi);
+  sum += dpp_f64<CTRL>(sum);   // both partners form the same sum (addition commutes)
+  if (piv_better(ob, oi, best, bi)) {
+    best = ob;
+    bi = oi;
+  }
+}
+
+template <int ROW>
+__device__ __forceinline__ void argmax_sum_fold_row(double best, int bi, double sum,
+                                                    double& B, int& I, double& T) {
+  const double ob = readlane_f64<16 * ROW>(best);
+  const int oi = __builtin_amdgcn_readlane(bi, 16 * ROW);
+  T += readlane_f64<16 * ROW>(sum);
+  if (piv_better(ob, oi, B, I)) {
+    B = ob;
+    I = oi;
+  }
+}
+
+// Argmax and sum over the 64 lanes of a wave (all lanes active).  Within
+// rows of 16 lanes: DPP butterflies (quad permutations, half-row and row
+// mirrors), after which every lane of a row holds the row's result; the four
+// rows are then folded in order through readlane.  The result is uniform and
+// the summation order is fixed.
+__device__ __forceinline__ void wave_argmax_sum(double& best, int& bi, double& sum) {
+  argmax_sum_step<0xB1>(best, bi, sum);   // quad_perm [1,0,3,2]
+  argmax_sum_step<0x4E>(best, bi, sum);   // quad_perm [2,3,0,1]
+  argmax_sum_step<0x141>(best, bi, sum);  // row_half_mirror
+  argmax_sum_step<0x140>(best, bi, sum);  // row_mirror
+  double B = readlane_f64<0>(best);
+  int I = __builtin_amdgcn_readlane(bi, 0);
+  double T = readlane_f64<0>(sum);
+  argmax_sum_fold_row<1>(best, bi, sum, B, I, T);
+  argmax_sum_fold_row<2>(best, bi, sum, B, I, T);
+  argmax_sum_fold_row<3>(best, bi, sum, B, I, T);
+  best = B;
+  bi = I;
+  sum = T;
+}
+
+// LDS state of the pivoted Cholesky (besides the Schur complement itself).
 constexpr int kPivKB = 16;   // pivot rows per delayed Schur-complement update
-
-struct PivShared {
-  double rblk[kPivKB][kMaxB];  // pivot rows of the current block of steps
-  int32_t chosen[kMaxB];
-  int32_t pivs[kMaxB];
-  double wbest[2], wtail[2];
-  int32_t wbi[2];
-};
-
+constexpr int kPivLd = 18;   // row stride (doubles) of the transposed pivot rows
 constexpr int kPivThreads = 256;
 
-// Pivoted Cholesky of the block's Gram matrix for the filter (kPivThreads
-// threads).  The Schur complement S (nb x nb, row stride nb + 1) lives in
-// LDS (Ss); thread j < nb keeps the exact diagonal entry S[j][j] in a
-// register and downdates it at every step.  Per pivot step: a fixed-order
-// argmax / sum over the diagonal (waves 0-1), then the pivot row of R from
-// the pivot's row of S minus the contributions of the earlier pivots of the
-// current group of kPivKB steps; S itself is brought up to date once per
-// group by a rank-kPivKB update over its remaining rows and columns (the
-// delayed update of blocked pivoted QR / Cholesky), so each step costs two
-// barriers and O(kPivKB) LDS reads per thread.  Outputs: pivots (kept ones first, the rest in
-// increasing order), b', the pivot rows of R with unpermuted columns (Rraw),
-// R11 in pivoted order (Rp, nb x nb, zero outside the leading b' x b' upper
-// triangle), ||V||_F^2 and the rank-guard flag.  Ends past a barrier.
+template <int NBMAX>
+struct PivShared {
+  double rblk[NBMAX][kPivLd];  // rblk[c][q]: entry c of pivot row q of the current group
+  int32_t chosen[NBMAX];
+  int32_t pivs[NBMAX];
+  double wbest[2][4], wsum[2][4], gdiag[2];
+  int32_t wbi[2][4];
+};
+
+// Cholesky of the block's Gram matrix G (nb x nb, nb <= NBMAX <= kPivThreads)
+// by kPivThreads threads: pivoted (PIVOTED, the filter: pivot = largest
+// remaining Schur diagonal, ties to the lower index, stop at the truncation
+// threshold) or in natural order (the reorthogonalisation pass).
+//
+// Thread c < nb owns column c of the Schur complement S: it keeps the exact
+// diagonal S[c][c] in a register, downdated at every step, and is the only
+// thread that reads or writes column c of S.  S is brought up to date only
+// once per group of kPivKB steps (a rank-kPivKB update of the owned column
+// with the group's pivot rows, the delayed update of blocked pivoted
+// Cholesky); inside a group the pivot row is formed from the last update
+// plus the corrections of the group's earlier pivots.  S lives in LDS (GS
+// false: copied from G, row stride nb + 1) or in global memory (GS true: S is
+// G itself, updated in place).  One barrier per step (two at a group's
+// first step); the per-step argmax and the sum of the diagonal are wave-level
+// DPP reductions folded across waves in a fixed order.
+//
+// Outputs: pivots (kept ones first, the rest in increasing order), b' (the
+// steps done), the pivot rows of R with unpermuted columns (Rraw), R11 in
+// pivoted order (Rp, nb_host x nb_host, zero outside the leading b' x b'
+// upper triangle), ||V||_F^2 and the rank-guard flag (pivoted mode only).
+// Ends past a barrier.
+template <int NBMAX, bool GS, bool PIVOTED>
 __device__ __forceinline__ void wg_piv_chol(
     const double* __restrict__ G, int64_t ldg, int32_t nb_host,
     const int32_t* __restrict__ nb_dev, double tau_b,
     const double* __restrict__ xs2_rows, int32_t* __restrict__ piv,
     double* __restrict__ Rraw, int64_t ldr, double* __restrict__ Rp, int64_t ldp,
     int32_t* __restrict__ bprime_out, double* __restrict__ tail1_out,
-    int32_t* __restrict__ stop_out, double* Ss, PivShared& sh) {
-  int32_t* chosen_s = sh.chosen;
-  int32_t* pivs = sh.pivs;
-  double* wbest = sh.wbest;
-  double* wtail = sh.wtail;
-  int32_t* wbi = sh.wbi;
+    int32_t* __restrict__ stop_out, double* __restrict__ S, PivShared<NBMAX>& sh) {
+  static_assert(NBMAX <= kPivThreads, "one thread per column");
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   int nb = nb_host;
   if (nb_dev) nb = min(nb, *nb_dev);
-  const int ld = nb + 1;
-  for (int e = tid; e < nb * nb; e += kPivThreads) {
-    const int r = e / nb, c = e - r * nb;
-    Ss[r * ld + c] = G[(int64_t)r * ldg + c];
+  const int64_t ld = GS ? ldg : nb + 1;
+  if constexpr (!GS) {
+    for (int e = tid; e < nb * nb; e += kPivThreads) {
+      const int r = e / nb, c = e - r * nb;
+      S[r * ld + c] = G[(int64_t)r * ldg + c];
+    }
   }
-  if (tid < kMaxB) chosen_s[tid] = (tid < nb) ? 0 : 1;
+  if (tid < NBMAX) sh.chosen[tid] = (tid < nb) ? 0 : 1;
   __syncthreads();
-  const bool owner = tid < nb;                 // owns diagonal entry tid
-  double dj = owner ? Ss[tid * ld + tid] : 0.0;
+  const bool owner = tid < nb;
+  double dj = owner ? S[(int64_t)tid * ld + tid] : 0.0;
   bool chosen = !owner;
+  const int nwv = (nb + 63) >> 6;
+  double rown[kPivKB];
+#pragma unroll
+  for (int q = 0; q < kPivKB; ++q) rown[q] = 0.0;
   double thr = 0.0;
   int bp = 0;
-  for (int p = 0; p <= nb; ++p) {
-    const int qb = p % kPivKB;
-    if (qb == 0 && p > 0) {
-      // delayed update of the remaining Schur complement by the last group
-      for (int e = tid; e < nb * nb; e += kPivThreads) {
-        const int i = e / nb, c = e - i * nb;
-        if (chosen_s[i] || chosen_s[c]) continue;
-        double s0 = 0.0, s1 = 0.0;
+  for (int g = 0;; ++g) {
+    bool fin = false;
 #pragma unroll
-        for (int q = 0; q < kPivKB; q += 2) {
-          s0 += sh.rblk[q][i] * sh.rblk[q][c];
-          s1 += sh.rblk[q + 1][i] * sh.rblk[q + 1][c];
+    for (int qb = 0; qb < kPivKB; ++qb) {
+      const int p = g * kPivKB + qb;
+      const int par = p & 1;
+      if (wv < nwv) {
+        double best = chosen ? -INFINITY : dj;
+        int bi = chosen ? -1 : tid;
+        double sum = chosen ? 0.0 : fmax(dj, 0.0);
+        wave_argmax_sum(best, bi, sum);
+        if (lane == 0) {
+          sh.wbest[par][wv] = best;
+          sh.wbi[par][wv] = bi;
+          sh.wsum[par][wv] = sum;
         }
-        Ss[i * ld + c] -= s0 + s1;
       }
+      if (!PIVOTED && tid == p) sh.gdiag[par] = dj;
       __syncthreads();
-    }
-    if (wv < 2) {
-      double best = chosen ? -INFINITY : dj;
-      int bi = chosen ? -1 : tid;
-      double tail = chosen ? 0.0 : fmax(dj, 0.0);
+      double best = sh.wbest[par][0];
+      int bi = sh.wbi[par][0];
+      double tail = sh.wsum[par][0];
+      for (int w2 = 1; w2 < nwv; ++w2) {
+        tail += sh.wsum[par][w2];
+        if (piv_better(sh.wbest[par][w2], sh.wbi[par][w2], best, bi)) {
+          best = sh.wbest[par][w2];
+          bi = sh.wbi[par][w2];
+        }
+      }
+      bool done = false;
+      if (PIVOTED && p == 0) {
+        thr = tau_b * tail * (1.0 - 4.0 * nb * 1.1102230246251565e-16);
+        if (tid == 0 && tail1_out) *tail1_out = tail;
+        if (xs2_rows) {
+          double xs2 = 0.0;
+          for (int q = 0; q < nb; ++q) xs2 += xs2_rows[q];
+          if (!(tail > 1e-26 * xs2)) {
+            done = true;
+            if (stop_out && tid == 0) *stop_out = 1;
+          }
+        }
+      }
+      int jp = bi;
+      double gv = best;
+      if (!PIVOTED) {
+        jp = p;
+        gv = p < nb ? sh.gdiag[par] : 0.0;
+      }
+      if (p >= nb || jp < 0 || !(gv > 0.0)) done = true;
+      if (PIVOTED && p > 0 && tail < thr) done = true;
+      if (done) {
+        bp = p;
+        fin = true;
+        break;
+      }
+      if (qb == 0 && g > 0) {
+        // delayed update of the owned column by the previous group's pivot rows
+        if (owner && !chosen) {
+          constexpr int RU = GS ? 8 : 4;
+          for (int i0 = 0; i0 < nb; i0 += RU) {
+            double a[RU];
+            bool live[RU];
 #pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        const double ob = __shfl_xor(best, off, kWave);
-        const int oi = __shfl_xor(bi, off, kWave);
-        tail += __shfl_xor(tail, off, kWave);
-        if (oi >= 0 && (bi < 0 || ob > best || (ob == best && oi < bi))) {
-          best = ob;
-          bi = oi;
+            for (int u = 0; u < RU; ++u) {
+              const int i = i0 + u;
+              live[u] = i < nb && !sh.chosen[i];
+              a[u] = S[(int64_t)(live[u] ? i : tid) * ld + tid];
+            }
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+              if (!live[u]) continue;
+              const double* ri = sh.rblk[i0 + u];
+              double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+              for (int q = 0; q < kPivKB; q += 2) {
+                s0 += ri[q] * rown[q];
+                s1 += ri[q + 1] * rown[q + 1];
+              }
+              S[(int64_t)(i0 + u) * ld + tid] = a[u] - (s0 + s1);
+            }
+          }
         }
+        __syncthreads();
       }
-      if (lane == 0) {
-        wbest[wv] = best;
-        wbi[wv] = bi;
-        wtail[wv] = tail;
-      }
-    }
-    __syncthreads();
-    double best = wbest[0];
-    int bi = wbi[0];
-    double tail = wtail[0] + wtail[1];
-    if (wbi[1] >= 0 && (bi < 0 || wbest[1] > best || (wbest[1] == best && wbi[1] < bi))) {
-      best = wbest[1];
-      bi = wbi[1];
-    }
-    bool done = false;
-    if (p == 0) {
-      thr = tau_b * tail * (1.0 - 4.0 * nb * 1.1102230246251565e-16);
-      if (tid == 0 && tail1_out) *tail1_out = tail;
-      if (xs2_rows) {
-        double xs2 = 0.0;
-        for (int q = 0; q < nb; ++q) xs2 += xs2_rows[q];
-        if (!(tail > 1e-26 * xs2)) {
-          done = true;
-          if (stop_out && tid == 0) *stop_out = 1;
+      const double r = sqrt(gv);
+      double v = 0.0;
+      if (owner) {
+        if (tid == jp) {
+          v = r;
+        } else if (!chosen) {
+          double a = S[(int64_t)jp * ld + tid];
+          const double* rj = sh.rblk[jp];
+#pragma unroll
+          for (int q = 0; q < qb; ++q) a -= rj[q] * rown[q];
+          v = a / r;
         }
+        sh.rblk[tid][qb] = v;
+        Rraw[(int64_t)p * ldr + tid] = v;
+        if (tid == jp) {
+          chosen = true;
+          sh.chosen[tid] = 1;
+          sh.pivs[p] = jp;
+        }
+        dj -= v * v;
       }
+      rown[qb] = v;
     }
-    if (p == nb || bi < 0 || !(best > 0.0)) done = true;
-    if (p > 0 && tail < thr) done = true;
-    if (done) {
-      bp = p;
-      break;
-    }
-    const int jp = bi;
-    const double r = sqrt(best);
-    if (tid < nb) {
-      double v;
-      if (tid == jp) v = r;
-      else if (chosen) v = 0.0;
-      else {
-        double a = Ss[jp * ld + tid];
-        for (int q = 0; q < qb; ++q) a -= sh.rblk[q][jp] * sh.rblk[q][tid];
-        v = a / r;
-      }
-      sh.rblk[qb][tid] = v;
-      Rraw[(int64_t)p * ldr + tid] = v;
-      if (tid == jp) {
-        chosen = true;
-        chosen_s[tid] = 1;
-        pivs[p] = jp;
-      }
-      dj -= v * v;
-    }
-    __syncthreads();
+    if (fin) break;
   }
   if (tid == 0) {
     int q = bp;
     for (int c = 0; c < nb; ++c)
-      if (!chosen_s[c]) pivs[q++] = c;
+      if (!sh.chosen[c]) sh.pivs[q++] = c;
     *bprime_out = bp;
   }
   __syncthreads();
-  if (tid < nb) piv[tid] = pivs[tid];
+  if (tid < nb) piv[tid] = sh.pivs[tid];
   // R11 in pivoted order, zero outside the leading b' x b' upper triangle
   for (int e = tid; e < nb_host * nb_host; e += kPivThreads) {
     const int a = e / nb_host, c = e - a * nb_host;
     double v = 0.0;
-    if (a < bp && c >= a && c < nb) v = Rraw[(int64_t)a * ldr + pivs[c]];
+    if (a < bp && c >= a && c < nb) v = Rraw[(int64_t)a * ldr + sh.pivs[c]];
     Rp[(int64_t)a * ldp + c] = v;
   }
   __syncthreads();

@@ -48,7 +48,8 @@ def test_workspace_size_is_host_only_and_validates(L):
     assert rb.workspace_size(0, 100, 16) == 0
     assert rb.workspace_size(100, 0, 16) == 0
     assert rb.workspace_size(100, 100, 0) == 0
-    assert rb.workspace_size(100, 100, 129) == 0
+    assert rb.workspace_size(100, 100, 256) > 0
+    assert rb.workspace_size(100, 100, 257) == 0
     assert rb.workspace_size(100, 100, 16, k_max=101) == 0
 
 
@@ -93,7 +94,7 @@ def test_hooks_validate_before_device_work(L):
                                ctypes.byref(n), ctypes.c_void_p(1), 1 << 30,
                                None) == B.RBRP_E_INVALID
     bp = ctypes.c_int32(0)
-    assert L.rbrp_block_cpqr(ctypes.c_void_p(1), 10, 200, 10, 0.1, ctypes.c_void_p(1),
+    assert L.rbrp_block_cpqr(ctypes.c_void_p(1), 10, 257, 10, 0.1, ctypes.c_void_p(1),
                              ctypes.c_void_p(1), ctypes.c_void_p(1), 10, ctypes.byref(bp),
                              ctypes.c_void_p(1), 1 << 30, None) == B.RBRP_E_INVALID
     assert L.rbrp_block_cpqr(ctypes.c_void_p(1), 10, 4, 10, 1.5, ctypes.c_void_p(1),

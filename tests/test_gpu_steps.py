@@ -89,7 +89,9 @@ def _generic_block(n, nb, seed):
 
 
 @pytest.mark.parametrize("n,nb,seed", [(1000, 64, 1), (200, 16, 2), (40, 100, 3),
-                                       (2048, 128, 4), (513, 37, 5), (7, 1, 6)])
+                                       (2048, 128, 4), (513, 37, 5), (7, 1, 6),
+                                       (3000, 256, 7), (1500, 200, 8), (300, 160, 9),
+                                       (4096, 256, 10), (129, 129, 11)])
 def test_block_filter_matches_oracle(rb, n, nb, seed):
     V = _generic_block(n, nb, seed)
     # a low-rank block with noise so that the filter truncates
@@ -132,3 +134,26 @@ def test_block_filter_on_gmm_rows(rb):
     piv, R, Qt, bp = rb.block_cpqr(_gpu(V.T), 1.0 / 64)
     opiv, _, _, _, obp = filter_block(V, 1.0 / 64)
     assert bp == obp and piv.cpu().numpy()[:bp].tolist() == opiv[:bp].tolist()
+
+
+@pytest.mark.parametrize("n,nb", [(400, 48), (900, 200)])
+def test_block_filter_ill_conditioned_exact_reorth(rb, n, nb):
+    # condition number 1e6 with every column kept (tau_b = 0): the first basis
+    # Q' = V(:, piv) R11^{-1} is orthogonal only to about u cond^2 ~ 1e-4,
+    # which sends the second pass down the exact Cholesky-QR path
+    rng = np.random.default_rng(nb)
+    U, _ = np.linalg.qr(rng.standard_normal((n, nb)))
+    Wm, _ = np.linalg.qr(rng.standard_normal((nb, nb)))
+    V = U @ np.diag(np.logspace(0, -6, nb)) @ Wm
+    print(f"block_cpqr ill-conditioned n={n} nb={nb}", flush=True)
+    piv, R, Qt, bp = rb.block_cpqr(_gpu(V.T), 0.0)
+    assert bp == nb
+    Q = Qt.cpu().numpy()[:bp].T
+    assert np.linalg.norm(Q.T @ Q - np.eye(bp)) <= 1e-13 * bp
+    # the kept columns span exactly the columns of V
+    assert np.linalg.norm(V - Q @ (Q.T @ V)) <= 1e-9 * np.linalg.norm(V)
+    p = piv.cpu().numpy()
+    assert sorted(p.tolist()) == list(range(nb))
+    # |diag R| is the greedy sequence of residual norms: non-increasing
+    dg = np.abs(np.diag(R.cpu().numpy()[:bp, :bp]))
+    assert np.all(dg[1:] <= dg[:-1] * (1 + 1e-6))

@@ -166,7 +166,9 @@ CONFIGS = {
     "adversarial_gmm_fp32": dict(m=100000, n=1000, eps=1e-3, b=64, dtype="f32", seed=1002),
     "svd_power_bf16": dict(m=200000, n=2048, eps=1e-4, b=128, dtype="f32", seed=1003),
     "kernel_blocks_batched": dict(count=4096, eps=1e-6, dtype="f32", seed=1004),
-    "random_features_large": dict(m=1000000, n=4096, eps=1e-3, b=256, dtype="f32", seed=1005),
+    # eps-rank at 1e-3 is close to n for this generator: fixed rank k = 2048
+    "random_features_large": dict(m=1000000, n=4096, eps=1e-3, b=256, dtype="f32", seed=1005,
+                                  k_max=2048, fixed_rank=True),
 }
 
 
