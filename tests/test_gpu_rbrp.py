@@ -50,6 +50,7 @@ def _run(rb, X, eps, b, seed, **kw):
     (700, 130, 64, 1e-4, 4),
     (3000, 1000, 256, 1e-3, 5),  # b > 128: global-memory filter, two deflation launches
     (1500, 400, 200, 1e-4, 6),   # ... and a run that ends at full rank (k = n)
+    (2500, 1300, 64, 1e-3, 7),   # 1024 < n <= 2048: eight-wave deflation panels
 ])
 def test_fp64_matches_oracle(rb, m, n, b, eps, seed):
     if b > 128:
@@ -116,7 +117,8 @@ def test_deterministic(rb):
     assert torch.equal(a.W, b.W)
 
 
-@pytest.mark.parametrize("m,n,b,seed", [(6000, 250, 32, 1), (20000, 1000, 64, 2)])
+@pytest.mark.parametrize("m,n,b,seed", [(6000, 250, 32, 1), (20000, 1000, 64, 2),
+                                        (8000, 1500, 64, 3)])
 def test_fp32_adversarial_gmm(rb, m, n, b, seed):
     eps = 1e-3
     X = adversarial_gmm(m, n, sub_dim=min(200, n // 2), n_comp=20, seed=seed)
