@@ -157,18 +157,40 @@ __global__ __launch_bounds__(256) void k_tri_inv_blocked(
     for (int i = wv; i + dd < nbk; i += 4) {
       const int j = i + dd;
       d4v_t acc = {0.0, 0.0, 0.0, 0.0};
-      for (int l = i + 1; l <= j; ++l) {
+      // the off-diagonal blocks l = i+1 .. j-1 four at a time, every load of a
+      // group issued before its MFMAs (indices clamped into range, values
+      // masked); then the diagonal block X_jj from LDS
+      const int bc = 16 * j + l16;
+      for (int l0 = i + 1; l0 < j; l0 += 4) {
+        double av[4][4], bv[4][4];
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) {
-          const int kk = 4 * s4 + lhi;
-          const int ac = 16 * l + kk;
-          const double a = ac < bp ? R[(int64_t)(16 * i + l16) * ldr + ac] : 0.0;
-          const int bc = 16 * j + l16;
-          double b;
-          if (l == j) b = Bd[j][kk][l16];
-          else b = bc < bp ? X[xoff(16 * l + kk, bc)] : 0.0;
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        for (int u = 0; u < 4; ++u) {
+          const int l = min(l0 + u, j - 1);
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const int kk = 4 * s4 + lhi;
+            av[u][s4] = R[(int64_t)(16 * i + l16) * ldr + min(16 * l + kk, bp - 1)];
+            bv[u][s4] = X[xoff(16 * l + kk, min(bc, nb_host - 1))];
+          }
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const bool live = l0 + u < j;
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const int kk = 4 * s4 + lhi;
+            const int l = l0 + u;
+            const double a = (live && 16 * l + kk < bp) ? av[u][s4] : 0.0;
+            const double b = (live && bc < bp) ? bv[u][s4] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int kk = 4 * s4 + lhi;
+        const double a = (16 * j + kk < bp) ? R[(int64_t)(16 * i + l16) * ldr + min(16 * j + kk, bp - 1)] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Bd[j][kk][l16], acc, 0, 0, 0);
       }
       d4v_t out = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -196,32 +218,59 @@ __global__ __launch_bounds__(256) void k_ortho_first_order(const double* __restr
                                                            double* __restrict__ M2,
                                                            int64_t ldm,
                                                            int32_t* __restrict__ need_exact) {
+  // thread (column c, part) handles rows part, part + TPC, ... of column c
+  // (nb_host <= 256); eight rows' loads are issued before they are used
   __shared__ double red[256];
   const int bp = *bprime;
+  const int tid = threadIdx.x;
+  const int ncols = nb_host <= 64 ? 64 : (nb_host <= 128 ? 128 : 256);
+  const int tpc = 256 / ncols;
+  const int c = tid % ncols, part = tid / ncols;
   double mx = 0.0;
-  for (int e = threadIdx.x; e < bp * bp; e += 256) {
-    const int a = e / bp, c = e - a * bp;
-    const double v = G2[(int64_t)a * ldg + c] - (a == c ? 1.0 : 0.0);
-    mx = fmax(mx, fabs(v));
+  if (c < bp) {
+    for (int a0 = part; a0 < bp; a0 += 8 * tpc) {
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = G2[(int64_t)min(a0 + u * tpc, bp - 1) * ldg + c];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int a = a0 + u * tpc;
+        if (a < bp) mx = fmax(mx, fabs(x[u] - (a == c ? 1.0 : 0.0)));
+      }
+    }
   }
-  red[threadIdx.x] = mx;
+  red[tid] = mx;
   __syncthreads();
   for (int h = 128; h >= 1; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+    if (tid < h) red[tid] = fmax(red[tid], red[tid + h]);
     __syncthreads();
   }
   const bool small = red[0] <= 1e-8;
-  if (threadIdx.x == 0) *need_exact = small ? 0 : 1;
+  if (tid == 0) *need_exact = small ? 0 : 1;
   if (!small) return;
-  for (int e = threadIdx.x; e < nb_host * nb_host; e += 256) {
-    const int a = e / nb_host, c = e - a * nb_host;
-    double v = 0.0;
-    if (a < bp && c < bp) {
-      // (M2^T)[a][c] = M2[c][a]: 1 - E[a][a] / 2 on the diagonal, -E[c][a] above
-      if (a == c) v = 1.0 - 0.5 * (G2[(int64_t)a * ldg + a] - 1.0);
-      else if (c > a) v = -G2[(int64_t)c * ldg + a];
+  // (M2^T)[a][c] = M2[c][a]: 1 - E[a][a] / 2 on the diagonal, -E[c][a] above
+  if (c < nb_host) {
+    for (int a0 = part; a0 < nb_host; a0 += 8 * tpc) {
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int a = a0 + u * tpc;
+        // the diagonal reads G2[a][a], the strict upper part G2[c][a]
+        // (clamped index: always in range, used only where it applies)
+        x[u] = G2[(int64_t)c * ldg + min(a, nb_host - 1)];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int a = a0 + u * tpc;
+        if (a >= nb_host) continue;
+        double v = 0.0;
+        if (a < bp && c < bp) {
+          if (a == c) v = 1.0 - 0.5 * (x[u] - 1.0);
+          else if (c > a) v = -x[u];
+        }
+        M2[(int64_t)a * ldm + c] = v;
+      }
     }
-    M2[(int64_t)a * ldm + c] = v;
   }
 }
 
@@ -243,7 +292,11 @@ hipError_t launch_cpqr_piv(double* G, int64_t ldg, int32_t nb, const int32_t* nb
                            int64_t ldr, double* Rp, int64_t ldp, int32_t* bprime_out,
                            double* tail1_out, int32_t* stop_out, hipStream_t s) {
   if (nb <= 0 || nb > kMaxB) return hipErrorInvalidValue;
-  if (nb <= kLdsCholMax) {
+  if (nb <= 64) {
+    hipLaunchKernelGGL((k_cpqr_piv<64, false>), dim3(1), dim3(kPivThreads),
+                       chol_lds_bytes(nb), s, G, ldg, nb, nb_dev, tau_b, xs2_rows, piv, Rraw,
+                       ldr, Rp, ldp, bprime_out, tail1_out, stop_out);
+  } else if (nb <= kLdsCholMax) {
     static bool attr = false;
     hipError_t e = set_chol_lds(k_cpqr_piv<kLdsCholMax, false>, &attr);
     if (e != hipSuccess) return e;
@@ -290,7 +343,11 @@ hipError_t launch_ortho_exact(double* G2, int64_t ldg, const int32_t* bprime, in
                               int64_t ldm, int32_t* steps_out, const int32_t* need_exact,
                               hipStream_t s) {
   if (nb_host <= 0 || nb_host > kMaxB) return hipErrorInvalidValue;
-  if (nb_host <= kLdsCholMax) {
+  if (nb_host <= 64) {
+    hipLaunchKernelGGL((k_chol_reorth<64, false>), dim3(1), dim3(kPivThreads),
+                       chol_lds_bytes(nb_host), s, G2, ldg, nb_host, bprime, piv2, R2raw,
+                       (int64_t)nb_host, R2, (int64_t)nb_host, steps_out, need_exact);
+  } else if (nb_host <= kLdsCholMax) {
     static bool attr = false;
     hipError_t e = set_chol_lds(k_chol_reorth<kLdsCholMax, false>, &attr);
     if (e != hipSuccess) return e;

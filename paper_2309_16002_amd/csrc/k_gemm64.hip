@@ -431,10 +431,10 @@ namespace rbrp {
 // when written to LDS.  Otherwise each element is loaded from a clamped
 // index.  Rows >= M of A and columns >= N of B only reach outputs that are
 // not stored, so they are loaded from clamped addresses and not masked.
-constexpr int TB_M = 128, TB_N = 64;
-constexpr int TA_LD = TB_M + 16, TBB_LD = TB_N + 16;  // row strides: 16 doubles = half the banks
+constexpr int TB_M = 128;
+constexpr int TA_LD = TB_M + 16;  // row stride: 16 doubles = half the banks
 
-template <typename TA, int TB_K>
+template <typename TA, int TB_K, int TB_N>
 struct TallStage {
   static constexpr int NA = TB_M * TB_K / 256, NB = TB_N * TB_K / 256;
   static constexpr int VW = 16 / sizeof(TA), NAV = NA / VW;
@@ -443,14 +443,16 @@ struct TallStage {
   double b[NB];
 };
 
-template <typename TA, bool VA, typename TC, int TB_K, int WPE>
+template <typename TA, bool VA, typename TC, int TB_K, int WPE, int TB_N>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_gemm_tall(
     int64_t M, int64_t N, int64_t K, double alpha, const TA* __restrict__ A, int64_t lda,
     const double* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C,
     int64_t ldc, const TC* __restrict__ Cin, int64_t ldcin, int64_t nrt, int64_t nct,
     int xcd_map, int b_lower_tri) {
-  typedef TallStage<TA, TB_K> St;
+  typedef TallStage<TA, TB_K, TB_N> St;
   constexpr int NA = St::NA, NB = St::NB, VW = St::VW, NAV = St::NAV;
+  constexpr int TBB_LD = TB_N + 16;
+  constexpr int WN = TB_N / 32;       // 16-column MFMA tiles per wave (2 x 2 waves)
   typedef typename St::av_t av_t;
   __shared__ double As[2][TB_K][TA_LD];
   __shared__ double Bs[2][TB_K][TBB_LD];
@@ -479,11 +481,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 
   {
     const int64_t i0 = r * TB_M, j0 = c * TB_N;
-    d4v acc[4][2];
+    d4v acc[4][WN];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = (d4v){0.0, 0.0, 0.0, 0.0};
+      for (int b = 0; b < WN; ++b) acc[a][b] = (d4v){0.0, 0.0, 0.0, 0.0};
     const int64_t ga = i0 + ai;
     const TA* ap = A + (ga < M ? ga : M - 1) * lda;
     const int64_t gbj = j0 + bj;
@@ -530,15 +532,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 #pragma unroll
       for (int ks = 0; ks < TB_K / 4; ++ks) {
         const int kr = 4 * ks + (lane >> 4);
-        double av[4], bv[2];
+        double av[4], bv[WN];
 #pragma unroll
         for (int a = 0; a < 4; ++a) av[a] = As[buf][kr][64 * wy + 16 * a + (lane & 15)];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) bv[b] = Bs[buf][kr][32 * wx + 16 * b + (lane & 15)];
+        for (int b = 0; b < WN; ++b) bv[b] = Bs[buf][kr][(TB_N / 2) * wx + 16 * b + (lane & 15)];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b)
+          for (int b = 0; b < WN; ++b)
             acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
       }
     };
@@ -579,43 +581,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
       if (t < nt) mma(0);  // nt odd: the last step sits in LDS 0
     }
 
-    // epilogue: all C-input loads first (clamped, unconditional), then the
-    // stores, so that the loads of a lane overlap instead of each waiting
-    // for the previous one
-    double cin[4][4][2];
-    if (beta != 0.0) {
+    // epilogue, one 16-row group of MFMA tiles at a time: its C-input loads
+    // first (clamped, unconditional), then its stores, so that the loads of a
+    // lane overlap instead of each waiting for the previous one
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a) {
+      double cin[4][WN];
+      if (beta != 0.0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int64_t gi = min(i0 + 64 * wy + 16 * a + (lane >> 4) + 4 * q, M - 1);
 #pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            const int64_t gj = min(j0 + 32 * wx + 16 * b + (lane & 15), N - 1);
-            cin[a][q][b] = Cin ? (double)Cin[gi * ldcin + gj] : C[gi * ldc + gj];
+          for (int b = 0; b < WN; ++b) {
+            const int64_t gj = min(j0 + (TB_N / 2) * wx + 16 * b + (lane & 15), N - 1);
+            cin[q][b] = Cin ? (double)Cin[gi * ldcin + gj] : C[gi * ldc + gj];
           }
         }
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
+      }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int64_t gi = i0 + 64 * wy + 16 * a + (lane >> 4) + 4 * q;
         if (gi >= M) continue;
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const int64_t gj = j0 + 32 * wx + 16 * b + (lane & 15);
+        for (int b = 0; b < WN; ++b) {
+          const int64_t gj = j0 + (TB_N / 2) * wx + 16 * b + (lane & 15);
           if (gj < N) {
             double v = alpha * acc[a][b][q];
-            if (beta != 0.0) v += beta * cin[a][q][b];
+            if (beta != 0.0) v += beta * cin[q][b];
             C[gi * ldc + gj] = v;
           }
         }
       }
+    }
   }
 }
 
-template <typename TA, typename TC, int BK = 8, int WPE = 3>
+template <typename TA, typename TC, int BK = 8, int WPE = 3, int TB_N = 64>
 static void dispatch_tall(int64_t M, int64_t N, int64_t K, double alpha, const TA* A,
                           int64_t lda, const double* B, int64_t ldb, double beta, double* C,
                           int64_t ldc, const TC* Cin, int64_t ldcin, int blt, hipStream_t s) {
@@ -625,11 +626,11 @@ static void dispatch_tall(int64_t M, int64_t N, int64_t K, double alpha, const T
   const int vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) &&
                   (lda % (int64_t)(16 / sizeof(TA)) == 0) && lda >= round_up(K, BK);
   if (vec)
-    hipLaunchKernelGGL((k_gemm_tall<TA, true, TC, BK, WPE>), dim3((unsigned)nblk), dim3(256),
+    hipLaunchKernelGGL((k_gemm_tall<TA, true, TC, BK, WPE, TB_N>), dim3((unsigned)nblk), dim3(256),
                        0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, Cin, ldcin, nrt, nct,
                        xcd, blt);
   else
-    hipLaunchKernelGGL((k_gemm_tall<TA, false, TC, BK, WPE>), dim3((unsigned)nblk), dim3(256),
+    hipLaunchKernelGGL((k_gemm_tall<TA, false, TC, BK, WPE, TB_N>), dim3((unsigned)nblk), dim3(256),
                        0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, Cin, ldcin, nrt, nct,
                        xcd, blt);
 }

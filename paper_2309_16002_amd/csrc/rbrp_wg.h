@@ -394,6 +394,28 @@ __device__ __forceinline__ void wave_argmax_sum(double& best, int& bi, double& s
   sum = T;
 }
 
+template <int CTRL>
+__device__ __forceinline__ void max_sum_step(double& mx, double& sum) {
+  mx = fmax(mx, dpp_f64<CTRL>(mx));
+  sum += dpp_f64<CTRL>(sum);
+}
+
+// Maximum and sum over the 64 lanes of a wave (all lanes active), both
+// uniform on return; the summation order is fixed (DPP butterflies within
+// rows of 16 lanes, then the four rows in order).
+__device__ __forceinline__ void wave_max_sum(double& mx, double& sum) {
+  max_sum_step<0xB1>(mx, sum);
+  max_sum_step<0x4E>(mx, sum);
+  max_sum_step<0x141>(mx, sum);
+  max_sum_step<0x140>(mx, sum);
+  const double m0 = readlane_f64<0>(mx), m1 = readlane_f64<16>(mx);
+  const double m2 = readlane_f64<32>(mx), m3 = readlane_f64<48>(mx);
+  const double t0 = readlane_f64<0>(sum), t1 = readlane_f64<16>(sum);
+  const double t2 = readlane_f64<32>(sum), t3 = readlane_f64<48>(sum);
+  mx = fmax(fmax(m0, m1), fmax(m2, m3));
+  sum = ((t0 + t1) + t2) + t3;
+}
+
 // LDS state of the pivoted Cholesky (besides the Schur complement itself).
 constexpr int kPivKB = 16;   // pivot rows per delayed Schur-complement update
 constexpr int kPivLd = 18;   // row stride (doubles) of the transposed pivot rows
@@ -401,29 +423,36 @@ constexpr int kPivThreads = 256;
 
 template <int NBMAX>
 struct PivShared {
-  double rblk[NBMAX][kPivLd];  // rblk[c][q]: entry c of pivot row q of the current group
+  alignas(16) double rblk[NBMAX][kPivLd];  // rblk[c][q]: entry c of pivot row q of the group
   int32_t chosen[NBMAX];
   int32_t pivs[NBMAX];
-  double wbest[2][4], wsum[2][4], gdiag[2];
-  int32_t wbi[2][4];
+  int32_t fin, bp;
 };
+
+template <int LANE_DUMMY = 0>
+__device__ __forceinline__ double readlane_f64_rt(double x, int lane) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
 
 // Cholesky of the block's Gram matrix G (nb x nb, nb <= NBMAX <= kPivThreads)
 // by kPivThreads threads: pivoted (PIVOTED, the filter: pivot = largest
 // remaining Schur diagonal, ties to the lower index, stop at the truncation
 // threshold) or in natural order (the reorthogonalisation pass).
 //
-// Thread c < nb owns column c of the Schur complement S: it keeps the exact
-// diagonal S[c][c] in a register, downdated at every step, and is the only
-// thread that reads or writes column c of S.  S is brought up to date only
-// once per group of kPivKB steps (a rank-kPivKB update of the owned column
-// with the group's pivot rows, the delayed update of blocked pivoted
-// Cholesky); inside a group the pivot row is formed from the last update
-// plus the corrections of the group's earlier pivots.  S lives in LDS (GS
-// false: copied from G, row stride nb + 1) or in global memory (GS true: S is
-// G itself, updated in place).  One barrier per step (two at a group's
-// first step); the per-step argmax and the sum of the diagonal are wave-level
-// DPP reductions folded across waves in a fixed order.
+// The pivot steps run in wave 0 alone, so that a step needs no barrier: lane
+// l owns columns l, l + 64, ... of the Schur complement S, keeps their exact
+// diagonal entries in registers (downdated at every step) and forms their
+// entries of each pivot row; the argmax and the sum of the diagonal are
+// wave-level DPP reductions in a fixed order.  S itself is brought up to
+// date only once per group of kPivKB steps, by all threads (a rank-kPivKB
+// update with the group's pivot rows, the delayed update of blocked pivoted
+// Cholesky); inside a group a pivot row is formed from the last update plus
+// the corrections of the group's earlier pivots.  S lives in LDS (GS false:
+// copied from G, row stride nb + 1) or in global memory (GS true: S is G
+// itself, updated in place).
 //
 // Outputs: pivots (kept ones first, the rest in increasing order), b' (the
 // steps done), the pivot rows of R with unpermuted columns (Rraw), R11 in
@@ -438,152 +467,233 @@ __device__ __forceinline__ void wg_piv_chol(
     double* __restrict__ Rraw, int64_t ldr, double* __restrict__ Rp, int64_t ldp,
     int32_t* __restrict__ bprime_out, double* __restrict__ tail1_out,
     int32_t* __restrict__ stop_out, double* __restrict__ S, PivShared<NBMAX>& sh) {
-  static_assert(NBMAX <= kPivThreads, "one thread per column");
+  static_assert(NBMAX <= kPivThreads, "at most one column per thread in the updates");
+  constexpr int NPL = (NBMAX + 63) / 64;       // columns per lane of wave 0
+  constexpr int NCOLS = 64 * NPL;
+  constexpr int TPC = kPivThreads / NCOLS;     // threads per column in the updates
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   int nb = nb_host;
   if (nb_dev) nb = min(nb, *nb_dev);
   const int64_t ld = GS ? ldg : nb + 1;
   if constexpr (!GS) {
-    for (int e = tid; e < nb * nb; e += kPivThreads) {
-      const int r = e / nb, c = e - r * nb;
-      S[r * ld + c] = G[(int64_t)r * ldg + c];
+    // thread (column c, part) copies rows part, part + TPC, ...; eight rows'
+    // loads are issued before their stores
+    const int c = tid % NCOLS, part = tid / NCOLS;
+    if (c < nb) {
+      for (int r0 = part; r0 < nb; r0 += 8 * TPC) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int r = min(r0 + u * TPC, nb - 1);
+          x[u] = G[(int64_t)r * ldg + c];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (r0 + u * TPC < nb) S[(r0 + u * TPC) * ld + c] = x[u];
+      }
     }
   }
   if (tid < NBMAX) sh.chosen[tid] = (tid < nb) ? 0 : 1;
-  __syncthreads();
-  const bool owner = tid < nb;
-  double dj = owner ? S[(int64_t)tid * ld + tid] : 0.0;
-  bool chosen = !owner;
-  const int nwv = (nb + 63) >> 6;
-  double rown[kPivKB];
-#pragma unroll
-  for (int q = 0; q < kPivKB; ++q) rown[q] = 0.0;
-  double thr = 0.0;
-  int bp = 0;
-  for (int g = 0;; ++g) {
-    bool fin = false;
-#pragma unroll
-    for (int qb = 0; qb < kPivKB; ++qb) {
-      const int p = g * kPivKB + qb;
-      const int par = p & 1;
-      if (wv < nwv) {
-        double best = chosen ? -INFINITY : dj;
-        int bi = chosen ? -1 : tid;
-        double sum = chosen ? 0.0 : fmax(dj, 0.0);
-        wave_argmax_sum(best, bi, sum);
-        if (lane == 0) {
-          sh.wbest[par][wv] = best;
-          sh.wbi[par][wv] = bi;
-          sh.wsum[par][wv] = sum;
-        }
-      }
-      if (!PIVOTED && tid == p) sh.gdiag[par] = dj;
-      __syncthreads();
-      double best = sh.wbest[par][0];
-      int bi = sh.wbi[par][0];
-      double tail = sh.wsum[par][0];
-      for (int w2 = 1; w2 < nwv; ++w2) {
-        tail += sh.wsum[par][w2];
-        if (piv_better(sh.wbest[par][w2], sh.wbi[par][w2], best, bi)) {
-          best = sh.wbest[par][w2];
-          bi = sh.wbi[par][w2];
-        }
-      }
-      bool done = false;
-      if (PIVOTED && p == 0) {
-        thr = tau_b * tail * (1.0 - 4.0 * nb * 1.1102230246251565e-16);
-        if (tid == 0 && tail1_out) *tail1_out = tail;
-        if (xs2_rows) {
-          double xs2 = 0.0;
-          for (int q = 0; q < nb; ++q) xs2 += xs2_rows[q];
-          if (!(tail > 1e-26 * xs2)) {
-            done = true;
-            if (stop_out && tid == 0) *stop_out = 1;
-          }
-        }
-      }
-      int jp = bi;
-      double gv = best;
-      if (!PIVOTED) {
-        jp = p;
-        gv = p < nb ? sh.gdiag[par] : 0.0;
-      }
-      if (p >= nb || jp < 0 || !(gv > 0.0)) done = true;
-      if (PIVOTED && p > 0 && tail < thr) done = true;
-      if (done) {
-        bp = p;
-        fin = true;
-        break;
-      }
-      if (qb == 0 && g > 0) {
-        // delayed update of the owned column by the previous group's pivot rows
-        if (owner && !chosen) {
-          constexpr int RU = GS ? 8 : 4;
-          for (int i0 = 0; i0 < nb; i0 += RU) {
-            double a[RU];
-            bool live[RU];
-#pragma unroll
-            for (int u = 0; u < RU; ++u) {
-              const int i = i0 + u;
-              live[u] = i < nb && !sh.chosen[i];
-              a[u] = S[(int64_t)(live[u] ? i : tid) * ld + tid];
-            }
-#pragma unroll
-            for (int u = 0; u < RU; ++u) {
-              if (!live[u]) continue;
-              const double* ri = sh.rblk[i0 + u];
-              double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-              for (int q = 0; q < kPivKB; q += 2) {
-                s0 += ri[q] * rown[q];
-                s1 += ri[q + 1] * rown[q + 1];
-              }
-              S[(int64_t)(i0 + u) * ld + tid] = a[u] - (s0 + s1);
-            }
-          }
-        }
-        __syncthreads();
-      }
-      const double r = sqrt(gv);
-      double v = 0.0;
-      if (owner) {
-        if (tid == jp) {
-          v = r;
-        } else if (!chosen) {
-          double a = S[(int64_t)jp * ld + tid];
-          const double* rj = sh.rblk[jp];
-#pragma unroll
-          for (int q = 0; q < qb; ++q) a -= rj[q] * rown[q];
-          v = a / r;
-        }
-        sh.rblk[tid][qb] = v;
-        Rraw[(int64_t)p * ldr + tid] = v;
-        if (tid == jp) {
-          chosen = true;
-          sh.chosen[tid] = 1;
-          sh.pivs[p] = jp;
-        }
-        dj -= v * v;
-      }
-      rown[qb] = v;
-    }
-    if (fin) break;
-  }
   if (tid == 0) {
-    int q = bp;
-    for (int c = 0; c < nb; ++c)
-      if (!sh.chosen[c]) sh.pivs[q++] = c;
-    *bprime_out = bp;
+    sh.fin = 0;
+    sh.bp = 0;
+  }
+  __syncthreads();
+  // wave-0 state: the owned columns' diagonal entries and flags (their
+  // entries of the group's pivot rows are read back from rblk)
+  double dj[NPL];
+  bool ch[NPL];
+#pragma unroll
+  for (int j = 0; j < NPL; ++j) {
+    const int c = lane + 64 * j;
+    ch[j] = c >= nb;
+    dj[j] = (wv == 0 && c < nb) ? S[(int64_t)c * ld + c] : 0.0;
+  }
+  double thr = 0.0;
+  for (int g = 0;; ++g) {
+    if (wv == 0) {
+      bool fin = false;
+      int bp = 0;
+#pragma unroll
+      for (int qb = 0; qb < kPivKB; ++qb) {
+        const int p = g * kPivKB + qb;
+        // largest remaining diagonal entry (the wave maximum, then the lowest
+        // column holding it: columns l + 64 j ascend with j, then with l)
+        double best = -INFINITY, sum = 0.0;
+#pragma unroll
+        for (int j = 0; j < NPL; ++j) {
+          if (!ch[j]) {
+            sum += fmax(dj[j], 0.0);
+            best = fmax(best, dj[j]);
+          }
+        }
+        wave_max_sum(best, sum);
+        int bi = -1;
+        if (best > -INFINITY) {
+#pragma unroll
+          for (int j = NPL - 1; j >= 0; --j) {
+            const unsigned long long hit = __ballot(!ch[j] && dj[j] == best);
+            if (hit) bi = 64 * j + (__ffsll((long long)hit) - 1);
+          }
+        }
+        const double tail = sum;
+        bool done = false;
+        if (PIVOTED && p == 0) {
+          thr = tau_b * tail * (1.0 - 4.0 * nb * 1.1102230246251565e-16);
+          if (lane == 0 && tail1_out) *tail1_out = tail;
+          if (xs2_rows) {
+            // ||X(S_t,:)||_F^2: all loads at once, then a wave sum
+            double xs2 = 0.0;
+#pragma unroll
+            for (int j = 0; j < NPL; ++j) {
+              const int c = lane + 64 * j;
+              const double x = xs2_rows[c < nb ? c : nb - 1];   // clamped: always in range
+              xs2 += c < nb ? x : 0.0;
+            }
+            double dmy = 0.0;
+            int dmi = -1;
+            wave_argmax_sum(dmy, dmi, xs2);
+            if (!(tail > 1e-26 * xs2)) {
+              done = true;
+              if (stop_out && lane == 0) *stop_out = 1;
+            }
+          }
+        }
+        int jp = bi;
+        double gv = best;
+        if (!PIVOTED) {
+          jp = p;
+          gv = 0.0;
+          if (p < nb) {
+            double x = dj[0];
+#pragma unroll
+            for (int j = 1; j < NPL; ++j)
+              if ((p >> 6) == j) x = dj[j];
+            gv = readlane_f64_rt(x, p & 63);
+          }
+        }
+        if (p >= nb || jp < 0 || !(gv > 0.0)) done = true;
+        if (PIVOTED && p > 0 && tail < thr) done = true;
+        if (done) {
+          bp = p;
+          fin = true;
+          break;
+        }
+        const double r = sqrt(gv);
+        const double rinv = 1.0 / r;
+        const double* rj = sh.rblk[jp];
+#pragma unroll
+        for (int j = 0; j < NPL; ++j) {
+          const int c = lane + 64 * j;
+          double v = 0.0;
+          if (c == jp) {
+            v = r;
+          } else if (!ch[j]) {
+            // the corrections of the group's qb earlier pivots (qb is a
+            // compile-time constant in each unrolled step: straight-line LDS
+            // reads, two partial sums)
+            const double a = S[(int64_t)jp * ld + c];
+            const double* rc = sh.rblk[c];
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int q = 0; q + 1 < qb; q += 2) {
+              s0 += rj[q] * rc[q];
+              s1 += rj[q + 1] * rc[q + 1];
+            }
+            if (qb & 1) s0 += rj[qb - 1] * rc[qb - 1];
+            v = (a - (s0 + s1)) * rinv;
+          }
+          if (c < NBMAX) sh.rblk[c][qb] = v;
+          if (c < nb) Rraw[(int64_t)p * ldr + c] = v;
+          if (c == jp) {
+            ch[j] = true;
+            sh.chosen[c] = 1;
+            sh.pivs[p] = jp;
+          }
+          dj[j] -= v * v;
+        }
+      }
+      if (lane == 0) {
+        sh.fin = fin ? 1 : 0;
+        sh.bp = bp;
+      }
+    }
+    __syncthreads();
+    if (sh.fin) break;
+    // delayed update of S by the group's pivot rows: thread (column c, part)
+    // takes rows part, part + TPC, ... (the same rows across a wave)
+    {
+      const int c = tid % NCOLS, part = tid / NCOLS;
+      if (c < nb && !sh.chosen[c]) {
+        double rc[kPivKB];
+#pragma unroll
+        for (int q = 0; q < kPivKB; ++q) rc[q] = sh.rblk[c][q];
+        constexpr int RU = GS ? 8 : 4;
+        for (int i0 = part; i0 < nb; i0 += RU * TPC) {
+          double a[RU];
+          bool live[RU];
+#pragma unroll
+          for (int u = 0; u < RU; ++u) {
+            const int i = i0 + u * TPC;
+            live[u] = i < nb && !sh.chosen[i];
+            a[u] = S[(int64_t)(live[u] ? i : c) * ld + c];
+          }
+#pragma unroll
+          for (int u = 0; u < RU; ++u) {
+            if (!live[u]) continue;
+            const double* ri = sh.rblk[i0 + u * TPC];
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int q = 0; q < kPivKB; q += 2) {
+              s0 += ri[q] * rc[q];
+              s1 += ri[q + 1] * rc[q + 1];
+            }
+            S[(int64_t)(i0 + u * TPC) * ld + c] = a[u] - (s0 + s1);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const int bp = sh.bp;
+  // the remaining columns after the kept ones, in increasing order
+  if (wv == 0) {
+    int base = bp;
+    for (int c0 = 0; c0 < nb; c0 += 64) {
+      const int c = c0 + lane;
+      const bool rest = c < nb && !sh.chosen[c];
+      const unsigned long long mask = __ballot(rest);
+      const int pos = __popcll(mask & ((1ull << lane) - 1ull));
+      if (rest) sh.pivs[base + pos] = c;
+      base += __popcll(mask);
+    }
+    if (lane == 0) *bprime_out = bp;
   }
   __syncthreads();
   if (tid < nb) piv[tid] = sh.pivs[tid];
-  // R11 in pivoted order, zero outside the leading b' x b' upper triangle
-  for (int e = tid; e < nb_host * nb_host; e += kPivThreads) {
-    const int a = e / nb_host, c = e - a * nb_host;
-    double v = 0.0;
-    if (a < bp && c >= a && c < nb) v = Rraw[(int64_t)a * ldr + sh.pivs[c]];
-    Rp[(int64_t)a * ldp + c] = v;
+  // R11 in pivoted order, zero outside the leading b' x b' upper triangle:
+  // thread (column c, part) fills rows part, part + TPC2, ... of column c,
+  // eight rows' loads before their stores
+  {
+    constexpr int TPC2 = kPivThreads / NCOLS;
+    const int c = tid % NCOLS, part = tid / NCOLS;
+    if (c < nb_host) {
+      const int pc = c < nb ? sh.pivs[c] : 0;
+      for (int a0 = part; a0 < nb_host; a0 += 8 * TPC2) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int a = a0 + u * TPC2;
+          const int ar = min(a, bp > 0 ? bp - 1 : 0);
+          x[u] = Rraw[(int64_t)ar * ldr + pc];
+          x[u] = (a < bp && c >= a && c < nb) ? x[u] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (a0 + u * TPC2 < nb_host) Rp[(int64_t)(a0 + u * TPC2) * ldp + c] = x[u];
+      }
+    }
   }
   __syncthreads();
 }
