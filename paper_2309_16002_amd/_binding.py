@@ -180,7 +180,7 @@ def _check_matrix(X):
 
 
 def make_options(k_max=0, tau_b=0.0, fixed_rank=False, greedy=False, precision="native",
-                 theta=0.0, w_refine=1, profile=False):
+                 theta=0.0, w_refine=-1, profile=False):
     o = rbrp_options()
     lib().rbrp_default_options(ctypes.byref(o))
     o.tau_b = float(tau_b)

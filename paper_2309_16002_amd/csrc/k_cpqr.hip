@@ -105,28 +105,39 @@ __global__ __launch_bounds__(kPivThreads) void k_chol_reorth(
 // diagonal and its leading b' x b' part is R^{-1}.  Output (nb_host x
 // nb_host, stride ldx): X, or X^T with trans, there and zero elsewhere.
 // With run_flag the kernel does nothing unless *run_flag != 0.
+// Batched form (bcount null): workgroup g inverts the diagonal block of
+// order min(nb_host, ntot - g nb_host) that starts at row and column
+// g nb_host; with rtrans the block is read transposed (R(r, c) = R[c][r]: the
+// upper triangular transpose of a lower triangular block).
 __global__ __launch_bounds__(256) void k_tri_inv_blocked(
     const double* __restrict__ R, int64_t ldr, const int32_t* __restrict__ bcount,
     int32_t nb_host, double* __restrict__ X, int64_t ldx, int trans,
-    const int32_t* __restrict__ run_flag) {
+    const int32_t* __restrict__ run_flag, int rtrans, int32_t ntot) {
   if (run_flag && *run_flag == 0) return;
   __shared__ double Bd[16][16][17];  // diagonal blocks of R, then their inverses
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int l16 = lane & 15, lhi = lane >> 4;
-  const int bp = min(*bcount, nb_host);
+  const int64_t boff = (int64_t)blockIdx.x * nb_host;
+  R += boff * (ldr + 1);
+  X += boff * (ldx + 1);
+  const int bp = bcount ? min(*bcount, nb_host) : min(nb_host, ntot - (int)boff);
+  const int nbh = bcount ? nb_host : bp;   // order of the output block
   const int nbk = (bp + 15) >> 4;
+  auto rat = [&](int r, int c) -> double {
+    return rtrans ? R[(int64_t)c * ldr + r] : R[(int64_t)r * ldr + c];
+  };
   auto xoff = [&](int r, int c) -> int64_t {
     return trans ? (int64_t)c * ldx + r : (int64_t)r * ldx + c;
   };
-  for (int e = tid; e < nb_host * nb_host; e += 256) {
-    const int r = e / nb_host, c = e - r * nb_host;
+  for (int e = tid; e < nbh * nbh; e += 256) {
+    const int r = e / nbh, c = e - r * nbh;
     if (!((r >> 4) <= (c >> 4) && (c >> 4) < nbk)) X[xoff(r, c)] = 0.0;
   }
   for (int e = tid; e < nbk * 256; e += 256) {
     const int k = e >> 8, r = (e >> 4) & 15, c = e & 15;
     const int gr = 16 * k + r, gc = 16 * k + c;
     double v;
-    if (gr < bp && gc < bp) v = c >= r ? R[(int64_t)gr * ldr + gc] : 0.0;
+    if (gr < bp && gc < bp) v = c >= r ? rat(gr, gc) : 0.0;
     else v = r == c ? 1.0 : 0.0;
     Bd[k][r][c] = v;
   }
@@ -149,7 +160,7 @@ __global__ __launch_bounds__(256) void k_tri_inv_blocked(
     for (int i = 0; i < 16; ++i) {
       Bd[kd][i][jd] = x[i];
       const int gr = 16 * kd + i, gc = 16 * kd + jd;
-      if (gr < nb_host && gc < nb_host) X[xoff(gr, gc)] = (gr < bp && gc < bp) ? x[i] : 0.0;
+      if (gr < nbh && gc < nbh) X[xoff(gr, gc)] = (gr < bp && gc < bp) ? x[i] : 0.0;
     }
   }
   __syncthreads();
@@ -169,8 +180,8 @@ __global__ __launch_bounds__(256) void k_tri_inv_blocked(
 #pragma unroll
           for (int s4 = 0; s4 < 4; ++s4) {
             const int kk = 4 * s4 + lhi;
-            av[u][s4] = R[(int64_t)(16 * i + l16) * ldr + min(16 * l + kk, bp - 1)];
-            bv[u][s4] = X[xoff(16 * l + kk, min(bc, nb_host - 1))];
+            av[u][s4] = rat(16 * i + l16, min(16 * l + kk, bp - 1));
+            bv[u][s4] = X[xoff(16 * l + kk, min(bc, nbh - 1))];
           }
         }
 #pragma unroll
@@ -189,7 +200,7 @@ __global__ __launch_bounds__(256) void k_tri_inv_blocked(
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) {
         const int kk = 4 * s4 + lhi;
-        const double a = (16 * j + kk < bp) ? R[(int64_t)(16 * i + l16) * ldr + min(16 * j + kk, bp - 1)] : 0.0;
+        const double a = (16 * j + kk < bp) ? rat(16 * i + l16, min(16 * j + kk, bp - 1)) : 0.0;
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Bd[j][kk][l16], acc, 0, 0, 0);
       }
       d4v_t out = {0.0, 0.0, 0.0, 0.0};
@@ -200,7 +211,7 @@ __global__ __launch_bounds__(256) void k_tri_inv_blocked(
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int gr = 16 * i + lhi + 4 * q, gc = 16 * j + l16;
-        if (gc < nb_host) X[xoff(gr, gc)] = gc < bp ? -out[q] : 0.0;
+        if (gc < nbh) X[xoff(gr, gc)] = gc < bp ? -out[q] : 0.0;
       }
     }
     __syncthreads();
@@ -316,7 +327,19 @@ hipError_t launch_tri_inv(const double* R, int64_t ldr, const int32_t* bcount, i
                           hipStream_t s) {
   if (nb_host <= 0 || nb_host > kMaxB) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_tri_inv_blocked, dim3(1), dim3(256), 0, s, R, ldr, bcount, nb_host, X,
-                     ldx, trans, run_flag);
+                     ldx, trans, run_flag, 0, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_lower_diag_inv(const double* L, int64_t ldl, int64_t n, int32_t nbs, double* X,
+                                 int64_t ldx, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (nbs <= 0 || nbs > kMaxB || n > INT32_MAX) return hipErrorInvalidValue;
+  // the transpose of each diagonal block is upper triangular; writing the
+  // inverse of that transpose transposed gives the block's own inverse
+  hipLaunchKernelGGL(k_tri_inv_blocked, dim3((unsigned)ceil_div(n, (int64_t)nbs)), dim3(256), 0,
+                     s, L, ldl, (const int32_t*)nullptr, nbs, X, ldx, 1,
+                     (const int32_t*)nullptr, 1, (int32_t)n);
   return hipGetLastError();
 }
 

@@ -8,6 +8,8 @@
 // 2x2 tiles of v_mfma_f64_16x16x4f64.  Lane layout of that instruction
 // (measured on gfx950): lane l supplies A[l%16][l/16] and B[l/16][l%16] and
 // receives D[l/16 + 4q][l%16] for q = 0..3.
+#include <type_traits>
+
 #include "rbrp_internal.h"
 
 namespace rbrp {
@@ -411,11 +413,11 @@ hipError_t launch_gemm_tn_small(int64_t M, int64_t N, int64_t K, double alpha,
 
 namespace rbrp {
 
-// C = alpha A B + beta Cin for tall A (M >> N, K): the three products of the
-// interpolation-matrix solve, W = L L_1^{-1} and its refinement
-// W += (L - W L_1) L_1^{-1} (Alg. 3).  A is M x K row-major (FP32 factor or
-// FP64), B is K x N FP64 and may be lower triangular (then column tile j
-// only reads K rows >= 64 j).
+// C = alpha A B + beta Cin for tall A (M >> N, K): the residual L - W L_1
+// of a refinement step of the interpolation-matrix solve (Alg. 3), and the
+// tiles of the blocked substitution below.  A is M x K row-major (FP32
+// factor or FP64), B is K x N FP64 and may be lower triangular (then column
+// tile j only reads K rows >= 64 j).
 //
 // 128 x 64 output tile per workgroup; four waves each own 64 x 32 of it as
 // 4 x 2 tiles of v_mfma_f64_16x16x4f64.  K goes through double-buffered LDS
@@ -434,14 +436,196 @@ namespace rbrp {
 constexpr int TB_M = 128;
 constexpr int TA_LD = TB_M + 16;  // row stride: 16 doubles = half the banks
 
-template <typename TA, int TB_K, int TB_N>
+template <typename TA, int TB_K, int TB_N, typename TD>
 struct TallStage {
   static constexpr int NA = TB_M * TB_K / 256, NB = TB_N * TB_K / 256;
   static constexpr int VW = 16 / sizeof(TA), NAV = NA / VW;
+  static constexpr int VWD = 16 / sizeof(TD), NDV = NA / VWD;
   typedef TA av_t __attribute__((ext_vector_type(VW)));
+  typedef TD dv_t __attribute__((ext_vector_type(VWD)));
   av_t a[NAV];
+  dv_t d[NDV];   // the same A elements when a step reads them from D
   double b[NB];
 };
+
+// One TB_M x TB_N tile of C = alpha A B + beta Cin: rows i0.., columns j0..,
+// K from kbeg to K.  Shared by the tall GEMM and the blocked triangular solve
+// below (which passes the same array as A and C: every load of A that a tile
+// uses completes before the tile's first store, and the pointers here are not
+// restrict-qualified).  When D is given, the K steps below kd_end take their
+// A elements from D (same rows and columns, leading dimension ldd, type TD)
+// instead of A; the step bounds are multiples of TB_K, so a step reads one
+// source only.
+template <typename TA, bool VA, typename TC, int TB_K, int TB_N, typename TD = TA>
+__device__ __forceinline__ void tall_tile(
+    int64_t i0, int64_t j0, int64_t kbeg, int64_t M, int64_t N, int64_t K, double alpha,
+    const TA* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+    int64_t ldc, const TC* Cin, int64_t ldcin, double (*As)[TB_K][TA_LD],
+    double (*Bs)[TB_K][TB_N + 16], const TD* D = nullptr, int64_t ldd = 0,
+    int64_t kd_end = 0) {
+  typedef TallStage<TA, TB_K, TB_N, TD> St;
+  constexpr int NA = St::NA, NB = St::NB, VW = St::VW, NAV = St::NAV;
+  constexpr int VWD = St::VWD, NDV = St::NDV;
+  typedef typename St::dv_t dv_t;
+  constexpr int WN = TB_N / 32;       // 16-column MFMA tiles per wave (2 x 2 waves)
+  typedef typename St::av_t av_t;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wy = w >> 1, wx = w & 1;
+  // VA staging: A row ai, NA consecutive k from ak.  Element staging: K
+  // column ke of rows re + RS q.  B: k row bk, NB columns from bj.
+  constexpr int RS = 256 / TB_K;
+  const int ai = tid >> 1, ak = (tid & 1) * NA;
+  const int ke = tid % TB_K, re = tid / TB_K;
+  const int bk = tid / (TB_N / NB), bj = (tid % (TB_N / NB)) * NB;
+  d4v acc[4][WN];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < WN; ++b) acc[a][b] = (d4v){0.0, 0.0, 0.0, 0.0};
+  const int64_t ga = i0 + ai;
+  const TA* ap = A + (ga < M ? ga : M - 1) * lda;
+  const TD* dp = D ? D + (ga < M ? ga : M - 1) * ldd : nullptr;
+  const int64_t gbj = j0 + bj;
+  const bool dsrc_any = D != nullptr;
+
+  auto fetch = [&](St& st, int64_t k0) {
+    const bool dsrc = dsrc_any && k0 < kd_end;
+    if constexpr (VA && std::is_same<TD, TA>::value) {
+      // one register set: only the row pointer changes with the source
+      const TA* rp = dsrc ? dp : ap;
+#pragma unroll
+      for (int v = 0; v < NAV; ++v)
+        st.a[v] = *reinterpret_cast<const av_t*>(rp + k0 + ak + v * VW);
+    } else if constexpr (VA) {
+      if (dsrc) {
+#pragma unroll
+        for (int v = 0; v < NDV; ++v)
+          st.d[v] = *reinterpret_cast<const dv_t*>(dp + k0 + ak + v * VWD);
+      } else {
+#pragma unroll
+        for (int v = 0; v < NAV; ++v)
+          st.a[v] = *reinterpret_cast<const av_t*>(ap + k0 + ak + v * VW);
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < NAV; ++v)
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+          const int64_t row = i0 + re + RS * (v * VW + e);
+          const int64_t kk = k0 + ke;
+          const int64_t rc = row < M ? row : M - 1, kc = kk < K ? kk : K - 1;
+          st.a[v][e] = dsrc ? (TA)D[rc * ldd + kc] : A[rc * lda + kc];
+        }
+    }
+    const int64_t gk = (k0 + bk < K) ? k0 + bk : K - 1;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int64_t gj = (gbj + q < N) ? gbj + q : N - 1;
+      st.b[q] = B[gk * ldb + gj];
+    }
+  };
+  auto stash = [&](const St& st, int buf, int64_t k0) {
+    const bool dsrc = VA && !std::is_same<TD, TA>::value && dsrc_any && k0 < kd_end;
+#pragma unroll
+    for (int v = 0; v < NAV; ++v)
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        const int q = v * VW + e;
+        const double xv = dsrc ? (double)st.d[q / VWD][q % VWD] : (double)st.a[v][e];
+        if constexpr (VA)
+          As[buf][ak + q][ai] = (k0 + ak + q < K) ? xv : 0.0;
+        else
+          As[buf][ke][re + RS * q] = (k0 + ke < K) ? xv : 0.0;
+      }
+    const bool krow = k0 + bk < K;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) Bs[buf][bk][bj + q] = krow ? st.b[q] : 0.0;
+  };
+  auto mma = [&](int buf) {
+#pragma unroll
+    for (int ks = 0; ks < TB_K / 4; ++ks) {
+      const int kr = 4 * ks + (lane >> 4);
+      double av[4], bv[WN];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[buf][kr][64 * wy + 16 * a + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < WN; ++b) bv[b] = Bs[buf][kr][(TB_N / 2) * wx + 16 * b + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < WN; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+  };
+
+  // K steps kbeg + t TB_K, t < nt.  At the top of step t, LDS buffer t%2
+  // holds step t and register set (t+1)%2 holds step t+1.  Loads and
+  // stores run unconditionally (steps past the end re-load the last one
+  // into a buffer that is not read again), so the loop body has no
+  // branches and each wait covers exactly the older register set.
+  const int64_t nt = (K > kbeg) ? ceil_div(K - kbeg, TB_K) : 0;
+  if (nt > 0) {
+    auto kstep = [&](int64_t t) { return kbeg + (t < nt ? t : nt - 1) * TB_K; };
+    St s0, s1;
+    fetch(s0, kbeg);
+    fetch(s1, kstep(1));
+    stash(s0, 0, kbeg);
+    __syncthreads();
+    int64_t t = 0;
+    // The scheduling barriers keep every MFMA of a step ahead of the wait
+    // for the registers it stashes, so that each fetch has two steps of
+    // MFMA work to arrive in.
+    for (; t + 2 <= nt; t += 2) {
+      // even step t: LDS 0, registers s1 = step t+1; s0 is free
+      fetch(s0, kstep(t + 2));
+      mma(0);
+      __builtin_amdgcn_sched_barrier(0);
+      stash(s1, 1, kstep(t + 1));
+      __syncthreads();
+      // odd step t+1: LDS 1, registers s0 = step t+2; s1 is free
+      fetch(s1, kstep(t + 3));
+      mma(1);
+      __builtin_amdgcn_sched_barrier(0);
+      stash(s0, 0, kstep(t + 2));
+      __syncthreads();
+    }
+    if (t < nt) mma(0);  // nt odd: the last step sits in LDS 0
+  }
+
+  // epilogue, one 16-row group of MFMA tiles at a time: its C-input loads
+  // first (clamped, unconditional), then its stores, so that the loads of a
+  // lane overlap instead of each waiting for the previous one
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    double cin[4][WN];
+    if (beta != 0.0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t gi = min(i0 + 64 * wy + 16 * a + (lane >> 4) + 4 * q, M - 1);
+#pragma unroll
+        for (int b = 0; b < WN; ++b) {
+          const int64_t gj = min(j0 + (TB_N / 2) * wx + 16 * b + (lane & 15), N - 1);
+          cin[q][b] = Cin ? (double)Cin[gi * ldcin + gj] : C[gi * ldc + gj];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t gi = i0 + 64 * wy + 16 * a + (lane >> 4) + 4 * q;
+      if (gi >= M) continue;
+#pragma unroll
+      for (int b = 0; b < WN; ++b) {
+        const int64_t gj = j0 + (TB_N / 2) * wx + 16 * b + (lane & 15);
+        if (gj < N) {
+          double v = alpha * acc[a][b][q];
+          if (beta != 0.0) v += beta * cin[q][b];
+          C[gi * ldc + gj] = v;
+        }
+      }
+    }
+  }
+}
 
 template <typename TA, bool VA, typename TC, int TB_K, int WPE, int TB_N>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_gemm_tall(
@@ -449,13 +633,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     const double* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C,
     int64_t ldc, const TC* __restrict__ Cin, int64_t ldcin, int64_t nrt, int64_t nct,
     int xcd_map, int b_lower_tri) {
-  typedef TallStage<TA, TB_K, TB_N> St;
-  constexpr int NA = St::NA, NB = St::NB, VW = St::VW, NAV = St::NAV;
-  constexpr int TBB_LD = TB_N + 16;
-  constexpr int WN = TB_N / 32;       // 16-column MFMA tiles per wave (2 x 2 waves)
-  typedef typename St::av_t av_t;
   __shared__ double As[2][TB_K][TA_LD];
-  __shared__ double Bs[2][TB_K][TBB_LD];
+  __shared__ double Bs[2][TB_K][TB_N + 16];
   int64_t r, c;
   {
     const uint32_t id = blockIdx.x, nc = (uint32_t)nct;
@@ -469,150 +648,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     }
   }
   if (r >= nrt) return;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wy = w >> 1, wx = w & 1;
-  // VA staging: A row ai, NA consecutive k from ak.  Element staging: K
-  // column ke of rows re + RS q.  B: k row bk, NB columns from bj.
-  constexpr int RS = 256 / TB_K;
-  const int ai = tid >> 1, ak = (tid & 1) * NA;
-  const int ke = tid % TB_K, re = tid / TB_K;
-  const int bk = tid / (TB_N / NB), bj = (tid % (TB_N / NB)) * NB;
+  const int64_t i0 = r * TB_M, j0 = c * TB_N;
+  // a lower-triangular B has B[k][j] = 0 for k < j
+  const int64_t kbeg = b_lower_tri ? (j0 / TB_K) * TB_K : 0;
+  tall_tile<TA, VA, TC, TB_K, TB_N>(i0, j0, kbeg, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                                    Cin, ldcin, As, Bs);
+}
 
-  {
-    const int64_t i0 = r * TB_M, j0 = c * TB_N;
-    d4v acc[4][WN];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < WN; ++b) acc[a][b] = (d4v){0.0, 0.0, 0.0, 0.0};
-    const int64_t ga = i0 + ai;
-    const TA* ap = A + (ga < M ? ga : M - 1) * lda;
-    const int64_t gbj = j0 + bj;
-
-    auto fetch = [&](St& st, int64_t k0) {
-      if constexpr (VA) {
-#pragma unroll
-        for (int v = 0; v < NAV; ++v)
-          st.a[v] = *reinterpret_cast<const av_t*>(ap + k0 + ak + v * VW);
-      } else {
-#pragma unroll
-        for (int v = 0; v < NAV; ++v)
-#pragma unroll
-          for (int e = 0; e < VW; ++e) {
-            const int64_t row = i0 + re + RS * (v * VW + e);
-            const int64_t kk = k0 + ke;
-            st.a[v][e] = A[(row < M ? row : M - 1) * lda + (kk < K ? kk : K - 1)];
-          }
-      }
-      const int64_t gk = (k0 + bk < K) ? k0 + bk : K - 1;
-#pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const int64_t gj = (gbj + q < N) ? gbj + q : N - 1;
-        st.b[q] = B[gk * ldb + gj];
-      }
-    };
-    auto stash = [&](const St& st, int buf, int64_t k0) {
-#pragma unroll
-      for (int v = 0; v < NAV; ++v)
-#pragma unroll
-        for (int e = 0; e < VW; ++e) {
-          const int q = v * VW + e;
-          const double xv = (double)st.a[v][e];
-          if constexpr (VA)
-            As[buf][ak + q][ai] = (k0 + ak + q < K) ? xv : 0.0;
-          else
-            As[buf][ke][re + RS * q] = (k0 + ke < K) ? xv : 0.0;
-        }
-      const bool krow = k0 + bk < K;
-#pragma unroll
-      for (int q = 0; q < NB; ++q) Bs[buf][bk][bj + q] = krow ? st.b[q] : 0.0;
-    };
-    auto mma = [&](int buf) {
-#pragma unroll
-      for (int ks = 0; ks < TB_K / 4; ++ks) {
-        const int kr = 4 * ks + (lane >> 4);
-        double av[4], bv[WN];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) av[a] = As[buf][kr][64 * wy + 16 * a + (lane & 15)];
-#pragma unroll
-        for (int b = 0; b < WN; ++b) bv[b] = Bs[buf][kr][(TB_N / 2) * wx + 16 * b + (lane & 15)];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < WN; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
-      }
-    };
-
-    // K steps kbeg + t TB_K, t < nt.  At the top of step t, LDS buffer t%2
-    // holds step t and register set (t+1)%2 holds step t+1.  Loads and
-    // stores run unconditionally (steps past the end re-load the last one
-    // into a buffer that is not read again), so the loop body has no
-    // branches and each wait covers exactly the older register set.
-    int64_t kbeg = 0;
-    if (b_lower_tri) kbeg = (j0 / TB_K) * TB_K;  // B[k][j] = 0 for k < j
-    const int64_t nt = (K > kbeg) ? ceil_div(K - kbeg, TB_K) : 0;
-    if (nt > 0) {
-      auto kstep = [&](int64_t t) { return kbeg + (t < nt ? t : nt - 1) * TB_K; };
-      St s0, s1;
-      fetch(s0, kbeg);
-      fetch(s1, kstep(1));
-      stash(s0, 0, kbeg);
-      __syncthreads();
-      int64_t t = 0;
-      // The scheduling barriers keep every MFMA of a step ahead of the wait
-      // for the registers it stashes, so that each fetch has two steps of
-      // MFMA work to arrive in.
-      for (; t + 2 <= nt; t += 2) {
-        // even step t: LDS 0, registers s1 = step t+1; s0 is free
-        fetch(s0, kstep(t + 2));
-        mma(0);
-        __builtin_amdgcn_sched_barrier(0);
-        stash(s1, 1, kstep(t + 1));
-        __syncthreads();
-        // odd step t+1: LDS 1, registers s0 = step t+2; s1 is free
-        fetch(s1, kstep(t + 3));
-        mma(1);
-        __builtin_amdgcn_sched_barrier(0);
-        stash(s0, 0, kstep(t + 2));
-        __syncthreads();
-      }
-      if (t < nt) mma(0);  // nt odd: the last step sits in LDS 0
-    }
-
-    // epilogue, one 16-row group of MFMA tiles at a time: its C-input loads
-    // first (clamped, unconditional), then its stores, so that the loads of a
-    // lane overlap instead of each waiting for the previous one
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      double cin[4][WN];
-      if (beta != 0.0) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int64_t gi = min(i0 + 64 * wy + 16 * a + (lane >> 4) + 4 * q, M - 1);
-#pragma unroll
-          for (int b = 0; b < WN; ++b) {
-            const int64_t gj = min(j0 + (TB_N / 2) * wx + 16 * b + (lane & 15), N - 1);
-            cin[q][b] = Cin ? (double)Cin[gi * ldcin + gj] : C[gi * ldc + gj];
-          }
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t gi = i0 + 64 * wy + 16 * a + (lane >> 4) + 4 * q;
-        if (gi >= M) continue;
-#pragma unroll
-        for (int b = 0; b < WN; ++b) {
-          const int64_t gj = j0 + (TB_N / 2) * wx + 16 * b + (lane & 15);
-          if (gj < N) {
-            double v = alpha * acc[a][b][q];
-            if (beta != 0.0) v += beta * cin[q][b];
-            C[gi * ldc + gj] = v;
-          }
-        }
-      }
-    }
+// Blocked substitution for W L_1 = L_2 (Alg. 3, lower-triangular L_1), one
+// TB_M-row strip of W per workgroup, in place: the 64-wide column blocks J
+// of W are formed from the last to the first as
+//   W(:, J) = L_2(:, J) D_J^{-1} + sum_{I > J} W(:, I) Bt(I, J),
+//   Bt(J, J) = D_J^{-1},  Bt(I, J) = -L_1(I, J) D_J^{-1} (I > J),
+// with D_J the diagonal block of L_1: one tile whose first 64 K rows read
+// L_2(:, J) from L (FP32 entries widened exactly) and the rest the finished
+// blocks of W.  Without L, W itself holds L_2 (block J is read before it is
+// overwritten).  Rows of one strip never depend on other rows, so no
+// workgroup waits for another; the tiles of one workgroup are ordered by the
+// barrier after each tile (its stores are then visible to the workgroup).
+template <typename TL, bool VA, int TB_K, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_trsm_tall(
+    int64_t M, int64_t K, const TL* __restrict__ L, int64_t ldl, const double* __restrict__ Bt,
+    int64_t ldb, double* W, int64_t ldw) {
+  constexpr int TBJ = 64;
+  __shared__ double As[2][TB_K][TA_LD];
+  __shared__ double Bs[2][TB_K][TBJ + 16];
+  const int64_t i0 = (int64_t)blockIdx.x * TB_M;
+  for (int64_t J = ceil_div(K, (int64_t)TBJ) - 1; J >= 0; --J) {
+    tall_tile<double, VA, double, TB_K, TBJ, TL>(i0, TBJ * J, TBJ * J, M, K, K, 1.0, W, ldw, Bt,
+                                                 ldb, 0.0, W, ldw, (const double*)nullptr, 0, As,
+                                                 Bs, L, ldl, TBJ * (J + 1));
+    __syncthreads();
   }
 }
 
@@ -668,6 +734,34 @@ static hipError_t gemm_typed(int64_t M, int64_t N, int64_t K, double alpha, cons
   return hipGetLastError();
 }
 
+
+template <typename TL, bool VA>
+static void trsm_typed(int64_t M, int64_t K, const TL* L, int64_t ldl, const double* Bt,
+                       double* W, int64_t ldw, hipStream_t s) {
+  hipLaunchKernelGGL((k_trsm_tall<TL, VA, 8, 3>), dim3((unsigned)ceil_div(M, TB_M)), dim3(256),
+                     0, s, M, K, L, ldl, Bt, K, W, ldw);
+}
+
+hipError_t launch_trsm_tall(int64_t M, int64_t K, const void* L, int l_f32, int64_t ldl,
+                            const double* Bt, double* W, int64_t ldw, hipStream_t s) {
+  if (M <= 0 || K <= 0) return hipSuccess;
+  // vector loads: 16-byte aligned rows of W (and of L when given) that
+  // extend to whole K steps
+  const int64_t kr = round_up(K, (int64_t)8);
+  bool vec = (reinterpret_cast<uintptr_t>(W) % 16 == 0) && (ldw % 2 == 0) && ldw >= kr;
+  if (L) {
+    const int64_t vw = l_f32 ? 4 : 2;
+    vec = vec && (reinterpret_cast<uintptr_t>(L) % 16 == 0) && (ldl % vw == 0) && ldl >= kr;
+  }
+  if (l_f32) {
+    if (vec) trsm_typed<float, true>(M, K, (const float*)L, ldl, Bt, W, ldw, s);
+    else trsm_typed<float, false>(M, K, (const float*)L, ldl, Bt, W, ldw, s);
+  } else {
+    if (vec) trsm_typed<double, true>(M, K, (const double*)L, ldl, Bt, W, ldw, s);
+    else trsm_typed<double, false>(M, K, (const double*)L, ldl, Bt, W, ldw, s);
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_gemm_tall(int64_t M, int64_t N, int64_t K, double alpha, const void* A,
                             int a_f32, int64_t lda, const double* B, int64_t ldb, double beta,

@@ -37,6 +37,7 @@ struct Plan {
   int native_mode;   // deflation mode of the NATIVE precision
   bool bf16;
   bool r_f64;
+  int32_t refine;    // refinement steps of the W solve
 };
 
 struct Work {
@@ -76,7 +77,7 @@ void fill_defaults(rbrp_options* o) {
   o->fixed_rank = 0;
   o->greedy = 0;
   o->precision = RBRP_PREC_NATIVE;
-  o->w_refine = 1;
+  o->w_refine = -1;
   o->theta = 0.0;
 }
 
@@ -101,6 +102,9 @@ bool make_plan(rbrp_dtype dt, int64_t m, int64_t n, int32_t b, const rbrp_option
   p->bf16 = o.precision == RBRP_PREC_BF16;
   p->r_f64 = dt == RBRP_F64;
   p->native_mode = p->r_f64 ? kModeF64 : kModeF32;
+  // FP32 input: the factor L is FP32, so the FP64 substitution is already
+  // far below its rounding and a refinement step would not change W visibly
+  p->refine = o.w_refine < 0 ? (p->r_f64 ? 1 : 0) : o.w_refine;
   p->ntiles = scan_num_tiles(m);
   const int64_t a = norms_num_partials(p->mr), c = deflate_num_partials(p->mr);
   p->nparts = a > c ? a : c;
@@ -138,7 +142,7 @@ size_t layout(const Plan& p, char* base, Work* w) {
   w->fragB1 = cv.take<char>(frag_bytes(mode, p.ldr, p.bdef));
   w->fragA2 = cv.take<char>(frag_bytes(mode, p.ldr, p.bdef));
   w->L = cv.take<char>((size_t)p.m * p.ldl * rs);
-  w->interp = cv.take<double>(interp_workspace_doubles(p.m, p.k_max));
+  w->interp = cv.take<double>(interp_workspace_doubles(p.m, p.k_max, p.refine));
   return cv.off + kAlign;
 }
 
@@ -277,7 +281,7 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
   if (!h) return RBRP_E_HIP;
   const double tau_b = o.tau_b > 0.0 ? o.tau_b : 1.0 / b;
   const double theta = o.theta > 0.0 ? o.theta : 25.0 * eps;
-  const int refine = o.w_refine < 0 ? 1 : o.w_refine;
+  const int refine = p.refine;
   const int64_t k_max = p.k_max;
   const int64_t ldr = p.ldr;
   rbrp_stats st;

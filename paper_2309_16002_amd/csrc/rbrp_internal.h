@@ -105,6 +105,11 @@ hipError_t launch_gemm_f64(int transA, int transB, int64_t M, int64_t N,
 // C = alpha A B + beta Cin (A, B FP64 row-major; Cin FP32 or FP64, own ld).
 // C = alpha A B + beta Cin (Cin == nullptr: C itself) for tall A (m x K, FP32
 // or FP64, row-major) and FP64 B (K x N), B optionally lower triangular.
+// W L_1 = L_2 by blocked substitution, in place in W (m x K, ldw): W starts
+// as a copy of L (FP32 when l_f32) unless L is null; Bt holds D_J^{-1} on the
+// 64 x 64 diagonal blocks and -L_1(I, J) D_J^{-1} below them (K x K, ld K).
+hipError_t launch_trsm_tall(int64_t M, int64_t K, const void* L, int l_f32, int64_t ldl,
+                            const double* Bt, double* W, int64_t ldw, hipStream_t s);
 hipError_t launch_gemm_tall(int64_t M, int64_t N, int64_t K, double alpha, const void* A,
                             int a_f32, int64_t lda, const double* B, int64_t ldb, double beta,
                             const void* Cin, int cin_f32, int64_t ldcin, double* C,
@@ -124,6 +129,11 @@ hipError_t launch_cpqr_piv(double* G, int64_t ldg, int32_t nb, const int32_t* nb
 hipError_t launch_tri_inv(const double* R, int64_t ldr, const int32_t* bcount, int32_t nb_host,
                           double* X, int64_t ldx, int trans, const int32_t* run_flag,
                           hipStream_t s);
+// Inverses of the nbs x nbs diagonal blocks of the lower-triangular n x n
+// matrix L (the last block may be smaller), written to the same positions of
+// X (the rest of X untouched).
+hipError_t launch_lower_diag_inv(const double* L, int64_t ldl, int64_t n, int32_t nbs, double* X,
+                                 int64_t ldx, hipStream_t s);
 
 // Qt = (R11^{-1})^T V(:, piv)^T: the orthonormal basis rows of the kept
 // columns, p < b'; rows b'..nb_host-1 zero.  Rinv_ws: nb_host^2 doubles.
@@ -191,7 +201,7 @@ size_t frag_bytes(int mode, int64_t ldr, int bmax);
 hipError_t launch_interp(const void* L, int l_f64, int64_t ldl, int64_t m,
                          int64_t k, const int64_t* S, double* W, int64_t ldw,
                          int refine, double* ws, hipStream_t s);
-size_t interp_workspace_doubles(int64_t m, int64_t k);
+size_t interp_workspace_doubles(int64_t m, int64_t k, int refine);
 
 // Deflation arithmetic modes.
 enum DeflateMode { kModeF64 = 0, kModeF32 = 1, kModeBF16x3 = 2, kModeBF16 = 3 };

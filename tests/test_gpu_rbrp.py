@@ -96,6 +96,46 @@ def test_fp64_kmax_capacity_and_fixed_rank(rb):
     assert res.k == 37 and res.S.cpu().tolist() == ref.S
 
 
+@pytest.mark.parametrize("refine", [0, 1, 2])
+def test_fp64_w_solve_refinement_steps(rb, refine):
+    """W by blocked substitution (Alg. 3) over several 64-wide column blocks
+    with a ragged last block: W matches X X_S^+ on the same S with and without
+    refinement steps."""
+    X = svd_matrix(3000, 400, geometric_spectrum(400, 0.97), seed=77)
+    res = _run(rb, X, 1e-4, 32, 2, w_refine=refine)
+    S = res.S.cpu().tolist()
+    assert res.k > 192 and res.k % 64 != 0
+    W = res.W.cpu().numpy()
+    Wref = w_lstsq(X, S)
+    tol = 1e-10 if refine > 0 else 1e-9
+    assert np.linalg.norm(W - Wref) <= tol * np.linalg.norm(Wref)
+    assert np.array_equal(W[S], np.eye(res.k))
+
+
+def test_fp64_w_solve_odd_leading_dimension(rb):
+    """k = k_max = 131 (an odd leading dimension of W: the element-wise load
+    path of the substitution) at fixed rank."""
+    X = svd_matrix(2000, 300, geometric_spectrum(300, 0.98), seed=78)
+    res = _run(rb, X, 1e-12, 16, 3, k_max=131, fixed_rank=True)
+    assert res.k == 131 and res.W.shape[1] == 131
+    S = res.S.cpu().tolist()
+    W = res.W.cpu().numpy()
+    Wref = w_lstsq(X, S)
+    assert np.linalg.norm(W - Wref) <= 1e-10 * np.linalg.norm(Wref)
+    assert np.array_equal(W[S], np.eye(131))
+
+
+def test_fp32_w_refinement_changes_nothing_visible(rb):
+    """FP32 input: the default solve (no refinement step) and one refinement
+    step give the same W to far below the FP32 rounding of L."""
+    X = adversarial_gmm(20000, 500, sub_dim=200, n_comp=20, seed=5)
+    a = _run(rb, X, 1e-3, 64, 4)
+    b = _run(rb, X, 1e-3, 64, 4, w_refine=1)
+    assert a.S.cpu().tolist() == b.S.cpu().tolist()
+    Wa, Wb = a.W.cpu().numpy(), b.W.cpu().numpy()
+    assert np.linalg.norm(Wa - Wb) <= 1e-9 * np.linalg.norm(Wb)
+
+
 def test_zero_matrix(rb):
     res = _run(rb, np.zeros((100, 40)), 1e-2, 8, 1)
     assert res.k == 0
