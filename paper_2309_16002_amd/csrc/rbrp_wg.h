@@ -125,6 +125,28 @@ __device__ __forceinline__ void wg_weights_scan_tile(
   __syncthreads();
 }
 
+// Exclusive count of the set flags before each thread of the workgroup
+// (thread order) by wave ballots; *total gets the count over all threads.
+// wtot: kSampleThreads / 64 ints of LDS.  Called by all threads; contains
+// barriers.
+__device__ __forceinline__ int wg_flag_offset(int f, int32_t* wtot, int* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const unsigned long long bal = __ballot(f != 0);
+  const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+  if (lane == 0) wtot[w] = __popcll(bal);
+  __syncthreads();
+  int base = 0, tot = 0;
+#pragma unroll
+  for (int v = 0; v < kSampleThreads / 64; ++v) {
+    const int c = wtot[v];
+    base += v < w ? c : 0;
+    tot += c;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + pre;
+}
+
 // LDS state of the block sampler (one workgroup of kSampleThreads threads).
 template <int MAXTILES, int MAXB>
 struct SampleShared {
@@ -134,7 +156,7 @@ struct SampleShared {
   int64_t cand[kSampleThreads];
   int32_t flag[kSampleThreads];
   uint64_t red[kSampleThreads];
-  int32_t nacc, npos, total_new;
+  int32_t nacc, npos;
   uint64_t W;
 };
 
@@ -151,7 +173,6 @@ __device__ __forceinline__ void wg_sample(
     int32_t* npos_out, SampleShared<MAXTILES, MAXB>& sh) {
   int32_t& s_nacc = sh.nacc;
   int32_t& s_npos = sh.npos;
-  int32_t& s_total_new = sh.total_new;
   uint64_t& s_W = sh.W;
   uint64_t* tile_excl = sh.tile_excl;
   int64_t* acc_idx = sh.acc_idx;
@@ -162,19 +183,56 @@ __device__ __forceinline__ void wg_sample(
   const int tid = threadIdx.x;
   const int64_t ntiles = ceil_div(m, kScanTile);
 
-  // exclusive prefix of tile totals (serial: ntiles is small)
-  if (tid == 0) {
-    uint64_t run = 0;
-    int npos = 0;
-    for (int64_t T = 0; T < ntiles; ++T) {
+  // exclusive prefix of the tile totals: each thread sums a run of tiles,
+  // wave 0 scans the run sums (four per lane), each thread writes its run
+  {
+    const int64_t per = ceil_div(ntiles, (int64_t)kSampleThreads);
+    const int64_t T0 = tid * per, T1 = min(ntiles, T0 + per);
+    uint64_t rs = 0;
+    int rp = 0;
+    for (int64_t T = T0; T < T1; ++T) {
+      rs += tile_sum[T];
+      rp += tile_pos[T];
+    }
+    red[tid] = rs;
+    flag[tid] = rp;
+    __syncthreads();
+    if (tid < 64) {
+      uint64_t v[4];
+      int np = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        v[u] = red[4 * tid + u];
+        np += flag[4 * tid + u];
+      }
+      const uint64_t mine = v[0] + v[1] + v[2] + v[3];
+      uint64_t incl = mine;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t o = __shfl_up(incl, off, kWave);
+        if (tid >= off) incl += o;
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) np += __shfl_xor(np, off, kWave);
+      uint64_t run = incl - mine;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        red[4 * tid + u] = run;
+        run += v[u];
+      }
+      if (tid == 63) {
+        s_W = incl;
+        s_npos = np;
+        s_nacc = 0;
+      }
+    }
+    __syncthreads();
+    uint64_t run = red[tid];
+    for (int64_t T = T0; T < T1; ++T) {
       tile_excl[T] = run;
       run += tile_sum[T];
-      npos += tile_pos[T];
     }
-    tile_excl[ntiles] = run;
-    s_W = run;
-    s_npos = npos;
-    s_nacc = 0;
+    if (tid == 0) tile_excl[ntiles] = s_W;
   }
   __syncthreads();
   const uint64_t W = s_W;
@@ -189,21 +247,10 @@ __device__ __forceinline__ void wg_sample(
       for (int64_t c0 = r0; c0 < r0 + kScanTile && c0 < m; c0 += kSampleThreads) {
         const int64_t i = c0 + tid;
         const int pos = (i < m && i < r0 + kScanTile) ? (weight_at(cdf_local, i) != 0) : 0;
-        flag[tid] = pos;
-        __syncthreads();
-        if (tid == 0) {
-          int run = nacc;
-          for (int q = 0; q < kSampleThreads; ++q) {
-            const int f = flag[q];
-            flag[q] = run;
-            run += f;
-          }
-          s_total_new = run;
-        }
-        __syncthreads();
-        if (pos) idx[flag[tid]] = i;
-        nacc = s_total_new;
-        __syncthreads();
+        int total;
+        const int off = wg_flag_offset(pos, flag, &total);
+        if (pos) idx[nacc + off] = i;
+        nacc += total;
       }
     }
     if (tid == 0) {
@@ -231,42 +278,49 @@ __device__ __forceinline__ void wg_sample(
         if (tile_excl[mid + 1] > target) hi = mid; else lo = mid + 1;
       }
       const uint64_t local = target - tile_excl[lo];
+      // smallest i of the tile with cdf_local[i] > local (cdf_local[z] is
+      // the tile total, so one exists): eight probes per round, all loaded
+      // before any is compared, shrink [a, z] to a ninth
       int64_t a = lo * kScanTile, z = min(m, (lo + 1) * (int64_t)kScanTile) - 1;
       while (a < z) {
-        const int64_t mid = (a + z) >> 1;
-        if (cdf_local[mid] > local) z = mid; else a = mid + 1;
+        int64_t pr[8];
+        uint64_t pv[8];
+#pragma unroll
+        for (int s8 = 0; s8 < 8; ++s8) {
+          pr[s8] = a + ((s8 + 1) * (z - a)) / 9;
+          pv[s8] = cdf_local[pr[s8]];
+        }
+        int64_t na = a, nz = z;
+#pragma unroll
+        for (int s8 = 0; s8 < 8; ++s8) {
+          if (pv[s8] > local) nz = min(nz, pr[s8]);
+          else na = max(na, pr[s8] + 1);
+        }
+        a = na;
+        z = nz;
       }
       my = a;
     }
     cand[tid] = my;
     __syncthreads();
-    int isnew = 0;
-    if (my >= 0) {
-      isnew = 1;
-      for (int q = 0; q < nacc && isnew; ++q) isnew = acc_idx[q] != my;
-      for (int q = 0; q < tid && isnew; ++q) isnew = cand[q] != my;
-    }
-    flag[tid] = isnew;
-    __syncthreads();
-    if (tid == 0) {
-      int run = 0;
-      for (int q = 0; q < kSampleThreads; ++q) {
-        const int f = flag[q];
-        flag[q] = run;
-        run += f;
-      }
-      s_total_new = run;
-    }
-    __syncthreads();
+    // new if neither accepted before nor drawn by an earlier candidate of
+    // the chunk (every comparison made: no data-dependent exit, so the LDS
+    // reads of a loop are issued back to back)
+    int dup = 0;
+    for (int q = 0; q < nacc; ++q) dup |= acc_idx[q] == my;
+    const int qend = tid | 63;   // the wave's last thread: a uniform bound
+    for (int q = 0; q < qend; ++q) dup |= (q < tid) & (cand[q] == my);
+    const int isnew = my >= 0 && !dup;
+    int total;
+    const int off = wg_flag_offset(isnew, flag, &total);
     if (isnew) {
-      const int p = nacc + flag[tid];
+      const int p = nacc + off;
       if (p < b) {
         acc_idx[p] = my;
         acc_w[p] = weight_at(cdf_local, my);
       }
     }
-    __syncthreads();
-    if (tid == 0) s_nacc = min(b, nacc + s_total_new);
+    if (tid == 0) s_nacc = min(b, nacc + total);
     __syncthreads();
   }
 
