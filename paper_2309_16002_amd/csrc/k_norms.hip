@@ -25,7 +25,11 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-template <typename TX, typename TRr>
+// VEC (FP32 X with 16-byte aligned rows and n a multiple of 4): each lane's
+// four columns are one 16-byte load and one 16-byte store, and all of a
+// row's loads (up to four per lane) are issued before any is used.  The
+// columns each lane accumulates, and their order, are the same either way.
+template <typename TX, typename TRr, bool VEC>
 __global__ __launch_bounds__(256) void k_init_norms(
     const TX* __restrict__ X, int64_t m, int64_t n, int64_t ldx,
     TRr* __restrict__ R, int64_t mr, int64_t ldr, double* __restrict__ d,
@@ -43,22 +47,55 @@ __global__ __launch_bounds__(256) void k_init_norms(
       const bool live = row < m;
       const TX* xr = X + (live ? row : 0) * ldx;
       TRr* rrow = R ? R + row * ldr : nullptr;
-      for (int64_t c = 4 * lane; c < ldr; c += 4 * kWave) {
-        TX v[4];
+      if constexpr (VEC) {
+        typedef float f4_t __attribute__((ext_vector_type(4)));
+        for (int64_t c0 = 4 * lane; c0 < ldr; c0 += 16 * kWave) {
+          f4_t v[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int64_t cc = c + q;
-          v[q] = (live && cc < n) ? xr[cc] : (TX)0;
+          for (int u = 0; u < 4; ++u) {
+            const int64_t c = c0 + u * 4 * kWave;
+            const bool in = live && c < n;
+            v[u] = *reinterpret_cast<const f4_t*>(xr + (in ? c : 0));
+            if (!in) v[u] = (f4_t){0.0f, 0.0f, 0.0f, 0.0f};
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int64_t c = c0 + u * 4 * kWave;
+            if (c >= ldr) break;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const double x = (double)v[u][q];
+              if (!isfinite(x)) bad = 1;
+              acc += x * x;
+            }
+            if (rrow) {
+              if constexpr (sizeof(TRr) == 4) {
+                *reinterpret_cast<f4_t*>(rrow + c) = v[u];
+              } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) rrow[c + q] = (TRr)v[u][q];
+              }
+            }
+          }
         }
+      } else {
+        for (int64_t c = 4 * lane; c < ldr; c += 4 * kWave) {
+          TX v[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const double x = (double)v[q];
-          if (!isfinite(x)) bad = 1;
-          acc += x * x;
-        }
-        if (rrow) {
+          for (int q = 0; q < 4; ++q) {
+            const int64_t cc = c + q;
+            v[q] = (live && cc < n) ? xr[cc] : (TX)0;
+          }
 #pragma unroll
-          for (int q = 0; q < 4; ++q) rrow[c + q] = (TRr)v[q];
+          for (int q = 0; q < 4; ++q) {
+            const double x = (double)v[q];
+            if (!isfinite(x)) bad = 1;
+            acc += x * x;
+          }
+          if (rrow) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) rrow[c + q] = (TRr)v[q];
+          }
         }
       }
     }
@@ -93,20 +130,29 @@ hipError_t launch_init_norms(const void* X, rbrp_dtype dt, int64_t m, int64_t n,
   if (ldr <= 0) ldr = round_up(n, 4);
   if (dt == RBRP_F64) {
     if (r_is_f64 || !R)
-      hipLaunchKernelGGL((k_init_norms<double, double>), dim3(grid), dim3(256), 0, s,
+      hipLaunchKernelGGL((k_init_norms<double, double, false>), dim3(grid), dim3(256), 0, s,
                          (const double*)X, m, n, ldx, (double*)R, mr, ldr, d,
                          part_sum, part_max, nonfinite);
     else
-      hipLaunchKernelGGL((k_init_norms<double, float>), dim3(grid), dim3(256), 0, s,
+      hipLaunchKernelGGL((k_init_norms<double, float, false>), dim3(grid), dim3(256), 0, s,
                          (const double*)X, m, n, ldx, (float*)R, mr, ldr, d,
                          part_sum, part_max, nonfinite);
   } else {
-    if (r_is_f64)
-      hipLaunchKernelGGL((k_init_norms<float, double>), dim3(grid), dim3(256), 0, s,
+    const bool vec = reinterpret_cast<uintptr_t>(X) % 16 == 0 && ldx % 4 == 0 && n % 4 == 0;
+    if (r_is_f64 && vec)
+      hipLaunchKernelGGL((k_init_norms<float, double, true>), dim3(grid), dim3(256), 0, s,
                          (const float*)X, m, n, ldx, (double*)R, mr, ldr, d,
                          part_sum, part_max, nonfinite);
+    else if (r_is_f64)
+      hipLaunchKernelGGL((k_init_norms<float, double, false>), dim3(grid), dim3(256), 0, s,
+                         (const float*)X, m, n, ldx, (double*)R, mr, ldr, d,
+                         part_sum, part_max, nonfinite);
+    else if (vec)
+      hipLaunchKernelGGL((k_init_norms<float, float, true>), dim3(grid), dim3(256), 0, s,
+                         (const float*)X, m, n, ldx, (float*)R, mr, ldr, d,
+                         part_sum, part_max, nonfinite);
     else
-      hipLaunchKernelGGL((k_init_norms<float, float>), dim3(grid), dim3(256), 0, s,
+      hipLaunchKernelGGL((k_init_norms<float, float, false>), dim3(grid), dim3(256), 0, s,
                          (const float*)X, m, n, ldx, (float*)R, mr, ldr, d,
                          part_sum, part_max, nonfinite);
   }
