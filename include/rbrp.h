@@ -66,10 +66,8 @@ typedef struct {
   int32_t greedy;      /* 1: take the b largest residual norms instead of
                           sampling (RBGP, Remark 4.3)                           */
   int32_t precision;   /* rbrp_precision                                         */
-  int32_t w_refine;    /* refinement steps of the W solve; < 0 -> 1 for FP64
-                          input, 0 for FP32 input (rbrp_id: the FP32 factor L
-                          carries rounding far above what the FP64
-                          substitution leaves); rbrp_id_batched: < 0 -> 1    */
+  int32_t w_refine;    /* iterative-refinement steps of the FP64 W solve
+                          (Alg. 3); < 0 -> 1                                  */
   double theta;        /* BF16 mode: split/plain switch; <= 0 -> 25 * eps        */
   int32_t profile;     /* 1: time the phases with HIP events on ``stream`` and
                           report them in rbrp_stats; 2: time only the
@@ -97,7 +95,7 @@ typedef struct {
 } rbrp_stats;
 
 /* Fill *opt with the defaults (tau_b = 1/b, k_max = min(m, n), sampling,
- * NATIVE precision, w_refine = -1: see rbrp_options). */
+ * NATIVE precision, one refinement step of the W solve). */
 void rbrp_default_options(rbrp_options* opt);
 
 /* Bytes of device workspace rbrp_id needs for these arguments (0 when the

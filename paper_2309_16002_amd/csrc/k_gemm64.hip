@@ -413,11 +413,10 @@ hipError_t launch_gemm_tn_small(int64_t M, int64_t N, int64_t K, double alpha,
 
 namespace rbrp {
 
-// C = alpha A B + beta Cin for tall A (M >> N, K): the residual L - W L_1
-// of a refinement step of the interpolation-matrix solve (Alg. 3), and the
-// tiles of the blocked substitution below.  A is M x K row-major (FP32
-// factor or FP64), B is K x N FP64 and may be lower triangular (then column
-// tile j only reads K rows >= 64 j).
+// Tiles of C = alpha A B + beta Cin for tall A (M >> N, K): the blocked
+// substitution of the interpolation-matrix solve (Alg. 3) and its
+// refinement step below.  A is M x K row-major (FP32 factor or FP64), B is
+// K x N FP64.
 //
 // 128 x 64 output tile per workgroup; four waves each own 64 x 32 of it as
 // 4 x 2 tiles of v_mfma_f64_16x16x4f64.  K goes through double-buffered LDS
@@ -455,14 +454,14 @@ struct TallStage {
 // restrict-qualified).  When D is given, the K steps below kd_end take their
 // A elements from D (same rows and columns, leading dimension ldd, type TD)
 // instead of A; the step bounds are multiples of TB_K, so a step reads one
-// source only.
+// source only.  C's column index is shifted by c_off (Cin's is not).
 template <typename TA, bool VA, typename TC, int TB_K, int TB_N, typename TD = TA>
 __device__ __forceinline__ void tall_tile(
     int64_t i0, int64_t j0, int64_t kbeg, int64_t M, int64_t N, int64_t K, double alpha,
     const TA* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
     int64_t ldc, const TC* Cin, int64_t ldcin, double (*As)[TB_K][TA_LD],
     double (*Bs)[TB_K][TB_N + 16], const TD* D = nullptr, int64_t ldd = 0,
-    int64_t kd_end = 0) {
+    int64_t kd_end = 0, int64_t c_off = 0) {
   typedef TallStage<TA, TB_K, TB_N, TD> St;
   constexpr int NA = St::NA, NB = St::NB, VW = St::VW, NAV = St::NAV;
   constexpr int VWD = St::VWD, NDV = St::NDV;
@@ -620,39 +619,11 @@ __device__ __forceinline__ void tall_tile(
         if (gj < N) {
           double v = alpha * acc[a][b][q];
           if (beta != 0.0) v += beta * cin[q][b];
-          C[gi * ldc + gj] = v;
+          C[gi * ldc + gj - c_off] = v;
         }
       }
     }
   }
-}
-
-template <typename TA, bool VA, typename TC, int TB_K, int WPE, int TB_N>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_gemm_tall(
-    int64_t M, int64_t N, int64_t K, double alpha, const TA* __restrict__ A, int64_t lda,
-    const double* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C,
-    int64_t ldc, const TC* __restrict__ Cin, int64_t ldcin, int64_t nrt, int64_t nct,
-    int xcd_map, int b_lower_tri) {
-  __shared__ double As[2][TB_K][TA_LD];
-  __shared__ double Bs[2][TB_K][TB_N + 16];
-  int64_t r, c;
-  {
-    const uint32_t id = blockIdx.x, nc = (uint32_t)nct;
-    if (xcd_map) {
-      const uint32_t x = id & 7u, s = id >> 3;
-      r = (int64_t)(s / nc) * 8 + x;
-      c = s % nc;
-    } else {
-      r = id / nc;
-      c = id % nc;
-    }
-  }
-  if (r >= nrt) return;
-  const int64_t i0 = r * TB_M, j0 = c * TB_N;
-  // a lower-triangular B has B[k][j] = 0 for k < j
-  const int64_t kbeg = b_lower_tri ? (j0 / TB_K) * TB_K : 0;
-  tall_tile<TA, VA, TC, TB_K, TB_N>(i0, j0, kbeg, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
-                                    Cin, ldcin, As, Bs);
 }
 
 // Blocked substitution for W L_1 = L_2 (Alg. 3, lower-triangular L_1), one
@@ -682,58 +653,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
   }
 }
 
-template <typename TA, typename TC, int BK = 8, int WPE = 3, int TB_N = 64>
-static void dispatch_tall(int64_t M, int64_t N, int64_t K, double alpha, const TA* A,
-                          int64_t lda, const double* B, int64_t ldb, double beta, double* C,
-                          int64_t ldc, const TC* Cin, int64_t ldcin, int blt, hipStream_t s) {
-  const int64_t nrt = ceil_div(M, TB_M), nct = ceil_div(N, TB_N);
-  const int xcd = nrt >= 16;
-  const int64_t nblk = (xcd ? round_up(nrt, 8) : nrt) * nct;
-  const int vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) &&
-                  (lda % (int64_t)(16 / sizeof(TA)) == 0) && lda >= round_up(K, BK);
-  if (vec)
-    hipLaunchKernelGGL((k_gemm_tall<TA, true, TC, BK, WPE, TB_N>), dim3((unsigned)nblk), dim3(256),
-                       0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, Cin, ldcin, nrt, nct,
-                       xcd, blt);
-  else
-    hipLaunchKernelGGL((k_gemm_tall<TA, false, TC, BK, WPE, TB_N>), dim3((unsigned)nblk), dim3(256),
-                       0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, Cin, ldcin, nrt, nct,
-                       xcd, blt);
-}
-
-template <typename TA, typename TC>
-struct TallD {
-  static void run(int64_t M, int64_t N, int64_t K, double alpha, const TA* A, int64_t lda,
-                  const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
-                  const TC* Cin, int64_t ldcin, int blt, hipStream_t s) {
-    dispatch_tall<TA, TC>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, Cin, ldcin, blt, s);
+// One step of iterative refinement of W L_1 = L_2 after the substitution
+// above, fused per 128-row strip: with the residual E = L_2 - W L_1 the
+// correction F of F L_1 = E is formed block by block from the last column
+// block to the first as F(:, J) = (E(:, J) - sum_{I > J} F(:, I) L_1(I, J))
+// D_J^{-1}, and W(:, J) += F(:, J) at once.  Since W(:, I) + F(:, I) is
+// then what W(:, I) holds for I > J, both sums fold into one tile over the
+// current W:
+//   T = L_2(:, J) - sum_{I >= J} W(:, I) L_1(I, J),   W(:, J) += T D_J^{-1},
+// with the strip's T in Tws (TB_M x 64 per strip, rows of the strip only).
+// Bt holds D_J^{-1} on its diagonal blocks; L_1 is lower triangular.
+template <typename TL, bool VA, int TB_K, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_trsm_refine(
+    int64_t M, int64_t K, const TL* __restrict__ L, int64_t ldl, const double* __restrict__ L1,
+    const double* __restrict__ Bt, double* W, int64_t ldw, double* __restrict__ Tws) {
+  constexpr int TBJ = 64;
+  __shared__ double As[2][TB_K][TA_LD];
+  __shared__ double Bs[2][TB_K][TBJ + 16];
+  const int64_t i0 = (int64_t)blockIdx.x * TB_M;
+  for (int64_t J = ceil_div(K, (int64_t)TBJ) - 1; J >= 0; --J) {
+    const int64_t j0 = TBJ * J, nb = min((int64_t)TBJ, K - j0);
+    tall_tile<double, VA, TL, TB_K, TBJ>(i0, j0, j0, M, K, K, -1.0, W, ldw, L1, K, 1.0, Tws,
+                                         TBJ, L, ldl, As, Bs, (const double*)nullptr, 0, 0, j0);
+    __syncthreads();
+    tall_tile<double, true, double, TB_K, TBJ>(i0, 0, 0, M, nb, nb, 1.0, Tws, TBJ,
+                                               Bt + j0 * K + j0, K, 1.0, W + j0, ldw, W + j0,
+                                               ldw, As, Bs);
+    __syncthreads();
   }
-};
-
-template <template <typename, typename> class D>
-static hipError_t gemm_typed(int64_t M, int64_t N, int64_t K, double alpha, const void* A,
-                            int a_f32, int64_t lda, const double* B, int64_t ldb, double beta,
-                            const void* Cin, int cin_f32, int64_t ldcin, double* C,
-                            int64_t ldc, int b_lower_tri, hipStream_t s) {
-  if (M <= 0 || N <= 0) return hipSuccess;
-  if (a_f32) {
-    if (cin_f32)
-      D<float, float>::run(M, N, K, alpha, (const float*)A, lda, B, ldb, beta, C, ldc,
-                                  (const float*)Cin, ldcin, b_lower_tri, s);
-    else
-      D<float, double>::run(M, N, K, alpha, (const float*)A, lda, B, ldb, beta, C, ldc,
-                                   (const double*)Cin, ldcin, b_lower_tri, s);
-  } else {
-    if (cin_f32)
-      D<double, float>::run(M, N, K, alpha, (const double*)A, lda, B, ldb, beta, C, ldc,
-                                   (const float*)Cin, ldcin, b_lower_tri, s);
-    else
-      D<double, double>::run(M, N, K, alpha, (const double*)A, lda, B, ldb, beta, C,
-                                    ldc, (const double*)Cin, ldcin, b_lower_tri, s);
-  }
-  return hipGetLastError();
 }
-
 
 template <typename TL, bool VA>
 static void trsm_typed(int64_t M, int64_t K, const TL* L, int64_t ldl, const double* Bt,
@@ -763,12 +711,28 @@ hipError_t launch_trsm_tall(int64_t M, int64_t K, const void* L, int l_f32, int6
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_tall(int64_t M, int64_t N, int64_t K, double alpha, const void* A,
-                            int a_f32, int64_t lda, const double* B, int64_t ldb, double beta,
-                            const void* Cin, int cin_f32, int64_t ldcin, double* C,
-                            int64_t ldc, int b_lower_tri, hipStream_t s) {
-  return gemm_typed<TallD>(M, N, K, alpha, A, a_f32, lda, B, ldb, beta, Cin, cin_f32, ldcin, C,
-                           ldc, b_lower_tri, s);
+template <typename TL, bool VA>
+static void refine_typed(int64_t M, int64_t K, const TL* L, int64_t ldl, const double* L1,
+                         const double* Bt, double* W, int64_t ldw, double* Tws, hipStream_t s) {
+  hipLaunchKernelGGL((k_trsm_refine<TL, VA, 8, 3>), dim3((unsigned)ceil_div(M, TB_M)),
+                     dim3(256), 0, s, M, K, L, ldl, L1, Bt, W, ldw, Tws);
 }
+
+hipError_t launch_trsm_refine(int64_t M, int64_t K, const void* L, int l_f32, int64_t ldl,
+                              const double* L1, const double* Bt, double* W, int64_t ldw,
+                              double* Tws, hipStream_t s) {
+  if (M <= 0 || K <= 0) return hipSuccess;
+  const int64_t kr = round_up(K, (int64_t)8);
+  const bool vec = (reinterpret_cast<uintptr_t>(W) % 16 == 0) && (ldw % 2 == 0) && ldw >= kr;
+  if (l_f32) {
+    if (vec) refine_typed<float, true>(M, K, (const float*)L, ldl, L1, Bt, W, ldw, Tws, s);
+    else refine_typed<float, false>(M, K, (const float*)L, ldl, L1, Bt, W, ldw, Tws, s);
+  } else {
+    if (vec) refine_typed<double, true>(M, K, (const double*)L, ldl, L1, Bt, W, ldw, Tws, s);
+    else refine_typed<double, false>(M, K, (const double*)L, ldl, L1, Bt, W, ldw, Tws, s);
+  }
+  return hipGetLastError();
+}
+
 
 }  // namespace rbrp

@@ -10,8 +10,8 @@
 //      Bt(I, J) = -L_1(I, J) D_J^{-1} (one small MFMA GEMM per block column);
 //   3. W L_1 = L solved in place in W by blocked substitution over the block
 //      columns, from the last to the first (one MFMA tile loop per 128-row
-//      strip); refinement steps solve E L_1 = L - W L_1 the same way and add
-//      E to W;
+//      strip); each refinement step (the residual E = L - W L_1, F L_1 = E,
+//      W += F) is one more pass of the same shape, fused per strip;
 //   4. W(S(j),:) = e_j exactly.
 #include "rbrp_internal.h"
 
@@ -37,21 +37,9 @@ __global__ __launch_bounds__(256) void k_identity_rows(const int64_t* __restrict
   for (int64_t p = threadIdx.x; p < k; p += 256) W[row * ldw + p] = (p == j) ? 1.0 : 0.0;
 }
 
-__global__ void k_add_rows(double* __restrict__ W, int64_t ldw, const double* __restrict__ E,
-                           int64_t lde, int64_t m, int64_t k) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= m * k) return;
-  const int64_t i = e / k, j = e - i * k;
-  W[i * ldw + j] += E[i * lde + j];
-}
-
-// Leading dimension of the m x k FP64 refinement term: rows 16-byte aligned
-// and padded to whole K steps of the tile loop.
-static int64_t interp_ld(int64_t k) { return round_up(k, 16); }
-
 size_t interp_workspace_doubles(int64_t m, int64_t k, int refine) {
-  // L1 and Bt (k x k each), E (m x interp_ld(k), refinement steps only)
-  return (size_t)(2 * k * k + (refine > 0 ? m * interp_ld(k) : 0));
+  // L1 and Bt (k x k each); with refinement a 64-column scratch per row
+  return (size_t)(2 * k * k + (refine > 0 ? round_up(m, 128) * 64 : 0));
 }
 
 hipError_t launch_interp(const void* L, int l_f64, int64_t ldl, int64_t m, int64_t k,
@@ -60,8 +48,7 @@ hipError_t launch_interp(const void* L, int l_f64, int64_t ldl, int64_t m, int64
   if (k <= 0 || m <= 0) return hipSuccess;
   double* L1 = ws;
   double* Bt = L1 + k * k;
-  double* E = Bt + k * k;
-  const int64_t lde = interp_ld(k);
+  double* Tws = Bt + k * k;
   hipError_t e;
   if (l_f64)
     hipLaunchKernelGGL(k_gather_l1<double>, dim3((unsigned)k), dim3(256), 0, s,
@@ -83,13 +70,8 @@ hipError_t launch_interp(const void* L, int l_f64, int64_t ldl, int64_t m, int64
   e = launch_trsm_tall(m, k, L, lf32, ldl, Bt, W, ldw, s);
   if (e != hipSuccess) return e;
   for (int it = 0; it < refine; ++it) {
-    // E = L - W L_1 ; E L_1 = E solved in place ; W += E
-    e = launch_gemm_tall(m, k, k, -1.0, W, 0, ldw, L1, k, 1.0, L, lf32, ldl, E, lde, 1, s);
+    e = launch_trsm_refine(m, k, L, lf32, ldl, L1, Bt, W, ldw, Tws, s);
     if (e != hipSuccess) return e;
-    e = launch_trsm_tall(m, k, nullptr, 0, 0, Bt, E, lde, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_add_rows, dim3((unsigned)ceil_div(m * k, 256)), dim3(256), 0, s, W,
-                       ldw, E, lde, m, k);
   }
   hipLaunchKernelGGL(k_identity_rows, dim3((unsigned)k), dim3(256), 0, s, S, k, W, ldw);
   return hipGetLastError();

@@ -102,9 +102,7 @@ bool make_plan(rbrp_dtype dt, int64_t m, int64_t n, int32_t b, const rbrp_option
   p->bf16 = o.precision == RBRP_PREC_BF16;
   p->r_f64 = dt == RBRP_F64;
   p->native_mode = p->r_f64 ? kModeF64 : kModeF32;
-  // FP32 input: the factor L is FP32, so the FP64 substitution is already
-  // far below its rounding and a refinement step would not change W visibly
-  p->refine = o.w_refine < 0 ? (p->r_f64 ? 1 : 0) : o.w_refine;
+  p->refine = o.w_refine < 0 ? 1 : o.w_refine;
   p->ntiles = scan_num_tiles(m);
   const int64_t a = norms_num_partials(p->mr), c = deflate_num_partials(p->mr);
   p->nparts = a > c ? a : c;

@@ -102,18 +102,18 @@ hipError_t launch_gemm_f64(int transA, int transB, int64_t M, int64_t N,
                            const int32_t* m_dev, const int32_t* n_dev,
                            int b_lower_tri, hipStream_t s);
 
-// C = alpha A B + beta Cin (A, B FP64 row-major; Cin FP32 or FP64, own ld).
-// C = alpha A B + beta Cin (Cin == nullptr: C itself) for tall A (m x K, FP32
-// or FP64, row-major) and FP64 B (K x N), B optionally lower triangular.
-// W L_1 = L_2 by blocked substitution, in place in W (m x K, ldw): W starts
-// as a copy of L (FP32 when l_f32) unless L is null; Bt holds D_J^{-1} on the
-// 64 x 64 diagonal blocks and -L_1(I, J) D_J^{-1} below them (K x K, ld K).
+// W L_1 = L_2 by blocked substitution, in place in W (m x K, ldw): the
+// diagonal blocks are read from L (FP32 when l_f32) unless L is null (then W
+// holds L_2); Bt holds D_J^{-1} on the 64 x 64 diagonal blocks and
+// -L_1(I, J) D_J^{-1} below them (K x K, ld K).
 hipError_t launch_trsm_tall(int64_t M, int64_t K, const void* L, int l_f32, int64_t ldl,
                             const double* Bt, double* W, int64_t ldw, hipStream_t s);
-hipError_t launch_gemm_tall(int64_t M, int64_t N, int64_t K, double alpha, const void* A,
-                            int a_f32, int64_t lda, const double* B, int64_t ldb, double beta,
-                            const void* Cin, int cin_f32, int64_t ldcin, double* C,
-                            int64_t ldc, int b_lower_tri, hipStream_t s);
+// One refinement step of that solve in place in W, fused per strip (Tws:
+// round_up(M, 128) x 64 doubles of scratch; L1 the lower-triangular k x k
+// factor, Bt as above).
+hipError_t launch_trsm_refine(int64_t M, int64_t K, const void* L, int l_f32, int64_t ldl,
+                              const double* L1, const double* Bt, double* W, int64_t ldw,
+                              double* Tws, hipStream_t s);
 // Pivoted Cholesky of the filter (one workgroup of 256 threads, nb <= kMaxB):
 // pivots, b' by the truncation rule, pivot rows Rraw (unpermuted columns),
 // R11 in pivoted order (Rp, zero-padded to nb), tail_1 = ||V||_F^2 and the

@@ -125,15 +125,21 @@ def test_fp64_w_solve_odd_leading_dimension(rb):
     assert np.array_equal(W[S], np.eye(131))
 
 
-def test_fp32_w_refinement_changes_nothing_visible(rb):
-    """FP32 input: the default solve (no refinement step) and one refinement
-    step give the same W to far below the FP32 rounding of L."""
+def test_fp32_w_refinement_step(rb):
+    """FP32 input: the default solve (one fused refinement step) and the
+    plain substitution give the same skeletons, and W to far below the FP32
+    rounding of L; the refined W is at least as close to X X_S^+."""
     X = adversarial_gmm(20000, 500, sub_dim=200, n_comp=20, seed=5)
-    a = _run(rb, X, 1e-3, 64, 4)
-    b = _run(rb, X, 1e-3, 64, 4, w_refine=1)
-    assert a.S.cpu().tolist() == b.S.cpu().tolist()
+    a = _run(rb, X, 1e-3, 64, 4, w_refine=0)
+    b = _run(rb, X, 1e-3, 64, 4)
+    S = b.S.cpu().tolist()
+    assert a.S.cpu().tolist() == S
     Wa, Wb = a.W.cpu().numpy(), b.W.cpu().numpy()
     assert np.linalg.norm(Wa - Wb) <= 1e-9 * np.linalg.norm(Wb)
+    assert np.array_equal(Wb[S], np.eye(b.k))
+    X64 = X.astype(np.float64)
+    e_b = relative_id_error(X64, Wb, S)
+    assert e_b <= 1.05 * relative_id_error(X64, w_lstsq(X64, S), S) + 1e-6
 
 
 def test_zero_matrix(rb):
