@@ -653,8 +653,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
   }
 }
 
-// One step of iterative refinement of W L_1 = L_2 after the substitution
-// above, fused per 128-row strip: with the residual E = L_2 - W L_1 the
+// A further refinement step on an existing W (after the pass below), fused
+// per 128-row strip: with the residual E = L_2 - W L_1 the
 // correction F of F L_1 = E is formed block by block from the last column
 // block to the first as F(:, J) = (E(:, J) - sum_{I > J} F(:, I) L_1(I, J))
 // D_J^{-1}, and W(:, J) += F(:, J) at once.  Since W(:, I) + F(:, I) is
@@ -664,7 +664,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 // with the strip's T in Tws (TB_M x 64 per strip, rows of the strip only).
 // Bt holds D_J^{-1} on its diagonal blocks; L_1 is lower triangular.
 template <typename TL, bool VA, int TB_K, int WPE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_trsm_refine(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_trsm_refine_step(
     int64_t M, int64_t K, const TL* __restrict__ L, int64_t ldl, const double* __restrict__ L1,
     const double* __restrict__ Bt, double* W, int64_t ldw, double* __restrict__ Tws) {
   constexpr int TBJ = 64;
@@ -679,6 +679,49 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     tall_tile<double, true, double, TB_K, TBJ>(i0, 0, 0, M, nb, nb, 1.0, Tws, TBJ,
                                                Bt + j0 * K + j0, K, 1.0, W + j0, ldw, W + j0,
                                                ldw, As, Bs);
+    __syncthreads();
+  }
+}
+
+
+// Substitution with one step of iterative refinement, per 128-row strip in
+// a single pass.  For column block J (last to first), with the blocks I > J
+// already final:
+//   R = L_2(:, J) - sum_{I > J} W(:, I) L_1(I, J)          (the right side)
+//   W(:, J) = R D_J^{-1}
+//   T = R - W(:, J) D_J    (= (L_2 - W L_1)(:, J), the residual of the block)
+//   W(:, J) += T D_J^{-1}
+// The residual of block J is exact for the current W (the later blocks are
+// final), so this is the refinement step W += F, F L_1 = L_2 - W L_1, taken
+// block by block in substitution order.  R and T live in Tws (TB_M x 64 per
+// strip: rows of the strip only); Bt holds D_J^{-1} on its diagonal blocks;
+// L_1 is lower triangular (zero above the diagonal).
+template <typename TL, bool VA, int TB_K, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_trsm_refine(
+    int64_t M, int64_t K, const TL* __restrict__ L, int64_t ldl, const double* __restrict__ L1,
+    const double* __restrict__ Bt, double* W, int64_t ldw, double* __restrict__ Tws) {
+  constexpr int TBJ = 64;
+  __shared__ double As[2][TB_K][TA_LD];
+  __shared__ double Bs[2][TB_K][TBJ + 16];
+  const int64_t i0 = (int64_t)blockIdx.x * TB_M;
+  for (int64_t J = ceil_div(K, (int64_t)TBJ) - 1; J >= 0; --J) {
+    const int64_t j0 = TBJ * J, nb = min((int64_t)TBJ, K - j0);
+    const double* Dinv = Bt + j0 * K + j0;
+    const double* Dj = L1 + j0 * K + j0;
+    // R (no K steps for the last block: the tile is then L_2(:, J) itself)
+    tall_tile<double, VA, TL, TB_K, TBJ>(i0, j0, j0 + TBJ, M, K, K, -1.0, W, ldw, L1, K, 1.0,
+                                         Tws, TBJ, L, ldl, As, Bs, (const double*)nullptr, 0,
+                                         0, j0);
+    __syncthreads();
+    tall_tile<double, true, double, TB_K, TBJ>(i0, 0, 0, M, nb, nb, 1.0, Tws, TBJ, Dinv, K,
+                                               0.0, W + j0, ldw, (const double*)nullptr, 0,
+                                               As, Bs);
+    __syncthreads();
+    tall_tile<double, VA, double, TB_K, TBJ>(i0, 0, 0, M, nb, nb, -1.0, W + j0, ldw, Dj, K,
+                                             1.0, Tws, TBJ, Tws, TBJ, As, Bs);
+    __syncthreads();
+    tall_tile<double, true, double, TB_K, TBJ>(i0, 0, 0, M, nb, nb, 1.0, Tws, TBJ, Dinv, K,
+                                               1.0, W + j0, ldw, W + j0, ldw, As, Bs);
     __syncthreads();
   }
 }
@@ -713,23 +756,29 @@ hipError_t launch_trsm_tall(int64_t M, int64_t K, const void* L, int l_f32, int6
 
 template <typename TL, bool VA>
 static void refine_typed(int64_t M, int64_t K, const TL* L, int64_t ldl, const double* L1,
-                         const double* Bt, double* W, int64_t ldw, double* Tws, hipStream_t s) {
-  hipLaunchKernelGGL((k_trsm_refine<TL, VA, 8, 3>), dim3((unsigned)ceil_div(M, TB_M)),
-                     dim3(256), 0, s, M, K, L, ldl, L1, Bt, W, ldw, Tws);
+                         const double* Bt, double* W, int64_t ldw, double* Tws, int step,
+                         hipStream_t s) {
+  const dim3 g((unsigned)ceil_div(M, TB_M));
+  if (step)
+    hipLaunchKernelGGL((k_trsm_refine_step<TL, VA, 8, 3>), g, dim3(256), 0, s, M, K, L, ldl, L1,
+                       Bt, W, ldw, Tws);
+  else
+    hipLaunchKernelGGL((k_trsm_refine<TL, VA, 8, 3>), g, dim3(256), 0, s, M, K, L, ldl, L1, Bt,
+                       W, ldw, Tws);
 }
 
 hipError_t launch_trsm_refine(int64_t M, int64_t K, const void* L, int l_f32, int64_t ldl,
                               const double* L1, const double* Bt, double* W, int64_t ldw,
-                              double* Tws, hipStream_t s) {
+                              double* Tws, int step, hipStream_t s) {
   if (M <= 0 || K <= 0) return hipSuccess;
   const int64_t kr = round_up(K, (int64_t)8);
   const bool vec = (reinterpret_cast<uintptr_t>(W) % 16 == 0) && (ldw % 2 == 0) && ldw >= kr;
   if (l_f32) {
-    if (vec) refine_typed<float, true>(M, K, (const float*)L, ldl, L1, Bt, W, ldw, Tws, s);
-    else refine_typed<float, false>(M, K, (const float*)L, ldl, L1, Bt, W, ldw, Tws, s);
+    if (vec) refine_typed<float, true>(M, K, (const float*)L, ldl, L1, Bt, W, ldw, Tws, step, s);
+    else refine_typed<float, false>(M, K, (const float*)L, ldl, L1, Bt, W, ldw, Tws, step, s);
   } else {
-    if (vec) refine_typed<double, true>(M, K, (const double*)L, ldl, L1, Bt, W, ldw, Tws, s);
-    else refine_typed<double, false>(M, K, (const double*)L, ldl, L1, Bt, W, ldw, Tws, s);
+    if (vec) refine_typed<double, true>(M, K, (const double*)L, ldl, L1, Bt, W, ldw, Tws, step, s);
+    else refine_typed<double, false>(M, K, (const double*)L, ldl, L1, Bt, W, ldw, Tws, step, s);
   }
   return hipGetLastError();
 }

@@ -9,9 +9,10 @@
 //      by 16 x 16 blocks on FP64 MFMA) and the sub-diagonal blocks scaled,
 //      Bt(I, J) = -L_1(I, J) D_J^{-1} (one small MFMA GEMM per block column);
 //   3. W L_1 = L solved in place in W by blocked substitution over the block
-//      columns, from the last to the first (one MFMA tile loop per 128-row
-//      strip); each refinement step (the residual E = L - W L_1, F L_1 = E,
-//      W += F) is one more pass of the same shape, fused per strip;
+//      columns, from the last to the first (MFMA tile loops per 128-row
+//      strip), with the first refinement step (the residual E = L - W L_1,
+//      F L_1 = E, W += F) taken block by block in the same pass; further
+//      steps are one more pass each;
 //   4. W(S(j),:) = e_j exactly.
 #include "rbrp_internal.h"
 
@@ -67,12 +68,16 @@ hipError_t launch_interp(const void* L, int l_f64, int64_t ldl, int64_t m, int64
     if (e != hipSuccess) return e;
   }
   const int lf32 = l_f64 ? 0 : 1;
-  e = launch_trsm_tall(m, k, L, lf32, ldl, Bt, W, ldw, s);
-  if (e != hipSuccess) return e;
-  for (int it = 0; it < refine; ++it) {
-    e = launch_trsm_refine(m, k, L, lf32, ldl, L1, Bt, W, ldw, Tws, s);
-    if (e != hipSuccess) return e;
+  if (refine <= 0) {
+    e = launch_trsm_tall(m, k, L, lf32, ldl, Bt, W, ldw, s);
+  } else {
+    // substitution with the first refinement step in the same pass, then
+    // any further steps on the result
+    e = launch_trsm_refine(m, k, L, lf32, ldl, L1, Bt, W, ldw, Tws, 0, s);
+    for (int it = 1; it < refine && e == hipSuccess; ++it)
+      e = launch_trsm_refine(m, k, L, lf32, ldl, L1, Bt, W, ldw, Tws, 1, s);
   }
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_identity_rows, dim3((unsigned)k), dim3(256), 0, s, S, k, W, ldw);
   return hipGetLastError();
 }

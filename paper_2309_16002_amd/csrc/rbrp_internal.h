@@ -108,12 +108,13 @@ hipError_t launch_gemm_f64(int transA, int transB, int64_t M, int64_t N,
 // -L_1(I, J) D_J^{-1} below them (K x K, ld K).
 hipError_t launch_trsm_tall(int64_t M, int64_t K, const void* L, int l_f32, int64_t ldl,
                             const double* Bt, double* W, int64_t ldw, hipStream_t s);
-// One refinement step of that solve in place in W, fused per strip (Tws:
-// round_up(M, 128) x 64 doubles of scratch; L1 the lower-triangular k x k
-// factor, Bt as above).
+// The same solve with one refinement step, in one pass per strip (step = 0:
+// W is written from scratch), or a further refinement step of an existing W
+// (step = 1).  Tws: round_up(M, 128) x 64 doubles of scratch; L1 the
+// lower-triangular k x k factor, Bt as above.
 hipError_t launch_trsm_refine(int64_t M, int64_t K, const void* L, int l_f32, int64_t ldl,
                               const double* L1, const double* Bt, double* W, int64_t ldw,
-                              double* Tws, hipStream_t s);
+                              double* Tws, int step, hipStream_t s);
 // Pivoted Cholesky of the filter (one workgroup of 256 threads, nb <= kMaxB):
 // pivots, b' by the truncation rule, pivot rows Rraw (unpermuted columns),
 // R11 in pivoted order (Rp, zero-padded to nb), tail_1 = ||V||_F^2 and the
