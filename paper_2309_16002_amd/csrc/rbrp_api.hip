@@ -215,6 +215,13 @@ struct Profiler {
   }
 };
 
+// Event marking the copy of a block's scalars (one per host thread).
+hipEvent_t scalars_event() {
+  static thread_local hipEvent_t e = nullptr;
+  if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) e = nullptr;
+  return e;
+}
+
 rbrp_status fetch(DevScalars* h, const DevScalars* dsc, hipStream_t s) {
   RBRP_HIP(hipMemcpyAsync(h, dsc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
   RBRP_HIP(hipStreamSynchronize(s));
@@ -277,6 +284,8 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
   hipStream_t s = (hipStream_t)stream;
   DevScalars* h = host_scalars();
   if (!h) return RBRP_E_HIP;
+  hipEvent_t ev_scalars = scalars_event();
+  if (!ev_scalars) return RBRP_E_HIP;
   const double tau_b = o.tau_b > 0.0 ? o.tau_b : 1.0 / b;
   const double theta = o.theta > 0.0 ? o.theta : 25.0 * eps;
   const int refine = p.refine;
@@ -407,16 +416,19 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
       prof.end();
     }
     RBRP_HIP(launch_reduce(w.part_sum, w.part_max, p.mr / def_rows, w.sc, 0, s));
-    // The next block's selection needs only d, S and the block size; when the
-    // size is certain (b rows, whatever b' turns out to be) it is queued now,
-    // so that the GPU samples while the host waits for this block's scalars.
-    // If the loop stops instead, the queued work is simply not used.
+    // This block's scalars are copied out first; the next block's selection
+    // needs only d, S and the block size, so when the size is certain (b
+    // rows, whatever b' turns out to be) it is queued behind the copy, and
+    // the host, waiting for the copy alone, decides and queues the next
+    // steps while the GPU samples.  If the loop stops instead, the queued
+    // work is simply not used.
+    RBRP_HIP(hipMemcpyAsync(h, w.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+    RBRP_HIP(hipEventRecord(ev_scalars, s));
     if (k_max - kS - bt >= b) {
       RBRP_HIP(select_block(t + 1, b));
       preselected = true;
     }
-    rs = fetch(h, w.sc, s);
-    if (rs != RBRP_OK) return rs;
+    RBRP_HIP(hipEventSynchronize(ev_scalars));
     const int bp = h->bprime;
     flops += 4.0 * (double)m * (double)n * (double)(bp > 0 ? bp : 0);
     if (t <= 256) st.bprime[t - 1] = bp;
