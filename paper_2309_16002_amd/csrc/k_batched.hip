@@ -126,7 +126,20 @@ __device__ __forceinline__ void lds_project(double* __restrict__ As, int na, int
     const double* q = Qt + p * n8;
     const double* a = As + j * n8;
     double s0 = 0.0, s1 = 0.0;
-    for (int64_t c0 = 0; c0 < n8; c0 += kChunk) {
+    // four chunks of Qt in flight per group (the loop is latency-bound:
+    // one workgroup per CU), then the remaining chunks one at a time
+    int64_t c0 = 0;
+    for (; c0 + 4 * kChunk <= n8; c0 += 4 * kChunk) {
+      double qv[4 * kChunk];
+#pragma unroll
+      for (int u = 0; u < 4 * kChunk; ++u) qv[u] = q[c0 + u];
+#pragma unroll
+      for (int u = 0; u < 4 * kChunk; u += 2) {
+        s0 += qv[u] * a[c0 + u];
+        s1 += qv[u + 1] * a[c0 + u + 1];
+      }
+    }
+    for (; c0 < n8; c0 += kChunk) {
       double qv[kChunk];
 #pragma unroll
       for (int u = 0; u < kChunk; ++u) qv[u] = q[c0 + u];
@@ -143,6 +156,16 @@ __device__ __forceinline__ void lds_project(double* __restrict__ As, int na, int
     const int64_t j = e / n8, c = e - j * n8;
     double v = As[j * n8 + c];
     int64_t p0 = 0;
+    for (; p0 + 2 * kChunk <= k; p0 += 2 * kChunk) {
+      double cv[2 * kChunk], qv[2 * kChunk];
+#pragma unroll
+      for (int u = 0; u < 2 * kChunk; ++u) {
+        cv[u] = C[(p0 + u) * na + j];
+        qv[u] = Qt[(p0 + u) * n8 + c];
+      }
+#pragma unroll
+      for (int u = 0; u < 2 * kChunk; ++u) v -= cv[u] * qv[u];
+    }
     for (; p0 + kChunk <= k; p0 += kChunk) {
       double cv[kChunk], qv[kChunk];
 #pragma unroll
@@ -493,98 +516,132 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
 
     // ---- W = L L_1^{-1}, one refinement step per prm.refine, W(S,:) = I ----
     const bool wl = 2 * k * k * 8 <= geom.lds_a + geom.lds_q;
-    double* L1 = wl ? As : L1g;
-    double* Linv = wl ? As + k * k : Linvg;
-    for (int64_t e = tid; e < k * k; e += kBT) {
-      const int64_t j = e / k, p = e - j * k;
-      L1[e] = (p <= j) ? (double)L[ds.S[j] * kcapw + p] : 0.0;
-    }
-    __syncthreads();
-    if (tid < k) {  // column tid of L_1^{-1} by forward substitution
-      const int64_t j = tid;
-      for (int64_t i = 0; i < j; ++i) Linv[i * k + j] = 0.0;
-      for (int64_t i = j; i < k; ++i) {
-        double v = (i == j) ? 1.0 : 0.0;
-        for (int64_t p = j; p < i; ++p) v -= L1[i * k + p] * Linv[p * k + j];
-        Linv[i * k + j] = v / L1[i * k + i];
+    // one copy of the solve per memory space of L_1 and L_1^{-1} (LDS when
+    // they fit, else global scratch), so that every access compiles to an
+    // LDS or a global instruction rather than a generic one
+    auto w_solve = [&](double* L1, double* Linv) {
+      for (int64_t e = tid; e < k * k; e += kBT) {
+        const int64_t j = e / k, p = e - j * k;
+        L1[e] = (p <= j) ? (double)L[ds.S[j] * kcapw + p] : 0.0;
       }
-    }
-    __syncthreads();
-    {
-      const int lane = tid & 63, wv = tid >> 6;
-      double* wl_row = wrow + wv * 2 * kcapw;   // this wave's copy of the row of L
-      double* wbuf = wl_row + kcapw;            // and of w, then of the residual e
-      constexpr int KS = kBatchMaxK / 64;
-      for (int64_t i = wv; i < m; i += kBT / 64) {
-        const T* lr = L + i * kcapw;
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-          const int64_t p = lane + 64 * s;
-          if (p < k) wl_row[p] = (double)lr[p];
+      __syncthreads();
+      if (tid < k) {  // column tid of L_1^{-1} by forward substitution
+        const int64_t j = tid;
+        for (int64_t i = 0; i < j; ++i) Linv[i * k + j] = 0.0;
+        for (int64_t i = j; i < k; ++i) {
+          double v = (i == j) ? 1.0 : 0.0;
+  #pragma unroll 8
+          for (int64_t p = j; p < i; ++p) v -= L1[i * k + p] * Linv[p * k + j];
+          Linv[i * k + j] = v / L1[i * k + i];
         }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        double w[KS];
-#pragma unroll
-        for (int s = 0; s < KS; ++s) w[s] = 0.0;
-        for (int64_t p = 0; p < k; ++p) {
-          const double lp = wl_row[p];
-#pragma unroll
+      }
+      __syncthreads();
+      {
+        const int lane = tid & 63, wv = tid >> 6;
+        double* wl_row = wrow + wv * 2 * kcapw;   // this wave's copy of the row of L
+        double* wbuf = wl_row + kcapw;            // and of w, then of the residual e
+        constexpr int KS = kBatchMaxK / 64;
+        for (int64_t i = wv; i < m; i += kBT / 64) {
+          const T* lr = L + i * kcapw;
+  #pragma unroll
           for (int s = 0; s < KS; ++s) {
-            const int64_t j = lane + 64 * s;
-            if (j < k) w[s] += lp * Linv[p * k + j];
-          }
-        }
-        for (int it = 0; it < prm.refine; ++it) {
-          // e = l - w L_1
-#pragma unroll
-          for (int s = 0; s < KS; ++s) {
-            const int64_t j = lane + 64 * s;
-            if (j < k) wbuf[j] = w[s];
+            const int64_t p = lane + 64 * s;
+            if (p < k) wl_row[p] = (double)lr[p];
           }
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          double ev[KS];
-#pragma unroll
-          for (int s = 0; s < KS; ++s) {
-            const int64_t p = lane + 64 * s;
-            double v = 0.0;
-            if (p < k) {
-              v = wl_row[p];
-              for (int64_t j = p; j < k; ++j) v -= wbuf[j] * L1[j * k + p];
+          double w[KS];
+  #pragma unroll
+          for (int s = 0; s < KS; ++s) w[s] = 0.0;
+          // w = l L_1^{-1}, four p per group: the group's loads are all
+          // issued before its FMAs (L_1^{-1} may be in global memory);
+          // each w[s] still sums over p in order
+          auto row_times_inv = [&](const double* lv) {
+            int64_t p = 0;
+            for (; p + 4 <= k; p += 4) {
+              double a4[4], iv[4][KS];
+  #pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                a4[u] = lv[p + u];
+  #pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                  const int64_t j = lane + 64 * s;
+                  iv[u][s] = 0.0;
+                  if (j < k) iv[u][s] = Linv[(p + u) * k + j];
+                }
+              }
+  #pragma unroll
+              for (int u = 0; u < 4; ++u)
+  #pragma unroll
+                for (int s = 0; s < KS; ++s) w[s] += a4[u] * iv[u][s];
             }
-            ev[s] = v;
-          }
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-#pragma unroll
-          for (int s = 0; s < KS; ++s) {
-            const int64_t p = lane + 64 * s;
-            if (p < k) wbuf[p] = ev[s];
-          }
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          // w += e L_1^{-1}
-          for (int64_t p = 0; p < k; ++p) {
-            const double ep = wbuf[p];
-#pragma unroll
+            for (; p < k; ++p) {
+              const double a = lv[p];
+  #pragma unroll
+              for (int s = 0; s < KS; ++s) {
+                const int64_t j = lane + 64 * s;
+                if (j < k) w[s] += a * Linv[p * k + j];
+              }
+            }
+          };
+          row_times_inv(wl_row);
+          for (int it = 0; it < prm.refine; ++it) {
+            // e = l - w L_1
+  #pragma unroll
             for (int s = 0; s < KS; ++s) {
               const int64_t j = lane + 64 * s;
-              if (j < k) w[s] += ep * Linv[p * k + j];
+              if (j < k) wbuf[j] = w[s];
             }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            double ev[KS];
+  #pragma unroll
+            for (int s = 0; s < KS; ++s) {
+              const int64_t p = lane + 64 * s;
+              double v = 0.0;
+              if (p < k) {
+                v = wl_row[p];
+                int64_t j = p;
+                for (; j + 4 <= k; j += 4) {
+                  double wv4[4], l4[4];
+  #pragma unroll
+                  for (int u = 0; u < 4; ++u) {
+                    wv4[u] = wbuf[j + u];
+                    l4[u] = L1[(j + u) * k + p];
+                  }
+  #pragma unroll
+                  for (int u = 0; u < 4; ++u) v -= wv4[u] * l4[u];
+                }
+                for (; j < k; ++j) v -= wbuf[j] * L1[j * k + p];
+              }
+              ev[s] = v;
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  #pragma unroll
+            for (int s = 0; s < KS; ++s) {
+              const int64_t p = lane + 64 * s;
+              if (p < k) wbuf[p] = ev[s];
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            // w += e L_1^{-1}
+            row_times_inv(wbuf);
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          }
+  #pragma unroll
+          for (int s = 0; s < KS; ++s) {
+            const int64_t j = lane + 64 * s;
+            if (j < k) ds.W[i * ds.ldw + j] = w[s];
           }
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-          const int64_t j = lane + 64 * s;
-          if (j < k) ds.W[i * ds.ldw + j] = w[s];
-        }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       }
-    }
+    };
+    if (wl) w_solve(As, As + k * k);
+    else w_solve(L1g, Linvg);
     __syncthreads();
     for (int64_t e = tid; e < k * k; e += kBT) {
       const int64_t j = e / k, c = e - j * k;
