@@ -754,14 +754,41 @@ hipError_t launch_trsm_tall(int64_t M, int64_t K, const void* L, int l_f32, int6
   return hipGetLastError();
 }
 
+// Compute units of the current device (cached per host thread).
+static int device_cus() {
+  static thread_local int dev = -1, cus = 0;
+  int d = 0;
+  if (hipGetDevice(&d) != hipSuccess) return 256;
+  if (d != dev) {
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    dev = d;
+  }
+  return cus;
+}
+
 template <typename TL, bool VA>
 static void refine_typed(int64_t M, int64_t K, const TL* L, int64_t ldl, const double* L1,
                          const double* Bt, double* W, int64_t ldw, double* Tws, int step,
                          hipStream_t s) {
-  const dim3 g((unsigned)ceil_div(M, TB_M));
-  if (step)
+  const int64_t strips = ceil_div(M, TB_M);
+  const dim3 g((unsigned)strips);
+  if (step) {
     hipLaunchKernelGGL((k_trsm_refine_step<TL, VA, 8, 3>), g, dim3(256), 0, s, M, K, L, ldl, L1,
                        Bt, W, ldw, Tws);
+    return;
+  }
+  // Every strip is one long dependent chain of tiles, so each round of
+  // resident workgroups costs a whole chain.  The four-per-CU build (fewer
+  // registers, a few spilled) runs a chain about 9 % slower than the
+  // three-per-CU build (measured at k = 202), so it is used when it needs
+  // fewer rounds by more than that (100000 x 202: 0.53 -> 0.49 ms).
+  const int64_t cus = device_cus();
+  const int64_t r3 = ceil_div(strips, 3 * cus), r4 = ceil_div(strips, 4 * cus);
+  if (109 * r4 < 100 * r3)
+    hipLaunchKernelGGL((k_trsm_refine<TL, VA, 8, 4>), g, dim3(256), 0, s, M, K, L, ldl, L1, Bt,
+                       W, ldw, Tws);
   else
     hipLaunchKernelGGL((k_trsm_refine<TL, VA, 8, 3>), g, dim3(256), 0, s, M, K, L, ldl, L1, Bt,
                        W, ldw, Tws);
