@@ -8,6 +8,7 @@
 // 2x2 tiles of v_mfma_f64_16x16x4f64.  Lane layout of that instruction
 // (measured on gfx950): lane l supplies A[l%16][l/16] and B[l/16][l%16] and
 // receives D[l/16 + 4q][l%16] for q = 0..3.
+#include <algorithm>
 #include <type_traits>
 
 #include "rbrp_internal.h"
@@ -195,10 +196,13 @@ namespace rbrp {
 
 // C[M x N] = alpha A[M x K] B[N x K]^T + beta C for small M, N and long K
 // (the projections Q^T V and the Gram matrices of the block filter).  One
-// workgroup per 16 x 16 output tile; its NW waves take interleaved 16-wide
-// K chunks straight from global memory into MFMA operands (no LDS staging,
-// no barriers in the K loop), and the NW partial tiles are summed in LDS in
-// wave order.  Within a chunk, lane l loads the 4 consecutive k of row l%16
+// workgroup per 16 x 16 output tile and K slice; its NW waves take
+// interleaved 16-wide K chunks straight from global memory into MFMA
+// operands (no LDS staging, no barriers in the K loop), and the NW partial
+// tiles are summed in LDS in wave order.  With several K slices (blockIdx.z,
+// kslice long) slice z writes its partial product to C + z cstride (beta =
+// 0) and the consumer adds the slices in order: a few output tiles then
+// spread their K over more CUs instead of streaming all of K through one.  Within a chunk, lane l loads the 4 consecutive k of row l%16
 // starting at 4(l/16); MFMA s then uses k = 4(l/16) + s as its K index for
 // both operands, which is a permutation of the chunk's K range.
 template <int NW>
@@ -208,7 +212,8 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_nt16(int64_t M, int64_t N, int
                                                       const double* __restrict__ B, int64_t ldb,
                                                       double beta, double* __restrict__ C,
                                                       int64_t ldc, const int32_t* m_dev,
-                                                      const int32_t* n_dev) {
+                                                      const int32_t* n_dev, int64_t kslice,
+                                                      int64_t cstride) {
   __shared__ double part[NW][256];
   if (m_dev) M = min(M, (int64_t)*m_dev);
   if (n_dev) N = min(N, (int64_t)*n_dev);
@@ -221,12 +226,16 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_nt16(int64_t M, int64_t N, int
   const double* bp = B + (vb ? jb : 0) * ldb;
   d4v acc = (d4v){0.0, 0.0, 0.0, 0.0};
   // groups of four 16-wide chunks per wave: every load of a group is issued
-  // before its MFMAs.  Chunk bases past K are clamped to the last chunk (K is
-  // a multiple of 16) and their products masked, so no load is conditional.
+  // before its MFMAs.  Chunk bases past the K slice are clamped to its last
+  // chunk (slice bounds are multiples of 16) and their products masked, so
+  // no load is conditional.
+  const int64_t kbeg = (int64_t)blockIdx.z * kslice;
+  const int64_t kend = min(K, kbeg + kslice);
+  C += (int64_t)blockIdx.z * cstride;
   const int64_t kstep = 16 * NW;
-  const int64_t klast = K - 16;
+  const int64_t klast = kend - 16;
   const int koff = 4 * (lane >> 4);
-  for (int64_t k0 = 16 * w; k0 < K; k0 += 4 * kstep) {
+  for (int64_t k0 = kbeg + 16 * w; k0 < kend; k0 += 4 * kstep) {
     d2v a[4][2], b[4][2];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -238,7 +247,7 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_nt16(int64_t M, int64_t N, int
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const bool live = k0 + u * kstep < K;
+      const bool live = k0 + u * kstep < kend;
       const bool la = live && va, lb = live && vb;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
@@ -315,22 +324,38 @@ __global__ __launch_bounds__(256) void k_gemm_nt16_any(int64_t M, int64_t N, int
 // K a multiple of 16 (the padded row length) with 16-byte aligned rows: the
 // batched-load kernel, sixteen waves splitting K when K >= 512; otherwise the
 // per-element kernel.  Partial tiles are summed in wave order (deterministic).
+int nt_slice_count(int64_t M, int64_t N, int64_t K) {
+  const int64_t tiles = ceil_div(N, (int64_t)16) * ceil_div(M, (int64_t)16);
+  if (tiles > 64 || K < 256 || K % 16) return 1;
+  const int64_t want = std::min<int64_t>(kNtMaxSlices, 256 / tiles);
+  const int64_t kslice = round_up(ceil_div(K, want), (int64_t)64);
+  return (int)ceil_div(K, kslice);
+}
+
 hipError_t launch_gemm_nt_small(int64_t M, int64_t N, int64_t K, double alpha,
                                 const double* A, int64_t lda, const double* B, int64_t ldb,
                                 double beta, double* C, int64_t ldc, const int32_t* m_dev,
-                                const int32_t* n_dev, hipStream_t s) {
+                                const int32_t* n_dev, hipStream_t s, int nsl, int64_t cstride) {
   if (M <= 0 || N <= 0) return hipSuccess;
   dim3 g((unsigned)ceil_div(N, 16), (unsigned)ceil_div(M, 16));
   if (K < 16 || K % 16 || lda % 2 || ldb % 2 || ((uintptr_t)A | (uintptr_t)B) % 16) {
-    if (m_dev || n_dev) return hipErrorInvalidValue;
+    if (m_dev || n_dev || nsl > 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_gemm_nt16_any, g, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb,
                        beta, C, ldc);
-  } else if (K >= 512)
-    hipLaunchKernelGGL(k_gemm_nt16<16>, g, dim3(1024), 0, s, M, N, K, alpha, A, lda, B, ldb,
-                       beta, C, ldc, m_dev, n_dev);
-  else
+  } else if (nsl > 1) {
+    // the slice count the consumer expects must be the one this launch uses
+    if (beta != 0.0 || nsl != nt_slice_count(M, N, K)) return hipErrorInvalidValue;
+    const int64_t kslice = round_up(ceil_div(K, (int64_t)nsl), (int64_t)64);
+    g.z = (unsigned)nsl;
     hipLaunchKernelGGL(k_gemm_nt16<4>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb,
-                       beta, C, ldc, m_dev, n_dev);
+                       beta, C, ldc, m_dev, n_dev, kslice, cstride);
+  } else if (K >= 512) {
+    hipLaunchKernelGGL(k_gemm_nt16<16>, g, dim3(1024), 0, s, M, N, K, alpha, A, lda, B, ldb,
+                       beta, C, ldc, m_dev, n_dev, K, (int64_t)0);
+  } else {
+    hipLaunchKernelGGL(k_gemm_nt16<4>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb,
+                       beta, C, ldc, m_dev, n_dev, K, (int64_t)0);
+  }
   return hipGetLastError();
 }
 
@@ -350,7 +375,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn16(int64_t M, int64_t N, int64_t
                                                    int64_t ldb, const int32_t* __restrict__ brow,
                                                    const int32_t* __restrict__ k_dev,
                                                    double beta, double* __restrict__ C,
-                                                   int64_t ldc) {
+                                                   int64_t ldc, int nsl, int64_t astride) {
   __shared__ double part[4][256];
   if (k_dev) K = min(K, (int64_t)*k_dev);
   const int64_t i0 = (int64_t)blockIdx.y * 16, j0 = (int64_t)blockIdx.x * 16;
@@ -370,6 +395,22 @@ __global__ __launch_bounds__(256) void k_gemm_tn16(int64_t M, int64_t N, int64_t
       const int64_t k = min(k0 + 64 * (s >> 2) + 4 * (s & 3) + kq, K - 1);
       kr[s] = GATHER ? (int64_t)brow[k] : k;
       a[s] = A[k * lda + iac];
+    }
+    // A given as K slices of partial sums (from the sliced NT product):
+    // every slice's loads issued together, then added in slice order
+    if (nsl > 1) {
+      double az[kNtMaxSlices - 1][8];
+#pragma unroll
+      for (int z = 1; z < kNtMaxSlices; ++z)
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int64_t k = min(k0 + 64 * (s >> 2) + 4 * (s & 3) + kq, K - 1);
+          az[z - 1][s] = z < nsl ? A[z * astride + k * lda + iac] : 0.0;
+        }
+#pragma unroll
+      for (int z = 1; z < kNtMaxSlices; ++z)
+#pragma unroll
+        for (int s = 0; s < 8; ++s) a[s] += az[z - 1][s];
     }
 #pragma unroll
     for (int s = 0; s < 8; ++s) b[s] = B[kr[s] * ldb + jbc];
@@ -397,15 +438,17 @@ __global__ __launch_bounds__(256) void k_gemm_tn16(int64_t M, int64_t N, int64_t
 hipError_t launch_gemm_tn_small(int64_t M, int64_t N, int64_t K, double alpha,
                                 const double* A, int64_t lda, const double* B, int64_t ldb,
                                 double beta, double* C, int64_t ldc, hipStream_t s,
-                                const int32_t* brow, const int32_t* k_dev) {
+                                const int32_t* brow, const int32_t* k_dev, int nsl,
+                                int64_t astride) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  if (nsl < 1) return hipErrorInvalidValue;
   dim3 g((unsigned)ceil_div(N, 16), (unsigned)ceil_div(M, 16));
   if (brow)
     hipLaunchKernelGGL(k_gemm_tn16<true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb,
-                       brow, k_dev, beta, C, ldc);
+                       brow, k_dev, beta, C, ldc, nsl, astride);
   else
     hipLaunchKernelGGL(k_gemm_tn16<false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb,
-                       brow, k_dev, beta, C, ldc);
+                       brow, k_dev, beta, C, ldc, nsl, astride);
   return hipGetLastError();
 }
 

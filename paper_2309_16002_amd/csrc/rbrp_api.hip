@@ -126,7 +126,7 @@ size_t layout(const Plan& p, char* base, Work* w) {
   w->idx = cv.take<int64_t>(kMaxB);
   w->xs2 = cv.take<double>(kMaxB);
   w->Vt = cv.take<double>((size_t)p.b * p.ldr);
-  w->C = cv.take<double>((size_t)p.k_max * p.b);
+  w->C = cv.take<double>((size_t)kNtMaxSlices * p.k_max * p.b);  // K slices of C
   w->G = cv.take<double>((size_t)p.b * p.b);
   w->piv = cv.take<int32_t>(kMaxB);
   w->piv2 = cv.take<int32_t>(kMaxB);
@@ -355,12 +355,16 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     preselected = false;
     // project twice against the basis
     prof.begin(2);
+    // C = Q V^T in K slices when it has few output tiles (the update adds
+    // the slices)
+    const int nsl = kS > 0 ? nt_slice_count(kS, bt, ldr) : 1;
+    const int64_t cstride = (int64_t)k_max * p.b;
     if (kS > 0) {
       for (int pass = 0; pass < 2; ++pass) {
         RBRP_HIP(launch_gemm_nt_small(kS, bt, ldr, 1.0, w.Qt, ldr, w.Vt, ldr, 0.0, w.C, bt,
-                                      nullptr, nullptr, s));
+                                      nullptr, nullptr, s, nsl, cstride));
         RBRP_HIP(launch_gemm_tn_small(bt, ldr, kS, -1.0, w.C, bt, w.Qt, ldr, 1.0, w.Vt, ldr,
-                                      s));
+                                      s, nullptr, nullptr, nsl, cstride));
       }
     }
     // robust blockwise filter: pivoted Cholesky of V^T V, then the kept columns'
@@ -374,9 +378,9 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     // second pass: project against the basis, then Cholesky QR
     if (kS > 0) {
       RBRP_HIP(launch_gemm_nt_small(kS, bt, ldr, 1.0, w.Qt, ldr, w.Qtmp, ldr, 0.0, w.C, bt,
-                                    nullptr, nullptr, s));
+                                    nullptr, nullptr, s, nsl, cstride));
       RBRP_HIP(launch_gemm_tn_small(bt, ldr, kS, -1.0, w.C, bt, w.Qt, ldr, 1.0, w.Qtmp, ldr,
-                                    s));
+                                    s, nullptr, nullptr, nsl, cstride));
     }
     RBRP_HIP(launch_gemm_nt_small(bt, bt, ldr, 1.0, w.Qtmp, ldr, w.Qtmp, ldr, 0.0, w.G, bt,
                                   nullptr, nullptr, s));

@@ -164,11 +164,19 @@ hipError_t launch_ortho_first_order(const double* G2, int64_t ldg, const int32_t
 hipError_t launch_gemm_tn_small(int64_t M, int64_t N, int64_t K, double alpha,
                                 const double* A, int64_t lda, const double* B, int64_t ldb,
                                 double beta, double* C, int64_t ldc, hipStream_t s,
-                                const int32_t* brow = nullptr, const int32_t* k_dev = nullptr);
+                                const int32_t* brow = nullptr, const int32_t* k_dev = nullptr,
+                                int nsl = 1, int64_t astride = 0);
+// Products with few 16 x 16 output tiles may split K into slices
+// (nt_slice_count); with nsl > 1 (beta = 0) slice z is written to
+// C + z cstride and the consumer (launch_gemm_tn_small with the same nsl)
+// adds the slices in order.
+constexpr int kNtMaxSlices = 4;
+int nt_slice_count(int64_t M, int64_t N, int64_t K);
 hipError_t launch_gemm_nt_small(int64_t M, int64_t N, int64_t K, double alpha,
                                 const double* A, int64_t lda, const double* B, int64_t ldb,
                                 double beta, double* C, int64_t ldc, const int32_t* m_dev,
-                                const int32_t* n_dev, hipStream_t s);
+                                const int32_t* n_dev, hipStream_t s, int nsl = 1,
+                                int64_t cstride = 0);
 
 // Skeleton bookkeeping after the filter: S[kS + p] = idx[piv[p]],
 // sel_block[S[kS+p]] = t; bchunk (optional) = b' split into deflation
