@@ -66,11 +66,12 @@ __global__ __launch_bounds__(kPivThreads) void k_cpqr_piv(
     const double* __restrict__ xs2_rows, int32_t* __restrict__ piv,
     double* __restrict__ Rraw, int64_t ldr, double* __restrict__ Rp, int64_t ldp,
     int32_t* __restrict__ bprime_out, double* __restrict__ tail1_out,
-    int32_t* __restrict__ stop_out) {
+    int32_t* __restrict__ stop_out, int nsl, int64_t gstride) {
   extern __shared__ double Ss[];
   __shared__ PivShared<NBMAX> sh;
   wg_piv_chol<NBMAX, GS, true>(G, ldg, nb_host, nb_dev, tau_b, xs2_rows, piv, Rraw, ldr, Rp,
-                               ldp, bprime_out, tail1_out, stop_out, GS ? G : Ss, sh);
+                               ldp, bprime_out, tail1_out, stop_out, GS ? G : Ss, sh, nsl,
+                               gstride);
 }
 
 // Exact reorthogonalisation factor: Cholesky in natural order of the Gram
@@ -81,7 +82,7 @@ __global__ __launch_bounds__(kPivThreads) void k_chol_reorth(
     double* __restrict__ G, int64_t ldg, int32_t nb_host, const int32_t* __restrict__ nb_dev,
     int32_t* __restrict__ piv2, double* __restrict__ Rraw, int64_t ldr,
     double* __restrict__ Rp, int64_t ldp, int32_t* __restrict__ steps_out,
-    const int32_t* __restrict__ run_flag) {
+    const int32_t* __restrict__ run_flag, int nsl, int64_t gstride) {
   if (*run_flag == 0) {
     if (threadIdx.x == 0) *steps_out = *nb_dev;
     return;
@@ -89,7 +90,8 @@ __global__ __launch_bounds__(kPivThreads) void k_chol_reorth(
   extern __shared__ double Ss[];
   __shared__ PivShared<NBMAX> sh;
   wg_piv_chol<NBMAX, GS, false>(G, ldg, nb_host, nb_dev, 0.0, nullptr, piv2, Rraw, ldr, Rp,
-                                ldp, steps_out, nullptr, nullptr, GS ? G : Ss, sh);
+                                ldp, steps_out, nullptr, nullptr, GS ? G : Ss, sh, nsl,
+                                gstride);
 }
 
 // X = R^{-1} for the upper triangular R (b' x b', b' = *bcount <= 256,
@@ -228,12 +230,27 @@ __global__ __launch_bounds__(256) void k_ortho_first_order(const double* __restr
                                                            int32_t nb_host,
                                                            double* __restrict__ M2,
                                                            int64_t ldm,
-                                                           int32_t* __restrict__ need_exact) {
+                                                           int32_t* __restrict__ need_exact,
+                                                           int nsl, int64_t gstride) {
   // thread (column c, part) handles rows part, part + TPC, ... of column c
   // (nb_host <= 256); eight rows' loads are issued before they are used
   __shared__ double red[256];
   const int bp = *bprime;
   const int tid = threadIdx.x;
+  // G2 may come as nsl K slices of partial sums (gstride apart): added in
+  // slice order, all slices' loads issued together
+  auto g2 = [&](int64_t off) {
+    double v = G2[off];
+    if (nsl > 1) {
+      // unconditional loads from clamped slices, unused ones masked after
+      double vz[kNtMaxSlices - 1];
+#pragma unroll
+      for (int z = 1; z < kNtMaxSlices; ++z) vz[z - 1] = G2[min(z, nsl - 1) * gstride + off];
+#pragma unroll
+      for (int z = 1; z < kNtMaxSlices; ++z) v += z < nsl ? vz[z - 1] : 0.0;
+    }
+    return v;
+  };
   const int ncols = nb_host <= 64 ? 64 : (nb_host <= 128 ? 128 : 256);
   const int tpc = 256 / ncols;
   const int c = tid % ncols, part = tid / ncols;
@@ -242,7 +259,7 @@ __global__ __launch_bounds__(256) void k_ortho_first_order(const double* __restr
     for (int a0 = part; a0 < bp; a0 += 8 * tpc) {
       double x[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) x[u] = G2[(int64_t)min(a0 + u * tpc, bp - 1) * ldg + c];
+      for (int u = 0; u < 8; ++u) x[u] = g2((int64_t)min(a0 + u * tpc, bp - 1) * ldg + c);
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int a = a0 + u * tpc;
@@ -268,7 +285,7 @@ __global__ __launch_bounds__(256) void k_ortho_first_order(const double* __restr
         const int a = a0 + u * tpc;
         // the diagonal reads G2[a][a], the strict upper part G2[c][a]
         // (clamped index: always in range, used only where it applies)
-        x[u] = G2[(int64_t)c * ldg + min(a, nb_host - 1)];
+        x[u] = g2((int64_t)c * ldg + min(a, nb_host - 1));
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -301,23 +318,25 @@ static hipError_t set_chol_lds(K kernel, bool* done) {
 hipError_t launch_cpqr_piv(double* G, int64_t ldg, int32_t nb, const int32_t* nb_dev,
                            double tau_b, const double* xs2_rows, int32_t* piv, double* Rraw,
                            int64_t ldr, double* Rp, int64_t ldp, int32_t* bprime_out,
-                           double* tail1_out, int32_t* stop_out, hipStream_t s) {
-  if (nb <= 0 || nb > kMaxB) return hipErrorInvalidValue;
+                           double* tail1_out, int32_t* stop_out, hipStream_t s, int nsl,
+                           int64_t gstride) {
+  if (nb <= 0 || nb > kMaxB || nsl < 1 || nsl > kNtMaxSlices) return hipErrorInvalidValue;
+  if (nsl > 1 && nb > kLdsCholMax) return hipErrorInvalidValue;  // S would be G itself
   if (nb <= 64) {
     hipLaunchKernelGGL((k_cpqr_piv<64, false>), dim3(1), dim3(kPivThreads),
                        chol_lds_bytes(nb), s, G, ldg, nb, nb_dev, tau_b, xs2_rows, piv, Rraw,
-                       ldr, Rp, ldp, bprime_out, tail1_out, stop_out);
+                       ldr, Rp, ldp, bprime_out, tail1_out, stop_out, nsl, gstride);
   } else if (nb <= kLdsCholMax) {
     static bool attr = false;
     hipError_t e = set_chol_lds(k_cpqr_piv<kLdsCholMax, false>, &attr);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_cpqr_piv<kLdsCholMax, false>), dim3(1), dim3(kPivThreads),
                        chol_lds_bytes(nb), s, G, ldg, nb, nb_dev, tau_b, xs2_rows, piv, Rraw,
-                       ldr, Rp, ldp, bprime_out, tail1_out, stop_out);
+                       ldr, Rp, ldp, bprime_out, tail1_out, stop_out, nsl, gstride);
   } else {
     hipLaunchKernelGGL((k_cpqr_piv<kMaxB, true>), dim3(1), dim3(kPivThreads), 0, s, G, ldg,
                        nb, nb_dev, tau_b, xs2_rows, piv, Rraw, ldr, Rp, ldp, bprime_out,
-                       tail1_out, stop_out);
+                       tail1_out, stop_out, 1, (int64_t)0);
   }
   return hipGetLastError();
 }
@@ -355,32 +374,38 @@ hipError_t launch_qsolve(const double* Vt, int64_t ldv, const int32_t* piv, cons
 
 hipError_t launch_ortho_first_order(const double* G2, int64_t ldg, const int32_t* bprime,
                                     int32_t nb_host, double* M2, int64_t ldm,
-                                    int32_t* need_exact, hipStream_t s) {
+                                    int32_t* need_exact, hipStream_t s, int nsl,
+                                    int64_t gstride) {
+  if (nsl < 1 || nsl > kNtMaxSlices) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_ortho_first_order, dim3(1), dim3(256), 0, s, G2, ldg, bprime, nb_host,
-                     M2, ldm, need_exact);
+                     M2, ldm, need_exact, nsl, gstride);
   return hipGetLastError();
 }
 
 hipError_t launch_ortho_exact(double* G2, int64_t ldg, const int32_t* bprime, int32_t nb_host,
                               int32_t* piv2, double* R2raw, double* R2, double* M2,
                               int64_t ldm, int32_t* steps_out, const int32_t* need_exact,
-                              hipStream_t s) {
-  if (nb_host <= 0 || nb_host > kMaxB) return hipErrorInvalidValue;
+                              hipStream_t s, int nsl, int64_t gstride) {
+  if (nb_host <= 0 || nb_host > kMaxB || nsl < 1 || nsl > kNtMaxSlices)
+    return hipErrorInvalidValue;
+  if (nsl > 1 && nb_host > kLdsCholMax) return hipErrorInvalidValue;
   if (nb_host <= 64) {
     hipLaunchKernelGGL((k_chol_reorth<64, false>), dim3(1), dim3(kPivThreads),
                        chol_lds_bytes(nb_host), s, G2, ldg, nb_host, bprime, piv2, R2raw,
-                       (int64_t)nb_host, R2, (int64_t)nb_host, steps_out, need_exact);
+                       (int64_t)nb_host, R2, (int64_t)nb_host, steps_out, need_exact, nsl,
+                       gstride);
   } else if (nb_host <= kLdsCholMax) {
     static bool attr = false;
     hipError_t e = set_chol_lds(k_chol_reorth<kLdsCholMax, false>, &attr);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_chol_reorth<kLdsCholMax, false>), dim3(1), dim3(kPivThreads),
                        chol_lds_bytes(nb_host), s, G2, ldg, nb_host, bprime, piv2, R2raw,
-                       (int64_t)nb_host, R2, (int64_t)nb_host, steps_out, need_exact);
+                       (int64_t)nb_host, R2, (int64_t)nb_host, steps_out, need_exact, nsl,
+                       gstride);
   } else {
     hipLaunchKernelGGL((k_chol_reorth<kMaxB, true>), dim3(1), dim3(kPivThreads), 0, s, G2, ldg,
                        nb_host, bprime, piv2, R2raw, (int64_t)nb_host, R2, (int64_t)nb_host,
-                       steps_out, need_exact);
+                       steps_out, need_exact, 1, (int64_t)0);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

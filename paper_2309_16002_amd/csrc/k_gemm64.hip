@@ -405,12 +405,12 @@ __global__ __launch_bounds__(256) void k_gemm_tn16(int64_t M, int64_t N, int64_t
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
           const int64_t k = min(k0 + 64 * (s >> 2) + 4 * (s & 3) + kq, K - 1);
-          az[z - 1][s] = z < nsl ? A[z * astride + k * lda + iac] : 0.0;
+          az[z - 1][s] = A[min(z, nsl - 1) * astride + k * lda + iac];
         }
 #pragma unroll
       for (int z = 1; z < kNtMaxSlices; ++z)
 #pragma unroll
-        for (int s = 0; s < 8; ++s) a[s] += az[z - 1][s];
+        for (int s = 0; s < 8; ++s) a[s] += z < nsl ? az[z - 1][s] : 0.0;
     }
 #pragma unroll
     for (int s = 0; s < 8; ++s) b[s] = B[kr[s] * ldb + jbc];

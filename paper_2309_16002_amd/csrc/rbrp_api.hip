@@ -127,7 +127,7 @@ size_t layout(const Plan& p, char* base, Work* w) {
   w->xs2 = cv.take<double>(kMaxB);
   w->Vt = cv.take<double>((size_t)p.b * p.ldr);
   w->C = cv.take<double>((size_t)kNtMaxSlices * p.k_max * p.b);  // K slices of C
-  w->G = cv.take<double>((size_t)p.b * p.b);
+  w->G = cv.take<double>((size_t)kNtMaxSlices * p.b * p.b);  // K slices of the Gram
   w->piv = cv.take<int32_t>(kMaxB);
   w->piv2 = cv.take<int32_t>(kMaxB);
   w->Rraw = cv.take<double>((size_t)p.b * p.b);
@@ -369,10 +369,16 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     }
     // robust blockwise filter: pivoted Cholesky of V^T V, then the kept columns'
     // orthonormal basis Q' = V(:, piv(1:b')) R11^{-1}
+    // the filter's Gram matrix in K slices too when it has few output tiles
+    // (the pivoted Cholesky adds them while copying G in); the second Gram
+    // below stays whole (its first-order check reads each entry, where the
+    // slices cost more than they save: measured)
+    const int nslg = nt_slice_count(bt, bt, ldr);
+    const int64_t gstride = (int64_t)p.b * p.b;
     RBRP_HIP(launch_gemm_nt_small(bt, bt, ldr, 1.0, w.Vt, ldr, w.Vt, ldr, 0.0, w.G, bt, nullptr,
-                                  nullptr, s));
+                                  nullptr, s, nslg, gstride));
     RBRP_HIP(launch_cpqr_piv(w.G, bt, bt, &w.sc->nt, tau_b, w.xs2, w.piv, w.Rraw, bt, w.Mc, bt,
-                             &w.sc->bprime, &w.sc->tail1, &w.sc->stop_rank, s));
+                             &w.sc->bprime, &w.sc->tail1, &w.sc->stop_rank, s, nslg, gstride));
     RBRP_HIP(launch_qsolve(w.Vt, ldr, w.piv, w.Mc, bt, &w.sc->bprime, bt, ldr, w.Qtmp, ldr,
                            w.Rinv, s));
     // second pass: project against the basis, then Cholesky QR

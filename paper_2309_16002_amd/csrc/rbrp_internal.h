@@ -16,6 +16,7 @@ constexpr int kWave = 64;
 constexpr int kRowPad = 64;
 // Rows per workgroup of the norm / weight kernels.
 constexpr int kNormRowsPerWG = 64;
+constexpr int kNtMaxSlices = 4;     // K slices of the small NT products (see launch_gemm_nt_small)
 constexpr int kScanTile = 2048;   // rows per tile of the fixed-point CDF
 constexpr int kMaxB = 256;        // largest block size
 constexpr int kDeflateMaxB = 128; // largest b' of one deflation launch
@@ -122,7 +123,8 @@ hipError_t launch_trsm_refine(int64_t M, int64_t K, const void* L, int l_f32, in
 hipError_t launch_cpqr_piv(double* G, int64_t ldg, int32_t nb, const int32_t* nb_dev,
                            double tau_b, const double* xs2_rows, int32_t* piv, double* Rraw,
                            int64_t ldr, double* Rp, int64_t ldp, int32_t* bprime_out,
-                           double* tail1_out, int32_t* stop_out, hipStream_t s);
+                           double* tail1_out, int32_t* stop_out, hipStream_t s, int nsl = 1,
+                           int64_t gstride = 0);
 
 // X = R^{-1} (or X^T with trans) of the upper triangular R (*bcount x
 // *bcount), zero elsewhere in the nb_host x nb_host output; skipped when
@@ -148,7 +150,8 @@ hipError_t launch_qsolve(const double* Vt, int64_t ldv, const int32_t* piv, cons
 hipError_t launch_ortho_exact(double* G2, int64_t ldg, const int32_t* bprime, int32_t nb_host,
                               int32_t* piv2, double* R2raw, double* R2, double* M2,
                               int64_t ldm, int32_t* steps_out, const int32_t* need_exact,
-                              hipStream_t s);
+                              hipStream_t s, int nsl = 1,
+                           int64_t gstride = 0);
 
 // First-order Cholesky-QR factor of G2 = I + E, stored transposed
 // (M2t = R2^{-1}), when max|E| <= 1e-8 (need_exact = 0), else need_exact = 1
@@ -156,7 +159,8 @@ hipError_t launch_ortho_exact(double* G2, int64_t ldg, const int32_t* bprime, in
 // Qn = M2t^T Qtmp.
 hipError_t launch_ortho_first_order(const double* G2, int64_t ldg, const int32_t* bprime,
                                     int32_t nb_host, double* M2, int64_t ldm,
-                                    int32_t* need_exact, hipStream_t s);
+                                    int32_t* need_exact, hipStream_t s, int nsl = 1,
+                           int64_t gstride = 0);
 
 // C = alpha A B^T + beta C for small M, N and long K (split over waves).
 // C[M x N] = alpha A^T B + beta C with A stored K x M and B K x N (small M).
@@ -170,7 +174,6 @@ hipError_t launch_gemm_tn_small(int64_t M, int64_t N, int64_t K, double alpha,
 // (nt_slice_count); with nsl > 1 (beta = 0) slice z is written to
 // C + z cstride and the consumer (launch_gemm_tn_small with the same nsl)
 // adds the slices in order.
-constexpr int kNtMaxSlices = 4;
 int nt_slice_count(int64_t M, int64_t N, int64_t K);
 hipError_t launch_gemm_nt_small(int64_t M, int64_t N, int64_t K, double alpha,
                                 const double* A, int64_t lda, const double* B, int64_t ldb,

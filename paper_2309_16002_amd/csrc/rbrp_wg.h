@@ -520,7 +520,8 @@ __device__ __forceinline__ void wg_piv_chol(
     const double* __restrict__ xs2_rows, int32_t* __restrict__ piv,
     double* __restrict__ Rraw, int64_t ldr, double* __restrict__ Rp, int64_t ldp,
     int32_t* __restrict__ bprime_out, double* __restrict__ tail1_out,
-    int32_t* __restrict__ stop_out, double* __restrict__ S, PivShared<NBMAX>& sh) {
+    int32_t* __restrict__ stop_out, double* __restrict__ S, PivShared<NBMAX>& sh,
+    int nsl = 1, int64_t gstride = 0) {
   static_assert(NBMAX <= kPivThreads, "at most one column per thread in the updates");
   constexpr int NPL = (NBMAX + 63) / 64;       // columns per lane of wave 0
   constexpr int NCOLS = 64 * NPL;
@@ -532,7 +533,8 @@ __device__ __forceinline__ void wg_piv_chol(
   const int64_t ld = GS ? ldg : nb + 1;
   if constexpr (!GS) {
     // thread (column c, part) copies rows part, part + TPC, ...; eight rows'
-    // loads are issued before their stores
+    // loads are issued before their stores.  G may come as nsl K slices of
+    // partial sums (gstride apart), added in slice order.
     const int c = tid % NCOLS, part = tid / NCOLS;
     if (c < nb) {
       for (int r0 = part; r0 < nb; r0 += 8 * TPC) {
@@ -541,6 +543,20 @@ __device__ __forceinline__ void wg_piv_chol(
         for (int u = 0; u < 8; ++u) {
           const int r = min(r0 + u * TPC, nb - 1);
           x[u] = G[(int64_t)r * ldg + c];
+        }
+        if (nsl > 1) {
+          double xz[kNtMaxSlices - 1][8];
+#pragma unroll
+          for (int z = 1; z < kNtMaxSlices; ++z)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int r = min(r0 + u * TPC, nb - 1);
+              xz[z - 1][u] = G[min(z, nsl - 1) * gstride + (int64_t)r * ldg + c];
+            }
+#pragma unroll
+          for (int z = 1; z < kNtMaxSlices; ++z)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] += z < nsl ? xz[z - 1][u] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u)
