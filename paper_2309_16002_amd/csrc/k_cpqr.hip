@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kPivThreads) void k_chol_reorth(
     double* __restrict__ G, int64_t ldg, int32_t nb_host, const int32_t* __restrict__ nb_dev,
     int32_t* __restrict__ piv2, double* __restrict__ Rraw, int64_t ldr,
     double* __restrict__ Rp, int64_t ldp, int32_t* __restrict__ steps_out,
-    const int32_t* __restrict__ run_flag, int nsl, int64_t gstride) {
+    const int32_t* __restrict__ run_flag) {
   if (*run_flag == 0) {
     if (threadIdx.x == 0) *steps_out = *nb_dev;
     return;
@@ -90,8 +90,7 @@ __global__ __launch_bounds__(kPivThreads) void k_chol_reorth(
   extern __shared__ double Ss[];
   __shared__ PivShared<NBMAX> sh;
   wg_piv_chol<NBMAX, GS, false>(G, ldg, nb_host, nb_dev, 0.0, nullptr, piv2, Rraw, ldr, Rp,
-                                ldp, steps_out, nullptr, nullptr, GS ? G : Ss, sh, nsl,
-                                gstride);
+                                ldp, steps_out, nullptr, nullptr, GS ? G : Ss, sh);
 }
 
 // X = R^{-1} for the upper triangular R (b' x b', b' = *bcount <= 256,
@@ -230,27 +229,12 @@ __global__ __launch_bounds__(256) void k_ortho_first_order(const double* __restr
                                                            int32_t nb_host,
                                                            double* __restrict__ M2,
                                                            int64_t ldm,
-                                                           int32_t* __restrict__ need_exact,
-                                                           int nsl, int64_t gstride) {
+                                                           int32_t* __restrict__ need_exact) {
   // thread (column c, part) handles rows part, part + TPC, ... of column c
   // (nb_host <= 256); eight rows' loads are issued before they are used
   __shared__ double red[256];
   const int bp = *bprime;
   const int tid = threadIdx.x;
-  // G2 may come as nsl K slices of partial sums (gstride apart): added in
-  // slice order, all slices' loads issued together
-  auto g2 = [&](int64_t off) {
-    double v = G2[off];
-    if (nsl > 1) {
-      // unconditional loads from clamped slices, unused ones masked after
-      double vz[kNtMaxSlices - 1];
-#pragma unroll
-      for (int z = 1; z < kNtMaxSlices; ++z) vz[z - 1] = G2[min(z, nsl - 1) * gstride + off];
-#pragma unroll
-      for (int z = 1; z < kNtMaxSlices; ++z) v += z < nsl ? vz[z - 1] : 0.0;
-    }
-    return v;
-  };
   const int ncols = nb_host <= 64 ? 64 : (nb_host <= 128 ? 128 : 256);
   const int tpc = 256 / ncols;
   const int c = tid % ncols, part = tid / ncols;
@@ -259,7 +243,7 @@ __global__ __launch_bounds__(256) void k_ortho_first_order(const double* __restr
     for (int a0 = part; a0 < bp; a0 += 8 * tpc) {
       double x[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) x[u] = g2((int64_t)min(a0 + u * tpc, bp - 1) * ldg + c);
+      for (int u = 0; u < 8; ++u) x[u] = G2[(int64_t)min(a0 + u * tpc, bp - 1) * ldg + c];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int a = a0 + u * tpc;
@@ -285,7 +269,7 @@ __global__ __launch_bounds__(256) void k_ortho_first_order(const double* __restr
         const int a = a0 + u * tpc;
         // the diagonal reads G2[a][a], the strict upper part G2[c][a]
         // (clamped index: always in range, used only where it applies)
-        x[u] = g2((int64_t)c * ldg + min(a, nb_host - 1));
+        x[u] = G2[(int64_t)c * ldg + min(a, nb_host - 1)];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -374,38 +358,32 @@ hipError_t launch_qsolve(const double* Vt, int64_t ldv, const int32_t* piv, cons
 
 hipError_t launch_ortho_first_order(const double* G2, int64_t ldg, const int32_t* bprime,
                                     int32_t nb_host, double* M2, int64_t ldm,
-                                    int32_t* need_exact, hipStream_t s, int nsl,
-                                    int64_t gstride) {
-  if (nsl < 1 || nsl > kNtMaxSlices) return hipErrorInvalidValue;
+                                    int32_t* need_exact, hipStream_t s) {
   hipLaunchKernelGGL(k_ortho_first_order, dim3(1), dim3(256), 0, s, G2, ldg, bprime, nb_host,
-                     M2, ldm, need_exact, nsl, gstride);
+                     M2, ldm, need_exact);
   return hipGetLastError();
 }
 
 hipError_t launch_ortho_exact(double* G2, int64_t ldg, const int32_t* bprime, int32_t nb_host,
                               int32_t* piv2, double* R2raw, double* R2, double* M2,
                               int64_t ldm, int32_t* steps_out, const int32_t* need_exact,
-                              hipStream_t s, int nsl, int64_t gstride) {
-  if (nb_host <= 0 || nb_host > kMaxB || nsl < 1 || nsl > kNtMaxSlices)
-    return hipErrorInvalidValue;
-  if (nsl > 1 && nb_host > kLdsCholMax) return hipErrorInvalidValue;
+                              hipStream_t s) {
+  if (nb_host <= 0 || nb_host > kMaxB) return hipErrorInvalidValue;
   if (nb_host <= 64) {
     hipLaunchKernelGGL((k_chol_reorth<64, false>), dim3(1), dim3(kPivThreads),
                        chol_lds_bytes(nb_host), s, G2, ldg, nb_host, bprime, piv2, R2raw,
-                       (int64_t)nb_host, R2, (int64_t)nb_host, steps_out, need_exact, nsl,
-                       gstride);
+                       (int64_t)nb_host, R2, (int64_t)nb_host, steps_out, need_exact);
   } else if (nb_host <= kLdsCholMax) {
     static bool attr = false;
     hipError_t e = set_chol_lds(k_chol_reorth<kLdsCholMax, false>, &attr);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_chol_reorth<kLdsCholMax, false>), dim3(1), dim3(kPivThreads),
                        chol_lds_bytes(nb_host), s, G2, ldg, nb_host, bprime, piv2, R2raw,
-                       (int64_t)nb_host, R2, (int64_t)nb_host, steps_out, need_exact, nsl,
-                       gstride);
+                       (int64_t)nb_host, R2, (int64_t)nb_host, steps_out, need_exact);
   } else {
     hipLaunchKernelGGL((k_chol_reorth<kMaxB, true>), dim3(1), dim3(kPivThreads), 0, s, G2, ldg,
                        nb_host, bprime, piv2, R2raw, (int64_t)nb_host, R2, (int64_t)nb_host,
-                       steps_out, need_exact, 1, (int64_t)0);
+                       steps_out, need_exact);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -119,7 +119,8 @@ hipError_t launch_trsm_refine(int64_t M, int64_t K, const void* L, int l_f32, in
 // Pivoted Cholesky of the filter (one workgroup of 256 threads, nb <= kMaxB):
 // pivots, b' by the truncation rule, pivot rows Rraw (unpermuted columns),
 // R11 in pivoted order (Rp, zero-padded to nb), tail_1 = ||V||_F^2 and the
-// rank-guard flag.  G is overwritten when nb > 128.
+// rank-guard flag.  G is overwritten when nb > 128.  For nb <= 128, G may
+// come as nsl K slices of partial sums gstride apart (added in slice order).
 hipError_t launch_cpqr_piv(double* G, int64_t ldg, int32_t nb, const int32_t* nb_dev,
                            double tau_b, const double* xs2_rows, int32_t* piv, double* Rraw,
                            int64_t ldr, double* Rp, int64_t ldp, int32_t* bprime_out,
@@ -150,8 +151,7 @@ hipError_t launch_qsolve(const double* Vt, int64_t ldv, const int32_t* piv, cons
 hipError_t launch_ortho_exact(double* G2, int64_t ldg, const int32_t* bprime, int32_t nb_host,
                               int32_t* piv2, double* R2raw, double* R2, double* M2,
                               int64_t ldm, int32_t* steps_out, const int32_t* need_exact,
-                              hipStream_t s, int nsl = 1,
-                           int64_t gstride = 0);
+                              hipStream_t s);
 
 // First-order Cholesky-QR factor of G2 = I + E, stored transposed
 // (M2t = R2^{-1}), when max|E| <= 1e-8 (need_exact = 0), else need_exact = 1
@@ -159,8 +159,7 @@ hipError_t launch_ortho_exact(double* G2, int64_t ldg, const int32_t* bprime, in
 // Qn = M2t^T Qtmp.
 hipError_t launch_ortho_first_order(const double* G2, int64_t ldg, const int32_t* bprime,
                                     int32_t nb_host, double* M2, int64_t ldm,
-                                    int32_t* need_exact, hipStream_t s, int nsl = 1,
-                           int64_t gstride = 0);
+                                    int32_t* need_exact, hipStream_t s);
 
 // C = alpha A B^T + beta C for small M, N and long K (split over waves).
 // C[M x N] = alpha A^T B + beta C with A stored K x M and B K x N (small M).
