@@ -51,6 +51,7 @@ def _run(rb, X, eps, b, seed, **kw):
     (3000, 1000, 256, 1e-3, 5),  # b > 128: global-memory filter, two deflation launches
     (1500, 400, 200, 1e-4, 6),   # ... and a run that ends at full rank (k = n)
     (2500, 1300, 64, 1e-3, 7),   # 1024 < n <= 2048: eight-wave deflation panels
+    (1200, 300, 32, 1e-4, 8),    # n padded to 384: the filter products in three K slices
 ])
 def test_fp64_matches_oracle(rb, m, n, b, eps, seed):
     if b > 128:
@@ -110,6 +111,21 @@ def test_fp64_w_solve_refinement_steps(rb, refine):
     tol = 1e-10 if refine > 0 else 1e-9
     assert np.linalg.norm(W - Wref) <= tol * np.linalg.norm(Wref)
     assert np.array_equal(W[S], np.eye(res.k))
+
+
+@pytest.mark.parametrize("k", [1, 64, 65, 128])
+def test_fp64_w_solve_block_boundaries(rb, k):
+    """Fixed rank k at and around the 64-column blocks of the substitution
+    (one column; exactly one block; one block plus one column; two blocks):
+    W matches X X_S^+ and W(S,:) = I."""
+    X = svd_matrix(1500, 300, geometric_spectrum(300, 0.98), seed=79)
+    res = _run(rb, X, 1e-12, 16, 4, k_max=k, fixed_rank=True)
+    assert res.k == k
+    S = res.S.cpu().tolist()
+    W = res.W.cpu().numpy()
+    Wref = w_lstsq(X, S)
+    assert np.linalg.norm(W - Wref) <= 1e-10 * np.linalg.norm(Wref)
+    assert np.array_equal(W[S], np.eye(k))
 
 
 def test_fp64_w_solve_odd_leading_dimension(rb):
