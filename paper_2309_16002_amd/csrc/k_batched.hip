@@ -214,7 +214,21 @@ __device__ __forceinline__ void deflate_rows(T* __restrict__ RT, int64_t mpad, i
     T acc[NBT];
 #pragma unroll
     for (int j = 0; j < NBT; ++j) acc[j] = (T)0;
-    for (int64_t c0 = 0; c0 < n8; c0 += kChunk) {
+    // two chunks of the row in flight per group (the loop is bound by the
+    // latency of its loads), then the remaining chunk
+    int64_t c0 = 0;
+    for (; c0 + 2 * kChunk <= n8; c0 += 2 * kChunk) {
+      T r[2 * kChunk];
+#pragma unroll
+      for (int u = 0; u < 2 * kChunk; ++u) r[u] = RT[(c0 + u) * mpad + i];
+#pragma unroll
+      for (int u = 0; u < 2 * kChunk; ++u) {
+        const T* qc = QfT + (c0 + u) * bq;
+#pragma unroll
+        for (int j = 0; j < NBT; ++j) acc[j] += r[u] * qc[j];
+      }
+    }
+    for (; c0 < n8; c0 += kChunk) {
       T r[kChunk];
 #pragma unroll
       for (int u = 0; u < kChunk; ++u) r[u] = RT[(c0 + u) * mpad + i];
@@ -232,10 +246,15 @@ __device__ __forceinline__ void deflate_rows(T* __restrict__ RT, int64_t mpad, i
     for (int j = 0; j < NBT; ++j)
       if (j < bp) lr[j] = earlier ? (T)0 : acc[j];
     double nrm = 0.0;
-    for (int64_t c0 = 0; c0 < n8; c0 += kChunk) {
-      T r[kChunk];
+    // the next chunk is loaded before the current one is updated and stored
+    // (another part of the row: no element is read after it is written)
+    T r[kChunk], rn[kChunk];
 #pragma unroll
-      for (int u = 0; u < kChunk; ++u) r[u] = RT[(c0 + u) * mpad + i];
+    for (int u = 0; u < kChunk; ++u) r[u] = RT[(int64_t)u * mpad + i];
+    for (int64_t c0 = 0; c0 < n8; c0 += kChunk) {
+      const int64_t cn = c0 + kChunk < n8 ? c0 + kChunk : c0;
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) rn[u] = RT[(cn + u) * mpad + i];
 #pragma unroll
       for (int u = 0; u < kChunk; ++u) {
         const T* qc = QfT + (c0 + u) * bq;
@@ -244,6 +263,8 @@ __device__ __forceinline__ void deflate_rows(T* __restrict__ RT, int64_t mpad, i
         RT[(c0 + u) * mpad + i] = r[u];
         nrm += (double)r[u] * (double)r[u];
       }
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) r[u] = rn[u];
     }
     d[i] = sb >= 0 ? 0.0 : nrm;
   }
