@@ -114,12 +114,60 @@ __device__ __forceinline__ void wg_sum_max(double s, double mx, double* red, dou
   __syncthreads();
 }
 
+// The update As -= C^T Qt of lds_project for na <= NA rows, one thread per
+// column (see there).
+template <int NA>
+__device__ __forceinline__ void lds_project_update(double* __restrict__ As, int na, int64_t n8,
+                                                   const double* __restrict__ Qt, int64_t k,
+                                                   const double* __restrict__ C,
+                                                   double* __restrict__ Cs, int64_t cs_cap) {
+  const int tid = threadIdx.x;
+  const int64_t P = cs_cap / na > 0 ? cs_cap / na : 1;
+  for (int64_t p0 = 0; p0 < k; p0 += P) {
+    const int64_t pn = min(P, k - p0);
+    for (int64_t e = tid; e < pn * na; e += kBT) Cs[e] = C[p0 * na + e];
+    __syncthreads();
+    for (int64_t c = tid; c < n8; c += kBT) {
+      double v[NA];
+#pragma unroll
+      for (int j = 0; j < NA; ++j) v[j] = j < na ? As[j * n8 + c] : 0.0;
+      for (int64_t pp = 0; pp < pn; pp += kChunk) {
+        // kChunk values of Qt in flight (rows past the group clamped, unused)
+        double qv[kChunk];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+          const int64_t pr = p0 + (pp + u < pn ? pp + u : pn - 1);
+          qv[u] = Qt[pr * n8 + c];
+        }
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+          if (pp + u < pn) {
+            const double* cr = Cs + (pp + u) * na;
+#pragma unroll
+            for (int j = 0; j < NA; ++j)
+              if (j < na) v[j] -= cr[j] * qv[u];
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NA; ++j)
+        if (j < na) As[j * n8 + c] = v[j];
+    }
+    __syncthreads();
+  }
+}
+
 // Rows of the LDS block As (na rows, stride n8) minus their projection on
 // the basis: C = Qt[0:k] As^T (C in global scratch, k x na), As -= C^T Qt.
 // Qt rows (stride n8) are zero beyond column n, as are the rows of As.
+// The update runs one thread per column (n8 <= kBT): the column's na entries
+// stay in registers, each Qt value is loaded once, and C is staged in LDS
+// (Cs, cs_cap doubles, free at this point) a group of rows at a time; every
+// entry still subtracts its terms in order of p.
 __device__ __forceinline__ void lds_project(double* __restrict__ As, int na, int64_t n8,
                                             const double* __restrict__ Qt, int64_t k,
-                                            double* __restrict__ C) {
+                                            double* __restrict__ C, double* __restrict__ Cs,
+                                            int64_t cs_cap) {
   const int tid = threadIdx.x;
   for (int64_t e = tid; e < k * na; e += kBT) {
     const int64_t p = e / na, j = e - p * na;
@@ -152,34 +200,8 @@ __device__ __forceinline__ void lds_project(double* __restrict__ As, int na, int
     C[p * na + j] = s0 + s1;
   }
   __syncthreads();
-  for (int64_t e = tid; e < na * n8; e += kBT) {
-    const int64_t j = e / n8, c = e - j * n8;
-    double v = As[j * n8 + c];
-    int64_t p0 = 0;
-    for (; p0 + 2 * kChunk <= k; p0 += 2 * kChunk) {
-      double cv[2 * kChunk], qv[2 * kChunk];
-#pragma unroll
-      for (int u = 0; u < 2 * kChunk; ++u) {
-        cv[u] = C[(p0 + u) * na + j];
-        qv[u] = Qt[(p0 + u) * n8 + c];
-      }
-#pragma unroll
-      for (int u = 0; u < 2 * kChunk; ++u) v -= cv[u] * qv[u];
-    }
-    for (; p0 + kChunk <= k; p0 += kChunk) {
-      double cv[kChunk], qv[kChunk];
-#pragma unroll
-      for (int u = 0; u < kChunk; ++u) {
-        cv[u] = C[(p0 + u) * na + j];
-        qv[u] = Qt[(p0 + u) * n8 + c];
-      }
-#pragma unroll
-      for (int u = 0; u < kChunk; ++u) v -= cv[u] * qv[u];
-    }
-    for (; p0 < k; ++p0) v -= C[p0 * na + j] * Qt[p0 * n8 + c];
-    As[j * n8 + c] = v;
-  }
-  __syncthreads();
+  if (na <= 16) lds_project_update<16>(As, na, n8, Qt, k, C, Cs, cs_cap);
+  else lds_project_update<kBatchMaxB>(As, na, n8, Qt, k, C, Cs, cs_cap);
 }
 
 // G = As As^T for na rows of the LDS block (global G, stride ldg).
@@ -296,6 +318,10 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
   T* QfT = reinterpret_cast<T*>(dsm + geom.lds_a);
   double* Ss = reinterpret_cast<double*>(dsm + geom.lds_a + geom.lds_q);
   double* wrow = reinterpret_cast<double*>(dsm + geom.lds_a + geom.lds_q + geom.lds_s);
+  // staging of the projection coefficients: the Q'^T, Schur and row-buffer
+  // regions, none of which is live during a projection
+  double* Cs = reinterpret_cast<double*>(dsm + geom.lds_a);
+  const int64_t cs_cap = (geom.lds_q + geom.lds_s + geom.lds_w) / 8;
 
   char* base = scratch + (int64_t)blockIdx.x * geom.slice;
   T* RT = reinterpret_cast<T*>(base + geom.off_rt);
@@ -421,8 +447,8 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
       }
       __syncthreads();
       if (kS > 0) {
-        lds_project(As, nt, n8, Qt, kS, C);
-        lds_project(As, nt, n8, Qt, kS, C);
+        lds_project(As, nt, n8, Qt, kS, C, Cs, cs_cap);
+        lds_project(As, nt, n8, Qt, kS, C, Cs, cs_cap);
       }
       // ---- robust blockwise filter: pivoted Cholesky of V^T V ----
       lds_gram(As, nt, n8, G, bmax);
@@ -454,7 +480,7 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
       }
       __syncthreads();
       // ---- reorthogonalisation: project, then Cholesky QR ----
-      if (kS > 0) lds_project(As, bp, n8, Qt, kS, C);
+      if (kS > 0) lds_project(As, bp, n8, Qt, kS, C, Cs, cs_cap);
       lds_gram(As, bp, n8, G, bmax);
       // Cholesky G = R2^T R2 (right-looking, in place in the upper triangle)
       if (tid == 0) s_flag = 0;
