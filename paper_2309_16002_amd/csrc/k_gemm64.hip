@@ -497,14 +497,18 @@ struct TallStage {
 // restrict-qualified).  When D is given, the K steps below kd_end take their
 // A elements from D (same rows and columns, leading dimension ldd, type TD)
 // instead of A; the step bounds are multiples of TB_K, so a step reads one
-// source only.  C's column index is shifted by c_off (Cin's is not).
+// source only.  C's column index is shifted by c_off (Cin's is not).  With
+// tri_k0 >= 0 the rows tri_k0 .. tri_k0 + TB_N - 1 of B are lower triangular
+// against the tile's columns (B[tri_k0 + r][j0 + c] = 0 for r < c): a wave
+// skips the products of a step whose rows all lie above its 16 columns
+// (they would add exact zeros).
 template <typename TA, bool VA, typename TC, int TB_K, int TB_N, typename TD = TA>
 __device__ __forceinline__ void tall_tile(
     int64_t i0, int64_t j0, int64_t kbeg, int64_t M, int64_t N, int64_t K, double alpha,
     const TA* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
     int64_t ldc, const TC* Cin, int64_t ldcin, double (*As)[TB_K][TA_LD],
     double (*Bs)[TB_K][TB_N + 16], const TD* D = nullptr, int64_t ldd = 0,
-    int64_t kd_end = 0, int64_t c_off = 0) {
+    int64_t kd_end = 0, int64_t c_off = 0, int64_t tri_k0 = -1) {
   typedef TallStage<TA, TB_K, TB_N, TD> St;
   constexpr int NA = St::NA, NB = St::NB, VW = St::VW, NAV = St::NAV;
   constexpr int VWD = St::VWD, NDV = St::NDV;
@@ -584,7 +588,13 @@ __device__ __forceinline__ void tall_tile(
 #pragma unroll
     for (int q = 0; q < NB; ++q) Bs[buf][bk][bj + q] = krow ? st.b[q] : 0.0;
   };
-  auto mma = [&](int buf) {
+  auto mma = [&](int buf, int64_t k0) {
+    // column tiles of this wave that the step leaves unchanged (uniform)
+    bool zero[WN];
+#pragma unroll
+    for (int b = 0; b < WN; ++b)
+      zero[b] = tri_k0 >= 0 && k0 >= tri_k0 &&
+                k0 + TB_K - 1 - tri_k0 < (TB_N / 2) * wx + 16 * b;
 #pragma unroll
     for (int ks = 0; ks < TB_K / 4; ++ks) {
       const int kr = 4 * ks + (lane >> 4);
@@ -594,10 +604,12 @@ __device__ __forceinline__ void tall_tile(
 #pragma unroll
       for (int b = 0; b < WN; ++b) bv[b] = Bs[buf][kr][(TB_N / 2) * wx + 16 * b + (lane & 15)];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < WN; ++b) {
+        if (zero[b]) continue;
 #pragma unroll
-        for (int b = 0; b < WN; ++b)
+        for (int a = 0; a < 4; ++a)
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
     }
   };
 
@@ -621,18 +633,18 @@ __device__ __forceinline__ void tall_tile(
     for (; t + 2 <= nt; t += 2) {
       // even step t: LDS 0, registers s1 = step t+1; s0 is free
       fetch(s0, kstep(t + 2));
-      mma(0);
+      mma(0, kstep(t));
       __builtin_amdgcn_sched_barrier(0);
       stash(s1, 1, kstep(t + 1));
       __syncthreads();
       // odd step t+1: LDS 1, registers s0 = step t+2; s1 is free
       fetch(s1, kstep(t + 3));
-      mma(1);
+      mma(1, kstep(t + 1));
       __builtin_amdgcn_sched_barrier(0);
       stash(s0, 0, kstep(t + 2));
       __syncthreads();
     }
-    if (t < nt) mma(0);  // nt odd: the last step sits in LDS 0
+    if (t < nt) mma(0, kstep(t));  // nt odd: the last step sits in LDS 0
   }
 
   // epilogue, one 16-row group of MFMA tiles at a time: its C-input loads
@@ -691,7 +703,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
   for (int64_t J = ceil_div(K, (int64_t)TBJ) - 1; J >= 0; --J) {
     tall_tile<double, VA, double, TB_K, TBJ, TL>(i0, TBJ * J, TBJ * J, M, K, K, 1.0, W, ldw, Bt,
                                                  ldb, 0.0, W, ldw, (const double*)nullptr, 0, As,
-                                                 Bs, L, ldl, TBJ * (J + 1));
+                                                 Bs, L, ldl, TBJ * (J + 1), 0, TBJ * J);
     __syncthreads();
   }
 }
@@ -717,11 +729,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
   for (int64_t J = ceil_div(K, (int64_t)TBJ) - 1; J >= 0; --J) {
     const int64_t j0 = TBJ * J, nb = min((int64_t)TBJ, K - j0);
     tall_tile<double, VA, TL, TB_K, TBJ>(i0, j0, j0, M, K, K, -1.0, W, ldw, L1, K, 1.0, Tws,
-                                         TBJ, L, ldl, As, Bs, (const double*)nullptr, 0, 0, j0);
+                                         TBJ, L, ldl, As, Bs, (const double*)nullptr, 0, 0, j0,
+                                         j0);
     __syncthreads();
     tall_tile<double, true, double, TB_K, TBJ>(i0, 0, 0, M, nb, nb, 1.0, Tws, TBJ,
                                                Bt + j0 * K + j0, K, 1.0, W + j0, ldw, W + j0,
-                                               ldw, As, Bs);
+                                               ldw, As, Bs, (const double*)nullptr, 0, 0, 0, 0);
     __syncthreads();
   }
 }
@@ -758,13 +771,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     __syncthreads();
     tall_tile<double, true, double, TB_K, TBJ>(i0, 0, 0, M, nb, nb, 1.0, Tws, TBJ, Dinv, K,
                                                0.0, W + j0, ldw, (const double*)nullptr, 0,
-                                               As, Bs);
+                                               As, Bs, (const double*)nullptr, 0, 0, 0, 0);
     __syncthreads();
     tall_tile<double, VA, double, TB_K, TBJ>(i0, 0, 0, M, nb, nb, -1.0, W + j0, ldw, Dj, K,
-                                             1.0, Tws, TBJ, Tws, TBJ, As, Bs);
+                                             1.0, Tws, TBJ, Tws, TBJ, As, Bs,
+                                             (const double*)nullptr, 0, 0, 0, 0);
     __syncthreads();
     tall_tile<double, true, double, TB_K, TBJ>(i0, 0, 0, M, nb, nb, 1.0, Tws, TBJ, Dinv, K,
-                                               1.0, W + j0, ldw, W + j0, ldw, As, Bs);
+                                               1.0, W + j0, ldw, W + j0, ldw, As, Bs,
+                                               (const double*)nullptr, 0, 0, 0, 0);
     __syncthreads();
   }
 }
