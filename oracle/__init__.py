@@ -38,9 +38,10 @@ from .cpqr import cpqr, truncation_rank, tails_from_r
 from .rbrp import rbrp, RBRPResult
 from .srp import srp
 from .interp import w_lstsq, w_from_l, relative_id_error
+from .trim import trim_rank, projection_error_sq
 
 __all__ = [
     "philox4x64_10", "philox_word0", "fixed_point_weights", "sample_block",
     "cpqr", "truncation_rank", "tails_from_r", "rbrp", "RBRPResult", "srp",
-    "w_lstsq", "w_from_l", "relative_id_error",
+    "w_lstsq", "w_from_l", "relative_id_error", "trim_rank", "projection_error_sq",
 ]
