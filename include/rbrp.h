@@ -72,7 +72,17 @@ typedef struct {
   int32_t profile;     /* 1: time the phases with HIP events on ``stream`` and
                           report them in rbrp_stats; 2: time only the
                           deflation launches (ms_deflate, deflate_launches)    */
-  int32_t reserved0;
+  int32_t trim;        /* 1: rank trimming.  The stopping rule of Alg. 2 runs
+                          between blocks, so the last block can add up to
+                          b' - 1 rows more than eps needs; with trim the
+                          returned k is the shortest prefix S(1:k) whose
+                          tracked error meets eps (the last block's columns
+                          taken one at a time: the block's starting residual
+                          minus the squared norms of its columns of L, which
+                          is the prefix's error by Pythagoras over the
+                          orthonormal basis), and W is formed for that
+                          prefix.  Ignored with fixed_rank.  0: keep every
+                          selected row (the paper's rule)                   */
 } rbrp_options;
 
 /* Per-call statistics (optional, host memory). */

@@ -35,7 +35,7 @@ class rbrp_options(ctypes.Structure):
         ("w_refine", ctypes.c_int32),
         ("theta", ctypes.c_double),
         ("profile", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("trim", ctypes.c_int32),
     ]
 
 
@@ -180,7 +180,7 @@ def _check_matrix(X):
 
 
 def make_options(k_max=0, tau_b=0.0, fixed_rank=False, greedy=False, precision="native",
-                 theta=0.0, w_refine=-1, profile=False):
+                 theta=0.0, w_refine=-1, profile=False, trim=False):
     o = rbrp_options()
     lib().rbrp_default_options(ctypes.byref(o))
     o.tau_b = float(tau_b)
@@ -191,6 +191,7 @@ def make_options(k_max=0, tau_b=0.0, fixed_rank=False, greedy=False, precision="
     o.theta = float(theta)
     o.w_refine = int(w_refine)
     o.profile = 2 if profile == "deflate" else int(bool(profile))
+    o.trim = int(bool(trim))
     return o
 
 

@@ -11,6 +11,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace rbrp {
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -234,6 +236,64 @@ hipError_t launch_reduce(const double* part_sum, const double* part_max,
                          int64_t np, DevScalars* sc, int set_d0, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, part_sum, part_max, np,
                      sc, set_d0);
+  return hipGetLastError();
+}
+
+// Squared norms of the columns c0 .. c0 + nc - 1 (nc <= 256) of L (m rows,
+// row-major, ld ldl): workgroup g sums rows g, g + G, ... with one thread
+// per column (each row is one contiguous segment), eight rows' loads before
+// their products; a single workgroup then adds the G partials of each
+// column in order.  Both stages run in a fixed order (bit-identical results).
+template <typename TL>
+__global__ __launch_bounds__(256) void k_col_sumsq_part(const TL* __restrict__ L, int64_t ldl,
+                                                        int64_t m, int64_t c0, int nc,
+                                                        double* __restrict__ part) {
+  const int c = threadIdx.x;
+  if (c >= nc) return;
+  const int64_t G = gridDim.x;
+  const TL* lc = L + c0 + c;
+  double s = 0.0;
+  int64_t r = blockIdx.x;
+  for (; r + 7 * G < m; r += 8 * G) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (double)lc[(r + u * G) * ldl];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u] * v[u];
+  }
+  for (; r < m; r += G) {
+    const double v = (double)lc[r * ldl];
+    s += v * v;
+  }
+  part[(int64_t)blockIdx.x * nc + c] = s;
+}
+
+__global__ __launch_bounds__(256) void k_col_sumsq_final(const double* __restrict__ part,
+                                                         int G, int nc,
+                                                         double* __restrict__ out) {
+  const int c = threadIdx.x;
+  if (c >= nc) return;
+  double s = 0.0;
+  for (int g = 0; g < G; ++g) s += part[(int64_t)g * nc + c];
+  out[c] = s;
+}
+
+int col_sumsq_groups(int64_t m) {
+  return (int)std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(m, (int64_t)64)));
+}
+
+hipError_t launch_col_sumsq(const void* L, int l_f64, int64_t ldl, int64_t m, int64_t c0,
+                            int nc, double* part, double* out, hipStream_t s) {
+  if (nc <= 0) return hipSuccess;
+  if (nc > 256 || m <= 0) return hipErrorInvalidValue;
+  const int G = col_sumsq_groups(m);
+  if (l_f64)
+    hipLaunchKernelGGL(k_col_sumsq_part<double>, dim3(G), dim3(256), 0, s, (const double*)L,
+                       ldl, m, c0, nc, part);
+  else
+    hipLaunchKernelGGL(k_col_sumsq_part<float>, dim3(G), dim3(256), 0, s, (const float*)L, ldl,
+                       m, c0, nc, part);
+  hipLaunchKernelGGL(k_col_sumsq_final, dim3(1), dim3(256), 0, s, part, G, nc, out);
   return hipGetLastError();
 }
 

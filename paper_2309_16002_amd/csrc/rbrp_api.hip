@@ -340,6 +340,8 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     return e;
   };
   bool preselected = false;
+  int64_t k_last = 0;        // skeletons before the last counted block
+  double sum_last = sum_d;   // tracked squared residual before that block
   while (true) {
     if (kS >= k_max) {
       if (!o.fixed_rank && sum_d > tau * D0) final_status = RBRP_E_CAPACITY;
@@ -445,8 +447,37 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     st.blocks = t;
     if (h->stop_rank || bp <= 0) break;
     if (h->b2 != bp) return RBRP_E_HIP;  // basis lost orthogonality beyond repair
+    k_last = kS;
+    sum_last = sum_d;
     kS += bp;
     sum_d = h->sum_d;
+  }
+  // Rank trimming: with Q' orthogonal to the earlier basis, the error of the
+  // prefix that ends j columns into the last block is its starting residual
+  // minus the squared norms of its first j columns of L (L-hat = X Q'); the
+  // shortest prefix that meets the stopping rule is kept.  The partial sums
+  // use the residual buffer (no longer needed), the column norms C.
+  if (o.trim && !o.fixed_rank && kS - k_last > 1 && !(sum_d > tau * D0)) {
+    const int nc = (int)(kS - k_last);
+    const int G = col_sumsq_groups(m);
+    const size_t rsz = (size_t)p.mr * p.ldr * (p.r_f64 ? sizeof(double) : sizeof(float));
+    if ((size_t)G * nc * sizeof(double) > rsz) return RBRP_E_HIP;
+    double* part = reinterpret_cast<double*>(w.R);
+    RBRP_HIP(launch_col_sumsq(w.L, p.r_f64, p.ldl, m, k_last, nc, part, w.C, s));
+    double colsq[kMaxB];
+    RBRP_HIP(hipMemcpyAsync(colsq, w.C, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
+    RBRP_HIP(hipStreamSynchronize(s));
+    double e = sum_last;
+    for (int j = 0; j < nc; ++j) {
+      e -= colsq[j];
+      if (e <= tau * D0) {
+        if (j + 1 < nc) {
+          kS = k_last + j + 1;
+          sum_d = e;
+        }
+        break;
+      }
+    }
   }
   *k_host = kS;
   st.resid_tracked = sqrt(fmax(sum_d, 0.0) / D0);

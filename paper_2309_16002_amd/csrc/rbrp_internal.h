@@ -61,6 +61,12 @@ hipError_t launch_masked_partials(const double* d, const uint8_t* excluded,
                                   int64_t m, double* part_sum, double* part_max,
                                   hipStream_t s);
 int64_t masked_num_partials(int64_t m);
+// Squared norms (FP64) of columns c0 .. c0 + nc - 1 (nc <= 256) of L (m rows,
+// ld ldl; FP64 if l_f64, else FP32) into out[nc]; part holds
+// col_sumsq_groups(m) * nc doubles of partial sums.
+int col_sumsq_groups(int64_t m);
+hipError_t launch_col_sumsq(const void* L, int l_f64, int64_t ldl, int64_t m, int64_t c0,
+                            int nc, double* part, double* out, hipStream_t s);
 
 // Fixed-order reduction of partial sums / maxima into sc->sum_d, sc->max_d
 // (and sc->d0 when set_d0).
