@@ -225,6 +225,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true",
                     help="skip the BF16 precision-form leg")
+    ap.add_argument("--trim", action="store_true",
+                    help="rank trimming: cut k to the shortest prefix of the selection "
+                         "that meets eps (an option of rbrp_id; off in the default line)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device-to-device copy of MB megabytes (the "
                          "reference for HBM byte counters) and exit")
@@ -280,7 +283,7 @@ def main():
         def step(seed, profile="deflate"):
             return rb.rbrp_id(Xg, cfg["eps"], cfg["b"], seed, workspace=ws, out_S=S_buf,
                               out_W=W_buf, precision=precision, profile=profile,
-                              k_max=k_max, fixed_rank=fixed)
+                              k_max=k_max, fixed_rank=fixed, trim=args.trim)
         for i in range(warmup):
             step(1000 + i)
             print(f"[bench] {precision} warmup {i + 1}/{warmup} done", file=sys.stderr,
@@ -356,6 +359,7 @@ def main():
         "config": {"workload": args.workload, "m": m, "n": n, "eps": cfg["eps"],
                    "b": cfg["b"], "tau_b": 1.0 / cfg["b"],
                    **({"fixed_rank": k_max} if fixed else {}),
+                   **({"trim": True} if args.trim else {}),
                    "deflation": "fp64-mfma" if dtype == "f64" else "fp32-mfma (plain)",
                    "parallelism": "single-gpu"},
         "roofline": roofline,

@@ -81,8 +81,11 @@ typedef struct {
                           minus the squared norms of its columns of L, which
                           is the prefix's error by Pythagoras over the
                           orthonormal basis), and W is formed for that
-                          prefix.  Ignored with fixed_rank.  0: keep every
-                          selected row (the paper's rule)                   */
+                          prefix.  Ignored with fixed_rank and in the BF16
+                          precision form (its tracked residual carries the
+                          BF16 rounding, which the whole last block's slack
+                          covers).  0: keep every selected row (the paper's
+                          rule)                                              */
 } rbrp_options;
 
 /* Per-call statistics (optional, host memory). */

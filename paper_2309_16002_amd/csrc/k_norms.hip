@@ -240,60 +240,91 @@ hipError_t launch_reduce(const double* part_sum, const double* part_max,
 }
 
 // Squared norms of the columns c0 .. c0 + nc - 1 (nc <= 256) of L (m rows,
-// row-major, ld ldl): workgroup g sums rows g, g + G, ... with one thread
-// per column (each row is one contiguous segment), eight rows' loads before
-// their products; a single workgroup then adds the G partials of each
-// column in order.  Both stages run in a fixed order (bit-identical results).
+// row-major, ld ldl).  Threads are (row lane, column) pairs: ncp, the power
+// of two >= nc, columns and 256 / ncp row lanes.  Stage 1: workgroup g takes
+// the rows [g chunk, (g + 1) chunk), each row lane every (256 / ncp)-th of
+// them with eight loads in flight, and the row lanes of a column are added
+// in lane order in LDS.  Stage 2 (one workgroup) adds the workgroups'
+// partials of each column the same way.  Every sum has a fixed order, so the
+// result is bit-identical from run to run.
+__device__ __forceinline__ double lanes_in_order(double s, int ncp, double* red) {
+  red[threadIdx.x] = s;
+  __syncthreads();
+  double t = 0.0;
+  if ((int)threadIdx.x < ncp)
+    for (int q = 0; q < 256 / ncp; ++q) t += red[q * ncp + threadIdx.x];
+  return t;
+}
+
 template <typename TL>
 __global__ __launch_bounds__(256) void k_col_sumsq_part(const TL* __restrict__ L, int64_t ldl,
-                                                        int64_t m, int64_t c0, int nc,
+                                                        int64_t m, int64_t c0, int nc, int ncp,
+                                                        int64_t chunk,
                                                         double* __restrict__ part) {
-  const int c = threadIdx.x;
-  if (c >= nc) return;
-  const int64_t G = gridDim.x;
-  const TL* lc = L + c0 + c;
+  __shared__ double red[256];
+  const int col = threadIdx.x & (ncp - 1), rl = threadIdx.x / ncp, RL = 256 / ncp;
+  const int64_t rbeg = (int64_t)blockIdx.x * chunk;
+  const int64_t rend = min(m, rbeg + chunk);
   double s = 0.0;
-  int64_t r = blockIdx.x;
-  for (; r + 7 * G < m; r += 8 * G) {
-    double v[8];
+  if (col < nc) {
+    const TL* lc = L + c0 + col;
+    int64_t r = rbeg + rl;
+    for (; r + 7 * RL < rend; r += 8 * RL) {
+      double v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = (double)lc[(r + u * G) * ldl];
+      for (int u = 0; u < 8; ++u) v[u] = (double)lc[(r + u * RL) * ldl];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s += v[u] * v[u];
+      for (int u = 0; u < 8; ++u) s += v[u] * v[u];
+    }
+    for (; r < rend; r += RL) {
+      const double v = (double)lc[r * ldl];
+      s += v * v;
+    }
   }
-  for (; r < m; r += G) {
-    const double v = (double)lc[r * ldl];
-    s += v * v;
-  }
-  part[(int64_t)blockIdx.x * nc + c] = s;
+  const double t = lanes_in_order(s, ncp, red);
+  if ((int)threadIdx.x < nc) part[(int64_t)blockIdx.x * nc + threadIdx.x] = t;
 }
 
 __global__ __launch_bounds__(256) void k_col_sumsq_final(const double* __restrict__ part,
-                                                         int G, int nc,
+                                                         int G, int nc, int ncp,
                                                          double* __restrict__ out) {
-  const int c = threadIdx.x;
-  if (c >= nc) return;
+  __shared__ double red[256];
+  const int col = threadIdx.x & (ncp - 1), rl = threadIdx.x / ncp, RL = 256 / ncp;
   double s = 0.0;
-  for (int g = 0; g < G; ++g) s += part[(int64_t)g * nc + c];
-  out[c] = s;
+  if (col < nc) {
+    int g = rl;
+    for (; g + 7 * RL < G; g += 8 * RL) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(g + u * RL) * nc + col];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; g < G; g += RL) s += part[(int64_t)g * nc + col];
+  }
+  const double t = lanes_in_order(s, ncp, red);
+  if ((int)threadIdx.x < nc) out[threadIdx.x] = t;
 }
 
 int col_sumsq_groups(int64_t m) {
-  return (int)std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(m, (int64_t)64)));
+  return (int)std::min<int64_t>(256, std::max<int64_t>(1, ceil_div(m, (int64_t)256)));
 }
 
 hipError_t launch_col_sumsq(const void* L, int l_f64, int64_t ldl, int64_t m, int64_t c0,
                             int nc, double* part, double* out, hipStream_t s) {
   if (nc <= 0) return hipSuccess;
   if (nc > 256 || m <= 0) return hipErrorInvalidValue;
+  int ncp = 1;
+  while (ncp < nc) ncp <<= 1;
   const int G = col_sumsq_groups(m);
+  const int64_t chunk = ceil_div(m, (int64_t)G);
   if (l_f64)
     hipLaunchKernelGGL(k_col_sumsq_part<double>, dim3(G), dim3(256), 0, s, (const double*)L,
-                       ldl, m, c0, nc, part);
+                       ldl, m, c0, nc, ncp, chunk, part);
   else
     hipLaunchKernelGGL(k_col_sumsq_part<float>, dim3(G), dim3(256), 0, s, (const float*)L, ldl,
-                       m, c0, nc, part);
-  hipLaunchKernelGGL(k_col_sumsq_final, dim3(1), dim3(256), 0, s, part, G, nc, out);
+                       m, c0, nc, ncp, chunk, part);
+  hipLaunchKernelGGL(k_col_sumsq_final, dim3(1), dim3(256), 0, s, part, G, nc, ncp, out);
   return hipGetLastError();
 }
 

@@ -456,8 +456,10 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
   // prefix that ends j columns into the last block is its starting residual
   // minus the squared norms of its first j columns of L (L-hat = X Q'); the
   // shortest prefix that meets the stopping rule is kept.  The partial sums
-  // use the residual buffer (no longer needed), the column norms C.
-  if (o.trim && !o.fixed_rank && kS - k_last > 1 && !(sum_d > tau * D0)) {
+  // use the residual buffer (no longer needed), the column norms C.  Not in
+  // the BF16 form: its tracked residual carries the BF16 rounding, and the
+  // whole last block keeps the slack that covers it.
+  if (o.trim && !o.fixed_rank && !p.bf16 && kS - k_last > 1 && !(sum_d > tau * D0)) {
     const int nc = (int)(kS - k_last);
     const int G = col_sumsq_groups(m);
     const size_t rsz = (size_t)p.mr * p.ldr * (p.r_f64 ? sizeof(double) : sizeof(float));

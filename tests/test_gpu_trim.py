@@ -104,3 +104,11 @@ def test_trim_ignored_with_fixed_rank(rb):
     t = _run(rb, X, 0.5, 16, 3, k_max=37, fixed_rank=True, trim=True)
     assert a.k == t.k == 37
     assert a.S.cpu().tolist() == t.S.cpu().tolist()
+
+
+def test_trim_ignored_in_bf16_form(rb):
+    X = adversarial_gmm(6000, 250, sub_dim=125, n_comp=20, seed=1)
+    a = _run(rb, X, 1e-3, 32, 1, precision="bf16")
+    t = _run(rb, X, 1e-3, 32, 1, precision="bf16", trim=True)
+    assert a.k == t.k
+    assert a.S.cpu().tolist() == t.S.cpu().tolist()
