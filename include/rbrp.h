@@ -60,7 +60,10 @@ typedef enum { RBRP_F32 = 0, RBRP_F64 = 1 } rbrp_dtype;
 typedef enum { RBRP_PREC_NATIVE = 0, RBRP_PREC_BF16 = 1 } rbrp_precision;
 
 typedef struct {
-  double tau_b;        /* filter tolerance of Alg. 2 (Remark 4.2); <= 0 -> 1/b  */
+  double tau_b;        /* filter tolerance of Alg. 2 (Remark 4.2): < 0 -> 1/b
+                          (RBRP, the default); 0 -> plain BRP (no filter:
+                          every sampled row is kept while the block's
+                          pivoted factor stays positive definite); at most 1 */
   int64_t k_max;       /* capacity of S and W; <= 0 -> min(m, n)                */
   int32_t fixed_rank;  /* 1: ignore eps and stop at |S| = k_max (Alg. 2, "or k") */
   int32_t greedy;      /* 1: take the b largest residual norms instead of

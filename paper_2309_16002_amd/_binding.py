@@ -179,11 +179,11 @@ def _check_matrix(X):
         raise ValueError("X must be a 2-D row-major tensor (unit column stride)")
 
 
-def make_options(k_max=0, tau_b=0.0, fixed_rank=False, greedy=False, precision="native",
+def make_options(k_max=0, tau_b=None, fixed_rank=False, greedy=False, precision="native",
                  theta=0.0, w_refine=-1, profile=False, trim=False):
     o = rbrp_options()
     lib().rbrp_default_options(ctypes.byref(o))
-    o.tau_b = float(tau_b)
+    o.tau_b = -1.0 if tau_b is None else float(tau_b)
     o.k_max = int(k_max)
     o.fixed_rank = int(bool(fixed_rank))
     o.greedy = int(bool(greedy))

@@ -367,7 +367,7 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
       continue;
     }
     const T* X = reinterpret_cast<const T*>(ds.X);
-    const double tau_b = prm.tau_b > 0.0 ? prm.tau_b : 1.0 / b;
+    const double tau_b = prm.tau_b < 0.0 ? 1.0 / b : prm.tau_b;
     const double tau = prm.eps * prm.eps;
 
     // ---- initial norms, R^T <- X^T (zero columns n..n8), skeleton flags ----

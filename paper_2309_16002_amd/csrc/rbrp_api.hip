@@ -72,7 +72,7 @@ struct Work {
 
 void fill_defaults(rbrp_options* o) {
   memset(o, 0, sizeof(*o));
-  o->tau_b = 0.0;
+  o->tau_b = -1.0;
   o->k_max = 0;
   o->fixed_rank = 0;
   o->greedy = 0;
@@ -88,6 +88,7 @@ bool make_plan(rbrp_dtype dt, int64_t m, int64_t n, int32_t b, const rbrp_option
   rbrp_options o;
   if (opt) o = *opt; else fill_defaults(&o);
   if (o.precision != RBRP_PREC_NATIVE && o.precision != RBRP_PREC_BF16) return false;
+  if (!(o.tau_b <= 1.0)) return false;   // NaN or above 1
   p->dt = dt;
   p->m = m;
   p->n = n;
@@ -286,7 +287,7 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
   if (!h) return RBRP_E_HIP;
   hipEvent_t ev_scalars = scalars_event();
   if (!ev_scalars) return RBRP_E_HIP;
-  const double tau_b = o.tau_b > 0.0 ? o.tau_b : 1.0 / b;
+  const double tau_b = o.tau_b < 0.0 ? 1.0 / b : o.tau_b;
   const double theta = o.theta > 0.0 ? o.theta : 25.0 * eps;
   const int refine = p.refine;
   const int64_t k_max = p.k_max;
@@ -642,6 +643,7 @@ static rbrp_status batch_check(int32_t count, rbrp_dtype dtype, double eps,
   if (!rbrp::batch_shape_ok(shape)) return RBRP_E_INVALID;
   rbrp_default_options(o);
   if (opt) *o = *opt;
+  if (!(o->tau_b <= 1.0)) return RBRP_E_INVALID;
   if (o->greedy || o->precision != RBRP_PREC_NATIVE) return RBRP_E_UNSUPPORTED;
   if (ws_bytes < rbrp::batch_workspace_size(dtype, shape)) return RBRP_E_WORKSPACE;
   if (rbrp::batch_lds_needed(dtype, shape) > 128 * 1024) return RBRP_E_UNSUPPORTED;
