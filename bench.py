@@ -225,6 +225,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true",
                     help="skip the BF16 precision-form leg")
+    ap.add_argument("--block", type=int, default=0, metavar="B",
+                    help="override the workload's block size b (b = 1 is sequential random "
+                         "pivoting, Algorithm 1: the matrix-vector baseline)")
     ap.add_argument("--trim", action="store_true",
                     help="rank trimming: cut k to the shortest prefix of the selection "
                          "that meets eps (an option of rbrp_id; off in the default line)")
@@ -256,7 +259,9 @@ def main():
         print(json.dumps({"copy_bytes": n_el * 4}))
         return
     rb.lib()
-    cfg = WORKLOADS[args.workload]
+    cfg = dict(WORKLOADS[args.workload])
+    if args.block:
+        cfg["b"] = args.block
     if args.workload == "kernel_blocks_batched":
         bench_batched(args, cfg)
         return

@@ -72,3 +72,18 @@ def test_tau_b_above_one_is_rejected(rb):
     X = np.ones((50, 10))
     with pytest.raises(rb.RBRPError):
         _run(rb, X, 1e-2, 4, 0, tau_b=1.5)
+
+
+@pytest.mark.parametrize("eps,seed", [(1e-2, 1), (1e-3, 2)])
+def test_b1_is_sequential_random_pivoting(rb, eps, seed):
+    # Alg. 1 (SRP): one row per step, drawn in proportion to the residual's
+    # squared row norms; the oracle's independent SRP code
+    from oracle import srp
+    X = svd_matrix(300, 80, geometric_spectrum(80, 0.85), seed=4000 + seed)
+    S_ref, _, _, _ = srp(X, eps, seed)
+    res = _run(rb, X, eps, 1, seed)
+    S = res.S.cpu().tolist()
+    assert S == list(S_ref)
+    W = res.W.cpu().numpy()
+    Wref = w_lstsq(X, S)
+    assert np.linalg.norm(W - Wref) <= 1e-10 * np.linalg.norm(Wref)
