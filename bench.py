@@ -228,6 +228,9 @@ def main():
     ap.add_argument("--block", type=int, default=0, metavar="B",
                     help="override the workload's block size b (b = 1 is sequential random "
                          "pivoting, Algorithm 1: the matrix-vector baseline)")
+    ap.add_argument("--greedy", action="store_true",
+                    help="blockwise greedy pivoting (the b largest residual norms, Remark 4.3) "
+                         "instead of sampling; with --block 1 this is column-pivoted QR")
     ap.add_argument("--trim", action="store_true",
                     help="rank trimming: cut k to the shortest prefix of the selection "
                          "that meets eps (an option of rbrp_id; off in the default line)")
@@ -288,7 +291,8 @@ def main():
         def step(seed, profile="deflate"):
             return rb.rbrp_id(Xg, cfg["eps"], cfg["b"], seed, workspace=ws, out_S=S_buf,
                               out_W=W_buf, precision=precision, profile=profile,
-                              k_max=k_max, fixed_rank=fixed, trim=args.trim)
+                              k_max=k_max, fixed_rank=fixed, trim=args.trim,
+                              greedy=args.greedy)
         for i in range(warmup):
             step(1000 + i)
             print(f"[bench] {precision} warmup {i + 1}/{warmup} done", file=sys.stderr,
@@ -365,6 +369,7 @@ def main():
                    "b": cfg["b"], "tau_b": 1.0 / cfg["b"],
                    **({"fixed_rank": k_max} if fixed else {}),
                    **({"trim": True} if args.trim else {}),
+                   **({"greedy": True} if args.greedy else {}),
                    "deflation": "fp64-mfma" if dtype == "f64" else "fp32-mfma (plain)",
                    "parallelism": "single-gpu"},
         "roofline": roofline,

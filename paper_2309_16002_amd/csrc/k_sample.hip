@@ -18,6 +18,8 @@
 // de-duplicates them in candidate order.
 #include "rbrp_wg.h"
 
+#include <utility>
+
 namespace rbrp {
 
 // 256 threads x 8 rows per tile, one workgroup per tile.
@@ -68,65 +70,125 @@ hipError_t launch_sample(const uint64_t* cdf_local, const uint64_t* tile_sum,
   return hipGetLastError();
 }
 
-// Greedy top-b selection (Remark 4.3): b rounds of a fixed-order argmax over
-// the rows not yet in S and not yet chosen; equal values go to the lower index.
-__global__ __launch_bounds__(256) void k_topb(const double* __restrict__ d,
-                                              const int32_t* __restrict__ sel_block,
-                                              int64_t m, int32_t b,
-                                              int64_t* __restrict__ idx,
-                                              DevScalars* sc) {
-  __shared__ double bv[256];
-  __shared__ int64_t bi[256];
-  __shared__ int64_t chosen[kMaxB];
-  __shared__ int s_n;
+// Greedy top-b selection (Remark 4.3): the b rows not in S with the largest
+// positive d, larger value first and equal values by lower row (the order of
+// b rounds of argmax).  Positive doubles order like their bit patterns, so
+// a row is the key (bits of d_i, i).  Each workgroup bitonic-sorts a chunk
+// of kTopChunk keys in LDS and keeps its first b; passes repeat over the
+// kept keys until one chunk is left, whose first b (at most the number of
+// valid keys) are the selection.  Rows that cannot be chosen get the key
+// (0, INT64_MAX), which sorts after every valid one.
+constexpr int kTopChunk = 2048;
+
+__device__ __forceinline__ bool key_before(uint64_t va, int64_t ia, uint64_t vb, int64_t ib) {
+  return va > vb || (va == vb && ia < ib);
+}
+
+template <bool FROM_D>
+__global__ __launch_bounds__(256) void k_topb_pass(
+    const double* __restrict__ d, const int32_t* __restrict__ sel_block, int64_t m,
+    const uint64_t* __restrict__ in_v, const int64_t* __restrict__ in_i, int64_t n_in,
+    int32_t b, uint64_t* __restrict__ out_v, int64_t* __restrict__ out_i,
+    int64_t* __restrict__ idx, DevScalars* sc) {
+  __shared__ uint64_t kv[kTopChunk];
+  __shared__ int64_t ki[kTopChunk];
   const int tid = threadIdx.x;
-  if (tid == 0) s_n = 0;
-  __syncthreads();
-  for (int r = 0; r < b; ++r) {
-    const int nch = s_n;
-    double best = 0.0;
-    int64_t besti = -1;
-    for (int64_t i = tid; i < m; i += 256) {
-      const double v = d[i];
-      if (!(v > 0.0) || (sel_block && sel_block[i] >= 0)) continue;
-      bool taken = false;
-      for (int q = 0; q < nch; ++q) taken |= chosen[q] == i;
-      if (taken) continue;
-      if (v > best) { best = v; besti = i; }
+  const int64_t base = (int64_t)blockIdx.x * kTopChunk;
+#pragma unroll
+  for (int e = 0; e < kTopChunk / 256; ++e) {
+    const int sl = e * 256 + tid;
+    const int64_t g = base + sl;
+    uint64_t v = 0;
+    int64_t i = INT64_MAX;
+    if constexpr (FROM_D) {
+      if (g < m) {
+        const double x = d[g];
+        if (x > 0.0 && !(sel_block && sel_block[g] >= 0)) {
+          v = (uint64_t)__double_as_longlong(x);
+          i = g;
+        }
+      }
+    } else if (g < n_in) {
+      v = in_v[g];
+      i = in_i[g];
     }
-    bv[tid] = best;
-    bi[tid] = besti;
-    __syncthreads();
-    for (int h = 128; h >= 1; h >>= 1) {
-      if (tid < h) {
-        const double v2 = bv[tid + h];
-        const int64_t i2 = bi[tid + h];
-        if (i2 >= 0 && (bi[tid] < 0 || v2 > bv[tid] || (v2 == bv[tid] && i2 < bi[tid]))) {
-          bv[tid] = v2;
-          bi[tid] = i2;
+    kv[sl] = v;
+    ki[sl] = i;
+  }
+  __syncthreads();
+  for (int k = 2; k <= kTopChunk; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int e = 0; e < kTopChunk / 512; ++e) {
+        const int pr = e * 256 + tid;                  // pair index
+        const int lo = 2 * j * (pr / j) + (pr % j);    // bit j clear
+        const int hi = lo + j;
+        const uint64_t va = kv[lo], vb = kv[hi];
+        const int64_t ia = ki[lo], ib = ki[hi];
+        // runs with bit k clear are put in key order, the others reversed
+        const bool swap = ((lo & k) == 0) ? key_before(vb, ib, va, ia)
+                                          : key_before(va, ia, vb, ib);
+        if (swap) {
+          kv[lo] = vb;
+          kv[hi] = va;
+          ki[lo] = ib;
+          ki[hi] = ia;
         }
       }
       __syncthreads();
     }
-    if (tid == 0 && bi[0] >= 0) {
-      chosen[nch] = bi[0];
-      s_n = nch + 1;
-    }
-    __syncthreads();
-    if (s_n == nch) break;
   }
+  if (gridDim.x > 1) {
+    for (int r = tid; r < b; r += 256) {
+      out_v[(int64_t)blockIdx.x * b + r] = kv[r];
+      out_i[(int64_t)blockIdx.x * b + r] = ki[r];
+    }
+    return;
+  }
+  // final pass: the valid keys come first
+  __shared__ int s_n;
+  if (tid == 0) s_n = 0;
+  __syncthreads();
+  for (int r = tid; r < b; r += 256)
+    if (kv[r] != 0 && (r + 1 == b || kv[r + 1] == 0)) s_n = r + 1;
+  __syncthreads();
   const int n = s_n;
-  for (int q = tid; q < n; q += 256) idx[q] = chosen[q];
+  for (int r = tid; r < n; r += 256) idx[r] = ki[r];
   if (tid == 0) {
     sc->nt = n;
     sc->npos = n;
   }
 }
 
+int64_t topb_scratch_words(int64_t m, int32_t b) {
+  if (m <= kTopChunk) return 0;
+  return 4 * ceil_div(m, (int64_t)kTopChunk) * (int64_t)b;
+}
+
 hipError_t launch_topb(const double* d, const int32_t* sel_block, int64_t m,
-                       int32_t b, int64_t* idx, DevScalars* sc, hipStream_t s) {
-  if (b > kMaxB) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_topb, dim3(1), dim3(256), 0, s, d, sel_block, m, b, idx, sc);
+                       int32_t b, int64_t* idx, DevScalars* sc, uint64_t* scratch,
+                       int64_t scratch_words, hipStream_t s) {
+  if (b <= 0 || b > kMaxB || m <= 0) return hipErrorInvalidValue;
+  if (scratch_words < topb_scratch_words(m, b)) return hipErrorInvalidValue;
+  // ping-pong halves of the scratch: values then rows, cap keys each
+  const int64_t cap = ceil_div(m, (int64_t)kTopChunk) * b;
+  uint64_t* v0 = scratch;
+  int64_t* i0 = reinterpret_cast<int64_t*>(scratch + cap);
+  uint64_t* v1 = scratch + 2 * cap;
+  int64_t* i1 = reinterpret_cast<int64_t*>(scratch + 3 * cap);
+  int64_t G = ceil_div(m, (int64_t)kTopChunk);
+  hipLaunchKernelGGL(k_topb_pass<true>, dim3((unsigned)G), dim3(256), 0, s, d, sel_block, m,
+                     (const uint64_t*)nullptr, (const int64_t*)nullptr, (int64_t)0, b, v0, i0,
+                     idx, sc);
+  int64_t n = G * b;
+  while (G > 1) {
+    G = ceil_div(n, (int64_t)kTopChunk);
+    hipLaunchKernelGGL(k_topb_pass<false>, dim3((unsigned)G), dim3(256), 0, s, d, sel_block,
+                       m, (const uint64_t*)v0, (const int64_t*)i0, n, b, v1, i1, idx, sc);
+    n = G * b;
+    std::swap(v0, v1);
+    std::swap(i0, i1);
+  }
   return hipGetLastError();
 }
 

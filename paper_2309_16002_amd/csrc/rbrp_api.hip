@@ -327,7 +327,7 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     prof.begin(1);
     hipError_t e;
     if (o.greedy) {
-      e = launch_topb(w.d, w.sel_block, m, bsz, w.idx, w.sc, s);
+      e = launch_topb(w.d, w.sel_block, m, bsz, w.idx, w.sc, w.cdf, p.m, s);
     } else {
       e = launch_weights_scan(w.d, w.sel_block, nullptr, m, w.sc, w.cdf, w.tile_sum,
                               w.tile_pos, s);

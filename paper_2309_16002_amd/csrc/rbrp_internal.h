@@ -88,9 +88,14 @@ hipError_t launch_sample(const uint64_t* cdf_local, const uint64_t* tile_sum,
                          uint64_t seed, uint64_t t, uint64_t ident,
                          int64_t* idx, DevScalars* sc, hipStream_t s);
 
-// Greedy top-b selection (Remark 4.3).
+// Greedy top-b selection (Remark 4.3): idx[0..n) the rows outside S with the
+// largest positive d (ties to the lower row), n = min(b, such rows), in
+// sc->nt and sc->npos.  scratch holds topb_scratch_words(m, b) words (none
+// for m <= 2048).
+int64_t topb_scratch_words(int64_t m, int32_t b);
 hipError_t launch_topb(const double* d, const int32_t* sel_block, int64_t m,
-                       int32_t b, int64_t* idx, DevScalars* sc, hipStream_t s);
+                       int32_t b, int64_t* idx, DevScalars* sc, uint64_t* scratch,
+                       int64_t scratch_words, hipStream_t s);
 
 // Vt[j,:] = X[idx[j], :] (FP64, zero beyond sc->nt and beyond n),
 // xs2[j] = ||X[idx[j],:]||^2.
