@@ -160,6 +160,83 @@ __global__ __launch_bounds__(256) void k_topb_pass(
   }
 }
 
+// b = 1: the first key in that order is an argmax, found by a reduction
+// (each workgroup over its rows, then one workgroup over the workgroups'
+// winners).  The order is total on (value, row), so the result does not
+// depend on the reduction's shape.
+__device__ __forceinline__ void wg_first_key(uint64_t& v, int64_t& i, uint64_t* sv,
+                                             int64_t* si) {
+  sv[threadIdx.x] = v;
+  si[threadIdx.x] = i;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if ((int)threadIdx.x < h &&
+        key_before(sv[threadIdx.x + h], si[threadIdx.x + h], sv[threadIdx.x], si[threadIdx.x])) {
+      sv[threadIdx.x] = sv[threadIdx.x + h];
+      si[threadIdx.x] = si[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  v = sv[0];
+  i = si[0];
+}
+
+__device__ __forceinline__ void top1_write(uint64_t v, int64_t i, int64_t* idx, DevScalars* sc) {
+  if (threadIdx.x == 0) {
+    const int n = v != 0 ? 1 : 0;
+    if (n) idx[0] = i;
+    sc->nt = n;
+    sc->npos = n;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_top1_part(const double* __restrict__ d,
+                                                   const int32_t* __restrict__ sel_block,
+                                                   int64_t m, int64_t chunk,
+                                                   uint64_t* __restrict__ out_v,
+                                                   int64_t* __restrict__ out_i,
+                                                   int64_t* __restrict__ idx, DevScalars* sc) {
+  __shared__ uint64_t sv[256];
+  __shared__ int64_t si[256];
+  const int64_t rbeg = (int64_t)blockIdx.x * chunk;
+  const int64_t rend = min(m, rbeg + chunk);
+  uint64_t v = 0;
+  int64_t i = INT64_MAX;
+  for (int64_t g = rbeg + threadIdx.x; g < rend; g += 256) {
+    const double x = d[g];
+    if (x > 0.0 && !(sel_block && sel_block[g] >= 0)) {
+      const uint64_t xv = (uint64_t)__double_as_longlong(x);
+      if (key_before(xv, g, v, i)) {
+        v = xv;
+        i = g;
+      }
+    }
+  }
+  wg_first_key(v, i, sv, si);
+  if (gridDim.x == 1) {
+    top1_write(v, i, idx, sc);
+  } else if (threadIdx.x == 0) {
+    out_v[blockIdx.x] = v;
+    out_i[blockIdx.x] = i;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_top1_final(const uint64_t* __restrict__ in_v,
+                                                    const int64_t* __restrict__ in_i, int G,
+                                                    int64_t* __restrict__ idx, DevScalars* sc) {
+  __shared__ uint64_t sv[256];
+  __shared__ int64_t si[256];
+  uint64_t v = 0;
+  int64_t i = INT64_MAX;
+  for (int g = threadIdx.x; g < G; g += 256)
+    if (key_before(in_v[g], in_i[g], v, i)) {
+      v = in_v[g];
+      i = in_i[g];
+    }
+  wg_first_key(v, i, sv, si);
+  top1_write(v, i, idx, sc);
+}
+
 int64_t topb_scratch_words(int64_t m, int32_t b) {
   if (m <= kTopChunk) return 0;
   return 4 * ceil_div(m, (int64_t)kTopChunk) * (int64_t)b;
@@ -170,6 +247,16 @@ hipError_t launch_topb(const double* d, const int32_t* sel_block, int64_t m,
                        int64_t scratch_words, hipStream_t s) {
   if (b <= 0 || b > kMaxB || m <= 0) return hipErrorInvalidValue;
   if (scratch_words < topb_scratch_words(m, b)) return hipErrorInvalidValue;
+  if (b == 1) {
+    const int G = (int)ceil_div(m, (int64_t)kTopChunk);   // <= scratch_words / 4
+    const int64_t chunk = ceil_div(m, (int64_t)G);
+    hipLaunchKernelGGL(k_top1_part, dim3(G), dim3(256), 0, s, d, sel_block, m, chunk, scratch,
+                       reinterpret_cast<int64_t*>(scratch + G), idx, sc);
+    if (G > 1)
+      hipLaunchKernelGGL(k_top1_final, dim3(1), dim3(256), 0, s, (const uint64_t*)scratch,
+                         reinterpret_cast<const int64_t*>(scratch + G), G, idx, sc);
+    return hipGetLastError();
+  }
   // ping-pong halves of the scratch: values then rows, cap keys each
   const int64_t cap = ceil_div(m, (int64_t)kTopChunk) * b;
   uint64_t* v0 = scratch;

@@ -56,6 +56,7 @@ def test_plain_brp_matches_oracle(rb, m, n, b, eps, seed):
     (400, 120, 16, 1e-2), (1500, 200, 8, 1e-3),
     (5000, 150, 32, 1e-2),    # more than one 2048-row chunk: two selection passes
     (20000, 100, 64, 1e-2),   # ten chunks, then a pass over their kept keys
+    (5000, 150, 1, 1e-2),     # b = 1: the argmax path over three chunks
 ])
 def test_greedy_blocks_match_oracle(rb, m, n, b, eps):
     X = svd_matrix(m, n, geometric_spectrum(min(m, n), 0.9), seed=3000 + m)
