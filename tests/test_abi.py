@@ -166,3 +166,23 @@ def test_batched_rejects_before_device_work(L):
 def test_batch_desc_layout():
     assert ctypes.sizeof(B.rbrp_batch_desc) == 64
     assert ctypes.sizeof(B.rbrp_batch_shape) == 32
+
+
+def test_default_options_and_binding_mapping(L):
+    # defaults: tau_b < 0 (-> 1/b), one W refinement step, no trimming
+    o = B.rbrp_options()
+    L.rbrp_default_options(ctypes.byref(o))
+    assert o.tau_b < 0 and o.w_refine < 0 and o.trim == 0 and o.k_max == 0
+    assert o.fixed_rank == 0 and o.greedy == 0
+    # the binding: tau_b=None keeps the default, 0.0 asks for plain BRP
+    assert B.make_options().tau_b < 0
+    assert B.make_options(tau_b=0.0).tau_b == 0.0
+    assert B.make_options(trim=True).trim == 1
+    assert ctypes.sizeof(B.rbrp_options) == 48
+
+
+def test_tau_b_above_one_is_rejected_by_workspace_size(L):
+    o = B.make_options(tau_b=1.5)
+    assert L.rbrp_workspace_size(0, 100, 20, 8, ctypes.byref(o)) == 0
+    o = B.make_options(tau_b=0.0)
+    assert L.rbrp_workspace_size(0, 100, 20, 8, ctypes.byref(o)) > 0
