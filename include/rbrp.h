@@ -53,8 +53,9 @@ typedef enum { RBRP_F32 = 0, RBRP_F64 = 1 } rbrp_dtype;
  * NATIVE: the input's type on MFMA (FP64 for F64 input; FP32 for F32 input,
  *         the "plain" single-precision form).
  * BF16:   BF16 MFMA operands with FP32 accumulation on an FP32 residual;
- *         split into hi+lo BF16 parts (three products) while the tracked
- *         relative residual is above theta, one BF16 product below it.
+ *         per block either split into hi+lo BF16 parts (three products) or
+ *         one BF16 product, chosen by the error budget of rbrp_options.theta
+ *         (the FP32 product where neither fits the budget).
  * In every mode the residual norms, the projection and reorthogonalisation
  * of the basis, the block CPQR and the solve for W are FP64. */
 typedef enum { RBRP_PREC_NATIVE = 0, RBRP_PREC_BF16 = 1 } rbrp_precision;
@@ -71,7 +72,13 @@ typedef struct {
   int32_t precision;   /* rbrp_precision                                         */
   int32_t w_refine;    /* iterative-refinement steps of the FP64 W solve
                           (Alg. 3); < 0 -> 1                                  */
-  double theta;        /* BF16 mode: split/plain switch; <= 0 -> 25 * eps        */
+  double theta;        /* BF16 mode.  > 0: split products while the tracked
+                          relative residual is above theta, one BF16 product
+                          below it.  <= 0 (the default): every block takes
+                          the cheapest of one BF16 product, the split BF16
+                          products and the FP32 product whose contribution,
+                          if kept for all later blocks, holds the error bound
+                          err_bound (rbrp_stats) within eps / 4            */
   int32_t profile;     /* 1: time the phases with HIP events on ``stream`` and
                           report them in rbrp_stats; 2: time only the
                           deflation launches (ms_deflate, deflate_launches)    */
@@ -96,6 +103,11 @@ typedef struct {
   int32_t blocks;          /* T, the number of sampled blocks                 */
   int32_t blocks_split;    /* BF16 mode: blocks deflated with hi+lo products  */
   double resid_tracked;    /* sqrt(||d||_1 / ||d^(0)||_1) at exit             */
+  double err_bound;        /* E_T: bound on ||R - X (I - Q Q^T)||_F / ||X||_F
+                              for the part of the deflation rounding that can
+                              lower the tracked residual below the optimal
+                              error on S (see rbrp_err_bound_increment); the
+                              loop stops when resid_tracked + err_bound <= eps */
   double norm_x_fro;       /* ||X||_F                                         */
   /* filled when rbrp_options.profile = 1 (milliseconds, HIP events; with
      profile = 2 only ms_deflate, deflate_flops and deflate_launches) */
@@ -106,7 +118,8 @@ typedef struct {
   double ms_interp;        /* W from L (Algorithm 3)                          */
   double deflate_flops;    /* algorithmic flops of the deflations: sum 4 m n b' */
   int32_t deflate_launches;
-  int32_t reserved0;
+  int32_t blocks_native;   /* BF16 mode: blocks the controller deflated with
+                              the FP32 product                              */
   int32_t bprime[256];     /* b' of the first 256 blocks                       */
 } rbrp_stats;
 
@@ -125,9 +138,14 @@ size_t rbrp_workspace_size(rbrp_dtype dtype, int64_t m, int64_t n, int32_t b,
  * Computes skeleton rows S and W with X ~= W X(S,:), stopping at the first
  * block boundary where ||X - W X(S,:)||_F <= eps ||X||_F as tracked by the
  * residual squared row norms (Alg. 2 stopping rule with tau = eps^2; the
- * rank-adaptive property of the paper's introduction).
+ * rank-adaptive property of the paper's introduction).  The tracked value
+ * carries the rounding of the deflation products, so the rule applied is
+ * rho + E <= eps, rho = sqrt(||d||_1 / ||d^(0)||_1) and E the running
+ * bound err_bound of rbrp_stats (about 1e-7 for FP32 products; for the BF16
+ * form at most eps / 4 under the default controller).
  *
- * X      [m x n], ld ldx, dtype F32 or F64; read only.
+ * X      [m x n], ld ldx, dtype F32 or F64; read only.  m <= 4096 * 2048
+ *        (the sampler's integer CDF tiles); larger m -> RBRP_E_UNSUPPORTED.
  * eps    relative Frobenius tolerance, 0 < eps < 1 (ignored if fixed_rank).
  * b      block size, 1 <= b <= 256.  Blocks with b' > 128 kept rows are
  *        deflated in two launches (columns 1..128, then the rest); for
@@ -153,6 +171,35 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n,
 
 /* Static text for a status code. */
 const char* rbrp_status_string(rbrp_status s);
+
+/*
+ * Increment of the squared error bound after one deflated block (host
+ * arithmetic only; no device work).  The block removed P = R Q' from the
+ * stored residual R (Alg. 2's L-hat update in explicit form); its products
+ * round Q' to the operand precision of ``mode`` and accumulate in FP32 (FP64
+ * for mode 0).  Rounding that lands in span(Q') only raises the tracked norm
+ * (it is orthogonal to X (I - Q Q^T) for every later basis); the rest -- the
+ * operand rounding of Q' in the update P Q'^T (applied to P and to the
+ * error of P), the product a split form drops and the accumulator rounding --
+ * is bounded under the model of independent, mean-zero relative rounding
+ * errors uniform in [-u, u] (variance u^2 / 3):
+ *
+ *   v = (s_q^2 + s_x^2) p^2 + ((s_q u_op)^2 + s_a^2 (bprime / kstep + 1)) r_prev^2,
+ *   p^2 = max(r_prev^2 - r_new^2, 0),
+ *
+ * with r_prev^2, r_new^2 the tracked squared residual norms before and after
+ * the block (relative to ||X||_F^2), s_q the operand-rounding deviation of
+ * Q' (u / sqrt 3, u = 2^-53, 2^-24, 2^-16 for split BF16, 2^-8 for BF16), s_x
+ * that of the dropped lo*lo product (2^-16 / sqrt 3, split only), u_op the
+ * relative error bound of the product R Q' (2u; 3 * 2^-16 split), s_a the
+ * accumulator's (2^-24 / sqrt 3; 2^-53 / sqrt 3 for FP64) and kstep the
+ * columns one MFMA step adds (4 for FP64/FP32, 32 for BF16).
+ * The bound after block t is err_bound = 3 sqrt(sum of v over blocks 1..t).
+ * mode: 0 FP64, 1 FP32, 2 split BF16 (hi + lo, three products), 3 BF16.
+ * Returns a negative value for an unknown mode or bprime < 0.
+ */
+double rbrp_err_bound_increment(int32_t mode, int32_t bprime, double r_prev_sq,
+                                double r_new_sq);
 
 /* ---- single-step entry points (the steps of Algorithm 2 in isolation) ---- */
 

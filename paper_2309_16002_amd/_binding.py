@@ -44,6 +44,7 @@ class rbrp_stats(ctypes.Structure):
         ("blocks", ctypes.c_int32),
         ("blocks_split", ctypes.c_int32),
         ("resid_tracked", ctypes.c_double),
+        ("err_bound", ctypes.c_double),
         ("norm_x_fro", ctypes.c_double),
         ("ms_init", ctypes.c_double),
         ("ms_select", ctypes.c_double),
@@ -52,7 +53,7 @@ class rbrp_stats(ctypes.Structure):
         ("ms_interp", ctypes.c_double),
         ("deflate_flops", ctypes.c_double),
         ("deflate_launches", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("blocks_native", ctypes.c_int32),
         ("bprime", ctypes.c_int32 * 256),
     ]
 
@@ -102,6 +103,7 @@ SIGNATURES = {
                            _c.POINTER(rbrp_options), _vp, _c.POINTER(_i64), _vp, _i64,
                            _c.POINTER(rbrp_stats), _vp, _sz, _vp]),
     "rbrp_status_string": (_c.c_char_p, [_c.c_int]),
+    "rbrp_err_bound_increment": (_dbl, [_i32, _i32, _dbl, _dbl]),
     "rbrp_row_norms_workspace_size": (_sz, [_i64]),
     "rbrp_row_norms": (_c.c_int, [_vp, _c.c_int, _i64, _i64, _i64, _vp,
                                   _c.POINTER(_dbl), _c.POINTER(_dbl), _vp, _sz, _vp]),
@@ -207,6 +209,8 @@ class IDResult:
     resid_tracked: float
     norm_x: float
     profile: dict = None
+    err_bound: float = 0.0       # bound on the rounding in the tracked residual
+    blocks_native: int = 0       # BF16 form: blocks deflated with the FP32 product
 
 
 def workspace_size(m, n, b, dtype="f32", **opts):
@@ -260,7 +264,18 @@ def rbrp_id(X, eps, b, seed=0, *, want_w=True, workspace=None, out_S=None, out_W
                     deflate_flops=st.deflate_flops, deflate_launches=st.deflate_launches)
     return IDResult(S[:kk], kk, W[:, :kk] if W is not None else None, status, st.blocks,
                     st.blocks_split, [int(x) for x in st.bprime[:nb]], st.resid_tracked,
-                    st.norm_x_fro, prof)
+                    st.norm_x_fro, prof, st.err_bound, st.blocks_native)
+
+
+DEFLATE_MODES = {"f64": 0, "f32": 1, "bf16x3": 2, "bf16": 3}
+
+
+def err_bound_increment(mode, bprime, r_prev_sq, r_new_sq):
+    """Variance increment of the rounding bound after one deflated block
+    (host arithmetic of the library; see rbrp_err_bound_increment)."""
+    code = DEFLATE_MODES[mode] if isinstance(mode, str) else int(mode)
+    return float(lib().rbrp_err_bound_increment(code, int(bprime), float(r_prev_sq),
+                                                float(r_new_sq)))
 
 
 def row_norms(X):

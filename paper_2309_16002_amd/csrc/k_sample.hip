@@ -48,7 +48,7 @@ hipError_t launch_weights_scan(const double* d, const int32_t* sel_block,
   return hipGetLastError();
 }
 
-constexpr int kMaxTiles = 4096;  // rows up to 4096 * 2048 per decomposition
+constexpr int kMaxTiles = kMaxScanTiles;  // rows up to kMaxRows per decomposition
 
 
 __global__ __launch_bounds__(kSampleThreads) void k_sample(

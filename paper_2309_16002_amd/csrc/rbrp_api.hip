@@ -85,6 +85,7 @@ bool make_plan(rbrp_dtype dt, int64_t m, int64_t n, int32_t b, const rbrp_option
                Plan* p) {
   if (dt != RBRP_F32 && dt != RBRP_F64) return false;
   if (m <= 0 || n <= 0 || b < 1 || b > kMaxB) return false;
+  if (m > kMaxRows) return false;   // the sampler's integer CDF tiles
   rbrp_options o;
   if (opt) o = *opt; else fill_defaults(&o);
   if (o.precision != RBRP_PREC_NATIVE && o.precision != RBRP_PREC_BF16) return false;
@@ -155,6 +156,59 @@ DevScalars* host_scalars() {
   return h;
 }
 
+// ---- running bound on the deflation rounding (the precision controller) ----
+//
+// Block s replaces the stored residual R by R - P Q'^T, P = R Q'.  Rounding
+// that falls in span(Q') (the product R Q' itself, and the operand rounding of
+// P in the update) stays orthogonal to X (I - Q Q^T) for every later basis, so
+// it can only raise the tracked norm.  The rest can lower it: the operand
+// rounding of Q' in the update (sd s_q |P|), the lo*lo product a split form
+// drops (sd s_x |P|), the same rounding of Q' applied to the error of R Q'
+// (at most u_op |R|), and the FP32 accumulator (sd s_a per rounding, about
+// bprime / kstep + 1 roundings of values of size |R|).  With independent,
+// mean-zero relative errors uniform in [-u, u] the squared Frobenius norm of
+// that part has expectation at most v below; blocks add (orthogonal
+// projections do not enlarge earlier errors), and the bound is kErrLambda
+// standard deviations of the sum.
+constexpr double kErrLambda = 3.0;
+constexpr double kErrBudget = 0.25;   // default controller: E <= eps / 4
+
+struct ModeDev { double sq, sx, sa, uop; int kstep; };
+
+bool mode_dev(int mode, ModeDev* d) {
+  const double r3 = 1.0 / sqrt(3.0);
+  const double u64 = ldexp(1.0, -53), u32 = ldexp(1.0, -24), ub = ldexp(1.0, -8);
+  switch (mode) {
+    case kModeF64: *d = {u64 * r3, 0.0, u64 * r3, 2 * u64, 4}; return true;
+    case kModeF32: *d = {u32 * r3, 0.0, u32 * r3, 2 * u32, 4}; return true;
+    case kModeBF16x3: *d = {ub * ub * r3, ub * ub * r3, u32 * r3, 3 * ub * ub, 32}; return true;
+    case kModeBF16: *d = {ub * r3, 0.0, u32 * r3, 2 * ub, 32}; return true;
+  }
+  return false;
+}
+
+// Variance increment of one block (relative to ||X||_F^2); -1 on bad input.
+double err_var_increment(int mode, int bprime, double r_prev_sq, double r_new_sq) {
+  ModeDev md;
+  if (!mode_dev(mode, &md) || bprime < 0) return -1.0;
+  const double p2 = fmax(r_prev_sq - r_new_sq, 0.0);
+  const double rp2 = fmax(r_prev_sq, 0.0);
+  return (md.sq * md.sq + md.sx * md.sx) * p2 +
+         (md.sq * md.uop * md.sq * md.uop +
+          md.sa * md.sa * ((double)bprime / md.kstep + 1.0)) * rp2;
+}
+
+// Worst contribution of keeping ``mode`` for every later block, starting from
+// the relative squared residual r_sq: the later blocks remove at most r_sq in
+// total, and the terms in |R| are allowed for up to 64 more blocks.
+double err_var_future(int mode, int b, double r_sq) {
+  ModeDev md;
+  if (!mode_dev(mode, &md)) return 1e300;
+  return (md.sq * md.sq + md.sx * md.sx) * r_sq +
+         64.0 * (md.sq * md.uop * md.sq * md.uop +
+                 md.sa * md.sa * ((double)b / md.kstep + 1.0)) * r_sq;
+}
+
 #define RBRP_HIP(expr)                             \
   do {                                             \
     hipError_t e_ = (expr);                        \
@@ -195,12 +249,12 @@ struct Profiler {
     sp.b = pool_event(2 * n + 1);
     if (!sp.a || !sp.b) { level = 0; return; }
     sp.phase = phase;
-    hipEventRecord(sp.a, s);
+    (void)hipEventRecord(sp.a, s);
     open = true;
   }
   void end() {
     if (!open) return;
-    hipEventRecord(spans[n].b, s);
+    (void)hipEventRecord(spans[n].b, s);
     ++n;
     open = false;
   }
@@ -237,6 +291,11 @@ void rbrp_default_options(rbrp_options* opt) {
   if (opt) fill_defaults(opt);
 }
 
+double rbrp_err_bound_increment(int32_t mode, int32_t bprime, double r_prev_sq,
+                                double r_new_sq) {
+  return err_var_increment(mode, bprime, r_prev_sq, r_new_sq);
+}
+
 const char* rbrp_status_string(rbrp_status s) {
   switch (s) {
     case RBRP_OK: return "ok";
@@ -267,6 +326,7 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
   if (opt) o = *opt; else fill_defaults(&o);
   Plan p;
   if (!X || !S || !k_host || !workspace) return RBRP_E_INVALID;
+  if (m > kMaxRows && (dtype == RBRP_F32 || dtype == RBRP_F64)) return RBRP_E_UNSUPPORTED;
   if (!make_plan(dtype, m, n, b, &o, &p)) return RBRP_E_INVALID;
   if (ldx < n) return RBRP_E_INVALID;
   if (!o.fixed_rank && !(eps > 0.0 && eps < 1.0)) return RBRP_E_INVALID;
@@ -274,7 +334,8 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
   if (p.bf16 && dtype != RBRP_F32) return RBRP_E_UNSUPPORTED;
   const int mode_hi = p.bf16 ? kModeBF16x3 : p.native_mode;
   const int mode_lo = p.bf16 ? kModeBF16 : p.native_mode;
-  if (!deflate_supported(mode_hi, p.ldr, p.bdef) || !deflate_supported(mode_lo, p.ldr, p.bdef))
+  if (!deflate_supported(mode_hi, p.ldr, p.bdef) || !deflate_supported(mode_lo, p.ldr, p.bdef) ||
+      !deflate_supported(p.native_mode, p.ldr, p.bdef))
     return RBRP_E_UNSUPPORTED;
   Work w;
   const size_t need = layout(p, nullptr, &w);
@@ -288,7 +349,7 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
   hipEvent_t ev_scalars = scalars_event();
   if (!ev_scalars) return RBRP_E_HIP;
   const double tau_b = o.tau_b < 0.0 ? 1.0 / b : o.tau_b;
-  const double theta = o.theta > 0.0 ? o.theta : 25.0 * eps;
+  const double theta = o.theta;   // > 0: fixed split/plain switch; else the budget
   const int refine = p.refine;
   const int64_t k_max = p.k_max;
   const int64_t ldr = p.ldr;
@@ -317,11 +378,18 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     if (stats_host) *stats_host = st;
     return RBRP_OK;
   }
-  const double tau = eps * eps;
   int64_t kS = 0;
   int32_t t = 0;
   rbrp_status final_status = RBRP_OK;
   double sum_d = h->sum_d;
+  // running variance of the rounding bound; the stopping rule of Alg. 2 is
+  // applied to the tracked residual plus the bound
+  double err_var = 0.0;
+  auto err_bound = [&]() { return kErrLambda * sqrt(err_var); };
+  auto met = [&](double sd) {
+    const double e = eps - err_bound();
+    return e > 0.0 && sd <= e * e * D0;
+  };
   const int def_rows = deflate_rows_per_wg(mode_hi, ldr);
   auto select_block = [&](int32_t tt, int32_t bsz) -> hipError_t {
     prof.begin(1);
@@ -345,10 +413,10 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
   double sum_last = sum_d;   // tracked squared residual before that block
   while (true) {
     if (kS >= k_max) {
-      if (!o.fixed_rank && sum_d > tau * D0) final_status = RBRP_E_CAPACITY;
+      if (!o.fixed_rank && !met(sum_d)) final_status = RBRP_E_CAPACITY;
       break;
     }
-    if (!o.fixed_rank && !(sum_d > tau * D0)) break;
+    if (!o.fixed_rank && met(sum_d)) break;
     ++t;
     const int32_t bt = (int32_t)((int64_t)b < k_max - kS ? b : k_max - kS);
     // sampling (or greedy top-b) and V^T, the sampled rows of X in FP64 --
@@ -405,9 +473,23 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     // deflation of the residual, in launches of at most kDeflateMaxB columns
     int mode = p.native_mode;
     if (p.bf16) {
-      const double rho = sqrt(sum_d / D0);
-      mode = rho > theta ? kModeBF16x3 : kModeBF16;
+      const double r_sq = sum_d / D0;
+      if (theta > 0.0) {
+        mode = sqrt(r_sq) > theta ? kModeBF16x3 : kModeBF16;
+      } else {
+        // cheapest product whose contribution, kept for every later block,
+        // holds the bound within the budget
+        const double lim = kErrBudget * eps / kErrLambda;
+        mode = p.native_mode;
+        for (int cand : {kModeBF16, kModeBF16x3}) {
+          if (err_var + err_var_future(cand, b, r_sq) <= lim * lim) {
+            mode = cand;
+            break;
+          }
+        }
+      }
       if (mode == kModeBF16x3) st.blocks_split++;
+      if (mode == p.native_mode) st.blocks_native++;
     }
     int nchunk = 1;
     if (b > kDeflateMaxB) {
@@ -451,6 +533,12 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     k_last = kS;
     sum_last = sum_d;
     kS += bp;
+    {
+      // a second deflation launch rounds the accumulator once more per row
+      const double v =
+          err_var_increment(mode, bp + 32 * (nchunk - 1), sum_d / D0, h->sum_d / D0);
+      if (v > 0.0) err_var += v;
+    }
     sum_d = h->sum_d;
   }
   // Rank trimming: with Q' orthogonal to the earlier basis, the error of the
@@ -460,7 +548,7 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
   // use the residual buffer (no longer needed), the column norms C.  Not in
   // the BF16 form: its tracked residual carries the BF16 rounding, and the
   // whole last block keeps the slack that covers it.
-  if (o.trim && !o.fixed_rank && !p.bf16 && kS - k_last > 1 && !(sum_d > tau * D0)) {
+  if (o.trim && !o.fixed_rank && !p.bf16 && kS - k_last > 1 && met(sum_d)) {
     const int nc = (int)(kS - k_last);
     const int G = col_sumsq_groups(m);
     const size_t rsz = (size_t)p.mr * p.ldr * (p.r_f64 ? sizeof(double) : sizeof(float));
@@ -473,7 +561,7 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     double e = sum_last;
     for (int j = 0; j < nc; ++j) {
       e -= colsq[j];
-      if (e <= tau * D0) {
+      if (met(e)) {
         if (j + 1 < nc) {
           kS = k_last + j + 1;
           sum_d = e;
@@ -484,6 +572,7 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
   }
   *k_host = kS;
   st.resid_tracked = sqrt(fmax(sum_d, 0.0) / D0);
+  st.err_bound = err_bound();
   if (W && kS > 0) {
     prof.begin(4);
     RBRP_HIP(launch_interp(w.L, p.r_f64, p.ldl, m, kS, S, W, ldw, refine, w.interp, s));

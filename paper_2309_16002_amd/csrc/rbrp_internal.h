@@ -21,6 +21,8 @@ constexpr int kScanTile = 2048;   // rows per tile of the fixed-point CDF
 constexpr int kMaxB = 256;        // largest block size
 constexpr int kDeflateMaxB = 128; // largest b' of one deflation launch
 constexpr int kRejectionFactor = 32;
+constexpr int kMaxScanTiles = 4096;  // tiles of the integer CDF (k_sample.hip)
+constexpr int64_t kMaxRows = (int64_t)kMaxScanTiles * kScanTile;
 
 __host__ __device__ inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 __host__ __device__ inline int64_t ceil_div(int64_t x, int64_t a) { return (x + a - 1) / a; }

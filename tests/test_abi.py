@@ -186,3 +186,19 @@ def test_tau_b_above_one_is_rejected_by_workspace_size(L):
     assert L.rbrp_workspace_size(0, 100, 20, 8, ctypes.byref(o)) == 0
     o = B.make_options(tau_b=0.0)
     assert L.rbrp_workspace_size(0, 100, 20, 8, ctypes.byref(o)) > 0
+
+
+def test_rows_beyond_the_sampler_limit_are_rejected_before_device_work(L):
+    # the integer CDF has at most 4096 tiles of 2048 rows
+    limit = 4096 * 2048
+    assert rb.workspace_size(limit, 8, 8, "f32") > 0
+    assert rb.workspace_size(limit + 1, 8, 8, "f32") == 0
+    st, k = _call_id(L, m=limit + 1, n=8, ldx=8)
+    assert st == B.RBRP_E_UNSUPPORTED and k == -7
+
+
+def test_stats_layout():
+    # blocks, blocks_split, resid_tracked, err_bound, norm_x_fro, five phase
+    # times, deflate_flops, deflate_launches, blocks_native, bprime[256]
+    assert ctypes.sizeof(B.rbrp_stats) == 8 + 8 * 9 + 8 + 4 * 256
+    assert B.rbrp_stats.err_bound.offset == 16

@@ -1,0 +1,140 @@
+"""The running bound on the deflation rounding (rbrp_err_bound_increment, the
+precision controller's arithmetic) against a CPU emulation of the deflation
+products.
+
+The emulation replays Algorithm 2's deflation R <- R - (R Q') Q'^T block by
+block on the same orthonormal blocks Q' the FP64 oracle selected, with the
+operands rounded as the GPU kernels round them (FP32; BF16 split into hi + lo
+with three products; one BF16 product) and FP32 accumulation (NumPy's float32
+matrix products).  For every block t it checks, in FP64:
+
+* the part of R_tracked - X (I - Q Q^T) outside span(Q) -- the only part
+  that can lower the tracked norm below the optimal error on S -- is within
+  the bound E_t = 3 sqrt(sum of the library's increments);
+* the optimal error ||X (I - Q Q^T)||_F / ||X||_F is at most the tracked
+  residual plus E_t, which is what the stopping rule rho + E_t <= eps uses;
+* the bound stays within a modest factor of the error it covers.
+
+Runs on the CPU only: the library's host function is called through ctypes.
+"""
+
+import numpy as np
+import pytest
+
+import paper_2309_16002_amd as rb
+from oracle import rbrp as oracle_rbrp
+from workloads import svd_matrix, power_spectrum, adversarial_gmm
+
+
+def _bf16(x):
+    """Round float32 values to BF16 (round to nearest, ties to even), kept in
+    float32 storage."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    b = x.view(np.uint32).astype(np.uint64)
+    b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+    return b.astype(np.uint32).view(np.float32)
+
+
+def _split(x):
+    hi = _bf16(x)
+    lo = _bf16(x - hi)
+    return hi, lo
+
+
+def _deflate(R, Qn, mode):
+    """One emulated deflation step of the FP32 residual R by the FP64 block Qn
+    (n x b'), products with FP32 accumulation."""
+    Qf = Qn.astype(np.float32)
+    if mode == "f32":
+        P = R @ Qf
+        return (R - P @ Qf.T).astype(np.float32)
+    if mode == "bf16":
+        Rb, Qb = _bf16(R), _bf16(Qf)
+        P = Rb @ Qb
+        return (R - _bf16(P) @ Qb.T).astype(np.float32)
+    assert mode == "bf16x3"
+    Rh, Rl = _split(R)
+    Qh, Ql = _split(Qf)
+    P = Rh @ Qh + Rh @ Ql + Rl @ Qh
+    Ph, Pl = _split(P)
+    return (R - (Ph @ Qh.T + Ph @ Ql.T + Pl @ Qh.T)).astype(np.float32)
+
+
+def _emulate(X32, eps, b, seed, modes):
+    X = X32.astype(np.float64)
+    ref = oracle_rbrp(X, eps, b, seed)
+    D0 = float(np.sum(X * X))
+    R = X32.copy()
+    r2_prev = 1.0
+    var = 0.0
+    out = []
+    k = 0
+    for t, (_, bp) in enumerate(ref.blocks):
+        mode = modes(t, r2_prev)
+        Qn = ref.Qt[k:k + bp].T
+        k += bp
+        R = _deflate(R, Qn, mode)
+        R64 = R.astype(np.float64)
+        r2 = float(np.sum(R64 * R64)) / D0
+        v = rb.err_bound_increment(mode, bp, r2_prev, r2)
+        assert v >= 0.0
+        var += v
+        E = 3.0 * np.sqrt(var)
+        Qk = ref.Qt[:k].T
+        Rtrue = X - (X @ Qk) @ Qk.T
+        Dlt = R64 - Rtrue
+        Dperp = Dlt - (Dlt @ Qk) @ Qk.T
+        nx = np.sqrt(D0)
+        out.append(dict(t=t + 1, mode=mode, E=E, perp=np.linalg.norm(Dperp) / nx,
+                        par=np.linalg.norm(Dlt - Dperp) / nx, rho=np.sqrt(r2),
+                        rho_true=np.linalg.norm(Rtrue) / nx))
+        r2_prev = r2
+    return out
+
+
+def _check(rows):
+    for r in rows:
+        print(f"  block {r['t']:2d} {r['mode']:6s} rho={r['rho']:.3e} true={r['rho_true']:.3e} "
+              f"perp={r['perp']:.2e} par={r['par']:.2e} E={r['E']:.2e}")
+        assert r["perp"] <= r["E"]
+        assert r["rho_true"] <= r["rho"] + r["E"]
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+@pytest.mark.parametrize("mode", ["f32", "bf16x3", "bf16"])
+def test_bound_covers_emulated_rounding_power_spectrum(mode, seed):
+    X = svd_matrix(2500, 256, power_spectrum(256, 1.5), seed=200 + seed).astype(np.float32)
+    rows = _emulate(X, 1e-4, 32, seed, lambda t, r2: mode)
+    _check(rows)
+    # the bound is not vacuous: within a modest factor of the largest error
+    # it covers (the model uses the worst-case variance u^2 / 3 and three
+    # standard deviations)
+    assert rows[-1]["E"] <= 30.0 * max(r["perp"] for r in rows)
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_bound_covers_controller_sequence_gmm(seed):
+    # split products while the residual is large, one product below 25 eps
+    eps = 1e-3
+    X = adversarial_gmm(4000, 300, sub_dim=80, n_comp=20, seed=seed)
+    rows = _emulate(X, eps, 32, seed,
+                    lambda t, r2: "bf16x3" if np.sqrt(r2) > 25 * eps else "bf16")
+    assert {r["mode"] for r in rows} == {"bf16x3", "bf16"}
+    _check(rows)
+
+
+def test_increment_formula_properties():
+    # cheaper products carry larger increments; no increment without work
+    args = (64, 0.25, 0.09)
+    v = [rb.err_bound_increment(m, *args) for m in ("f64", "f32", "bf16x3", "bf16")]
+    assert 0.0 < v[0] < v[1] < v[2] < v[3]
+    assert rb.err_bound_increment("bf16", 0, 0.0, 0.0) == 0.0
+    # the term in the removed energy p^2 = r_prev^2 - r_new^2 dominates BF16
+    u = 2.0 ** -8
+    p2 = args[1] - args[2]
+    assert v[3] == pytest.approx(u * u / 3 * p2, rel=0.05)
+    # a block cannot remove negative energy
+    assert rb.err_bound_increment("bf16", 64, 0.1, 0.2) < rb.err_bound_increment(
+        "bf16", 64, 0.2, 0.1)
+    assert rb.err_bound_increment(9, 64, 0.1, 0.05) < 0.0
+    assert rb.err_bound_increment("f32", -1, 0.1, 0.05) < 0.0
