@@ -96,6 +96,19 @@ typedef struct {
                           BF16 rounding, which the whole last block's slack
                           covers).  0: keep every selected row (the paper's
                           rule)                                              */
+  const double* replay_d; /* test hook (device, FP64 [replay_blocks x m], row
+                          t-1 = the squared residual row norms that block t
+                          samples from), used when replay_blocks > 0: block t
+                          draws from row t-1 instead of the tracked norms (the
+                          weights, the Philox stream and the exclusion of rows
+                          already in S are unchanged), and the loop runs
+                          exactly replay_blocks blocks (fewer only if k_max is
+                          reached or a block lies in span(Q)) instead of
+                          applying the stopping rule.  Fed the norms another
+                          implementation drew from, the skeletons of every
+                          block can be compared with its, whatever the
+                          deflation's precision.  NULL / 0: off           */
+  int32_t replay_blocks;
 } rbrp_options;
 
 /* Per-call statistics (optional, host memory). */

@@ -1,31 +1,25 @@
-"""Algorithm 2 -- robust blockwise random pivoting (RBRP) -- in plain FP64.
-Test infrastructure only.
+"""Robust blockwise random pivoting (RBRP, Algorithm 2 of section 4) in plain
+FP64.  Test infrastructure only.
 
-The loop follows Algorithm 2 step by step, in the paper's order and notation
-(the paper's n x d matrix is m x n here):
+What is computed (the paper's n x d data matrix is m x n here): an ordered
+set S of skeleton rows of X, grown one block at a time.  A block draws b rows
+from the squared-norm distribution of the current residual X (I - Q Q^T)
+(section 2.2's distribution, applied to the residual), removes from them the
+part the current orthonormal basis Q already spans, and keeps the b' of them
+that a column-pivoted QR ranks first, cut where the rest carries less than
+tau_b of the block's projected mass (the robust truncation of Remark 4.2).
+The kept rows join S, their orthonormal directions Q' join Q, and X Q' (zero
+on the rows of earlier skeletons) joins the factor L from which Algorithm 3
+forms W.  The loop ends once the residual's squared Frobenius norm is at
+most eps^2 ||X||_F^2, or at k_max rows.
 
-  d^(0)_i = ||x_i||^2                                      (initial norms)
-  while ||d||_1 > tau ||d^(0)||_1  (and |S| < k_max):       (stopping rule)
-      t <- t + 1;  b_t <- min(b, k_max - |S|)
-      S_t <- b_t rows drawn from d / ||d||_1 without replacement
-      V   <- X(S_t,:)^T - Q (Q^T X(S_t,:)^T)                (projection)
-      Q_V, R_V, pi_V <- column-pivoted QR of V                (local CPQR)
-      b'  <- max{i : ||R_V(i:b,i:b)||_F^2 >= tau_b ||R_V||_F^2}
-      S'_t <- S_t(pi_V(1:b')),  Q' <- Q_V(:, 1:b')
-      Q   <- [Q, Q']
-      L-hat(pi_a,:) <- X(pi_a,:) Q'  (zero on rows already in S)
-      S   <- S u S'_t;  L <- [L, L-hat]
-      d_i <- 0 for i in S;  d_i <- d_i - ||L-hat(i,:)||^2 otherwise
+The residual row norms d are kept in one of two ways, which give the same
+skeletons in exact arithmetic (Q' is orthogonal to Q, so R Q' = X Q'):
 
-Two forms of the update are provided:
-
-* form "A" is the paper-literal one above: L-hat from the original X and the
-  squared norms downdated (the timed CPU baseline);
-* form "B" keeps the residual R = X (I - Q Q^T) explicitly: P = R Q',
-  R <- R - P Q'^T, L-hat = P with rows already in S zeroed, d_i = ||R_i||^2.
-  Since Q' is orthogonal to the previous Q, X Q' = R Q' and
-  ||R_i - P_i Q'^T||^2 = d_i - ||P_i||^2 in exact arithmetic, so both forms
-  select the same skeletons; form B is the one the GPU library implements.
+* form "A" downdates d by the squared rows of X Q', as the paper describes
+  (the timed CPU baseline);
+* form "B" stores the residual R = X (I - Q Q^T) and recomputes its row norms
+  after each block; this is the form the GPU library implements.
 
 Readings (where the paper is silent or ambiguous)
 -------------------------------------------------
@@ -72,8 +66,11 @@ class RBRPResult:
 
 
 def rbrp(X, eps, b, seed, tau_b=None, k_max=None, form="B", greedy=False,
-         fixed_rank=False, ident=0):
-    """Run Algorithm 2 on X (m x n, FP64).  Returns an RBRPResult."""
+         fixed_rank=False, ident=0, trace=None):
+    """Run Algorithm 2 on X (m x n, FP64).  Returns an RBRPResult.
+
+    ``trace``: a list to which a copy of the residual norms each block
+    samples from is appended (no effect on the result)."""
     X = np.asarray(X, dtype=np.float64)
     m, n = X.shape
     if tau_b is None:
@@ -96,6 +93,8 @@ def rbrp(X, eps, b, seed, tau_b=None, k_max=None, form="B", greedy=False,
     while len(S) < k_max and (fixed_rank or d.sum() > tau * D0):
         t += 1
         b_t = min(b, k_max - len(S))
+        if trace is not None:
+            trace.append(d.copy())
         if greedy:
             S_t = top_b(d, in_S, b_t)
         else:

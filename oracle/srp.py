@@ -1,22 +1,24 @@
-"""Algorithm 1 -- sequential random pivoting (SRP) -- in plain FP64.
+"""Sequential random pivoting (SRP, Algorithm 1 of section 3) in plain FP64.
 Test infrastructure only.
+
+What is computed (the paper's n x d data matrix is m x n here): skeleton rows
+chosen one at a time, each drawn from the squared-norm distribution of the
+current residual X (I - Q Q^T).  The drawn row's residual direction q (the
+row minus its projection on span(Q), normalised) joins the orthonormal basis;
+the factor L gains the column X q, zero on the rows of earlier skeletons; and
+every residual squared row norm drops by the square of that row's entry of
+X q (Pythagoras over the orthonormal basis).  The loop ends once the
+residual's squared Frobenius norm is at most eps^2 ||X||_F^2.
 
 Used as an independent special case of Algorithm 2: with b = 1 the robust
 filter keeps the single sampled row (tau_b = 1/1 and tail_1 >= tail_1), so
 RBRP with b = 1 and SRP select the same skeletons from the same random stream.
 
-Per step (Alg. 1), with the paper's n x d matrix written m x n here:
-  s_t ~ d / ||d||_1
-  v   <- x_{s_t} - Q (Q^T x_{s_t});  Q <- [Q, v / ||v||]
-  a   <- X(pi_a,:) v  on the active rows (zero on earlier skeletons)
-  L   <- [L, a / sqrt(a(s_t))]
-  d_i <- 0 for i in S,  d_i <- d_i - a_i^2 / a(s_t) otherwise
-
-Reading: the loop condition printed in Alg. 1 compares with "<"; it is read
-as ">" as in Algorithm 2 (continue while the residual is above tolerance).
-The single draw per step uses the same fixed-point draw as the block sampler
-with b = 1 (its first candidate), and v is projected twice as in the block
-form.
+Readings: the loop condition printed in Algorithm 1 compares with "<"; it is
+read as ">" as in Algorithm 2 (continue while the residual is above the
+tolerance).  The single draw per step uses the same fixed-point draw as the
+block sampler with b = 1 (its first candidate), and the direction is
+projected twice as in the block form.
 """
 
 import numpy as np
@@ -34,8 +36,8 @@ def srp(X, eps, seed, k_max=None, ident=0):
     D0 = float(d.sum())
     S = []
     in_S = np.zeros(m, dtype=bool)
-    Qcols = []
-    Lcols = []
+    basis = []            # orthonormal residual directions, one per skeleton
+    columns = []          # the columns of L
     t = 0
     while D0 > 0 and d.sum() > tau * D0 and len(S) < k_max:
         t += 1
@@ -43,22 +45,23 @@ def srp(X, eps, seed, k_max=None, ident=0):
         if not drawn:
             break
         s = drawn[0]
-        v = X[s, :].copy()
+        # the drawn row's residual direction: project out span(Q) twice
+        r = X[s, :].copy()
         for _ in range(2):
-            for q in Qcols:
-                v -= q * (q @ v)
-        nv = np.linalg.norm(v)
-        if nv == 0.0:
+            for q in basis:
+                r -= q * (q @ r)
+        nr = np.linalg.norm(r)
+        if nr == 0.0:
             break
-        a = X @ v                      # unnormalised v, as in Alg. 1
-        a[in_S] = 0.0
+        q = r / nr
+        col = X @ q                    # = residual @ q, since q is orthogonal to span(Q)
+        col[in_S] = 0.0
         S.append(s)
         in_S[s] = True
-        a_s = a[s]                     # equals ||v||^2 = d(s) in exact arithmetic
-        Lcols.append(a / np.sqrt(a_s))
-        d = d - a * a / a_s
+        columns.append(col)
+        d = d - col * col
         d[in_S] = 0.0
         d = np.maximum(d, 0.0)
-        Qcols.append(v / nv)
-    L = np.column_stack(Lcols) if Lcols else np.zeros((m, 0))
+        basis.append(q)
+    L = np.column_stack(columns) if columns else np.zeros((m, 0))
     return S, L, d, D0

@@ -36,6 +36,8 @@ class rbrp_options(ctypes.Structure):
         ("theta", ctypes.c_double),
         ("profile", ctypes.c_int32),
         ("trim", ctypes.c_int32),
+        ("replay_d", ctypes.c_void_p),
+        ("replay_blocks", ctypes.c_int32),
     ]
 
 
@@ -182,7 +184,7 @@ def _check_matrix(X):
 
 
 def make_options(k_max=0, tau_b=None, fixed_rank=False, greedy=False, precision="native",
-                 theta=0.0, w_refine=-1, profile=False, trim=False):
+                 theta=0.0, w_refine=-1, profile=False, trim=False, replay_d=None):
     o = rbrp_options()
     lib().rbrp_default_options(ctypes.byref(o))
     o.tau_b = -1.0 if tau_b is None else float(tau_b)
@@ -194,6 +196,14 @@ def make_options(k_max=0, tau_b=None, fixed_rank=False, greedy=False, precision=
     o.w_refine = int(w_refine)
     o.profile = 2 if profile == "deflate" else int(bool(profile))
     o.trim = int(bool(trim))
+    if replay_d is not None:
+        # test hook: [blocks, m] FP64 device tensor of the norms each block
+        # samples from (the caller keeps it alive for the call)
+        if replay_d.dtype != _torch().float64 or not replay_d.is_cuda or replay_d.dim() != 2 \
+                or not replay_d.is_contiguous():
+            raise ValueError("replay_d must be a contiguous [blocks, m] float64 GPU tensor")
+        o.replay_d = replay_d.data_ptr()
+        o.replay_blocks = int(replay_d.shape[0])
     return o
 
 

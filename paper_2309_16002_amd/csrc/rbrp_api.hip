@@ -331,6 +331,7 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
   if (ldx < n) return RBRP_E_INVALID;
   if (!o.fixed_rank && !(eps > 0.0 && eps < 1.0)) return RBRP_E_INVALID;
   if (W && ldw < p.k_max) return RBRP_E_INVALID;
+  if (o.replay_blocks < 0 || (o.replay_blocks > 0 && !o.replay_d)) return RBRP_E_INVALID;
   if (p.bf16 && dtype != RBRP_F32) return RBRP_E_UNSUPPORTED;
   const int mode_hi = p.bf16 ? kModeBF16x3 : p.native_mode;
   const int mode_lo = p.bf16 ? kModeBF16 : p.native_mode;
@@ -391,13 +392,17 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     return e > 0.0 && sd <= e * e * D0;
   };
   const int def_rows = deflate_rows_per_wg(mode_hi, ldr);
+  // test hook: block tt draws from the supplied norms and the loop runs
+  // exactly replay_blocks blocks
+  const bool replay = o.replay_blocks > 0;
   auto select_block = [&](int32_t tt, int32_t bsz) -> hipError_t {
     prof.begin(1);
     hipError_t e;
+    const double* dsrc = replay ? o.replay_d + (int64_t)(tt - 1) * m : w.d;
     if (o.greedy) {
-      e = launch_topb(w.d, w.sel_block, m, bsz, w.idx, w.sc, w.cdf, p.m, s);
+      e = launch_topb(dsrc, w.sel_block, m, bsz, w.idx, w.sc, w.cdf, p.m, s);
     } else {
-      e = launch_weights_scan(w.d, w.sel_block, nullptr, m, w.sc, w.cdf, w.tile_sum,
+      e = launch_weights_scan(dsrc, w.sel_block, nullptr, m, w.sc, w.cdf, w.tile_sum,
                               w.tile_pos, s);
       if (e == hipSuccess)
         e = launch_sample(w.cdf, w.tile_sum, w.tile_pos, m, bsz, seed, (uint64_t)tt, 0, w.idx,
@@ -413,10 +418,14 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
   double sum_last = sum_d;   // tracked squared residual before that block
   while (true) {
     if (kS >= k_max) {
-      if (!o.fixed_rank && !met(sum_d)) final_status = RBRP_E_CAPACITY;
+      if (!o.fixed_rank && !replay && !met(sum_d)) final_status = RBRP_E_CAPACITY;
       break;
     }
-    if (!o.fixed_rank && met(sum_d)) break;
+    if (replay) {
+      if (t >= o.replay_blocks) break;
+    } else if (!o.fixed_rank && met(sum_d)) {
+      break;
+    }
     ++t;
     const int32_t bt = (int32_t)((int64_t)b < k_max - kS ? b : k_max - kS);
     // sampling (or greedy top-b) and V^T, the sampled rows of X in FP64 --
@@ -519,7 +528,7 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     // work is simply not used.
     RBRP_HIP(hipMemcpyAsync(h, w.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
     RBRP_HIP(hipEventRecord(ev_scalars, s));
-    if (k_max - kS - bt >= b) {
+    if (k_max - kS - bt >= b && (!replay || t < o.replay_blocks)) {
       RBRP_HIP(select_block(t + 1, b));
       preselected = true;
     }
@@ -548,7 +557,7 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
   // use the residual buffer (no longer needed), the column norms C.  Not in
   // the BF16 form: its tracked residual carries the BF16 rounding, and the
   // whole last block keeps the slack that covers it.
-  if (o.trim && !o.fixed_rank && !p.bf16 && kS - k_last > 1 && met(sum_d)) {
+  if (o.trim && !o.fixed_rank && !replay && !p.bf16 && kS - k_last > 1 && met(sum_d)) {
     const int nc = (int)(kS - k_last);
     const int G = col_sumsq_groups(m);
     const size_t rsz = (size_t)p.mr * p.ldr * (p.r_f64 ? sizeof(double) : sizeof(float));

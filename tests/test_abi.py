@@ -178,7 +178,26 @@ def test_default_options_and_binding_mapping(L):
     assert B.make_options().tau_b < 0
     assert B.make_options(tau_b=0.0).tau_b == 0.0
     assert B.make_options(trim=True).trim == 1
-    assert ctypes.sizeof(B.rbrp_options) == 48
+    # the binding's struct has the C struct's size: rbrp_default_options
+    # clears sizeof(rbrp_options) bytes of a buffer filled with 0xAB
+    buf = (ctypes.c_uint8 * 256)(*([0xAB] * 256))
+    L.rbrp_default_options(ctypes.cast(buf, ctypes.POINTER(B.rbrp_options)))
+    c_size = max(i for i in range(256) if buf[i] != 0xAB) + 1
+    assert c_size == ctypes.sizeof(B.rbrp_options) == 64
+    assert B.rbrp_options.replay_d.offset == 48 and B.rbrp_options.replay_blocks.offset == 56
+
+
+def test_replay_hook_validation(L):
+    """replay_blocks > 0 needs the norms' pointer; a negative count is invalid
+    (both rejected before any device work, k untouched)."""
+    o = B.make_options()
+    o.replay_blocks = 3
+    st, k = _call_id(L, opt=o)
+    assert st == B.RBRP_E_INVALID and k == -7
+    o.replay_blocks = -1
+    o.replay_d = 1
+    st, k = _call_id(L, opt=o)
+    assert st == B.RBRP_E_INVALID and k == -7
 
 
 def test_tau_b_above_one_is_rejected_by_workspace_size(L):
