@@ -20,9 +20,10 @@
  * - Arguments are validated before any device work is issued.  On
  *   RBRP_E_INVALID / RBRP_E_WORKSPACE nothing is written anywhere.
  * - No entry point allocates device memory: every scratch buffer lives in the
- *   caller-provided workspace (size from rbrp_workspace_size).  The library
- *   holds one small pinned host buffer per process for the per-block stop
- *   test.
+ *   caller-provided workspace (size from rbrp_workspace_size), except for
+ *   rbrp_id_batched_noalloc, whose scratch is a static 256 MiB device array
+ *   of the library.  The library holds one small pinned host buffer per
+ *   process for the per-block stop test.
  * - Calls that share a workspace must not overlap; distinct workspaces on
  *   distinct streams are independent.
  */
@@ -318,6 +319,31 @@ rbrp_status rbrp_id_batched(const rbrp_batch_desc* descs, const int32_t* order,
                             const rbrp_batch_shape* shape, int32_t* k_out,
                             int32_t* status_out, double* resid_out,
                             void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * rbrp_id_batched without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The per-workgroup scratch comes from a
+ * static device array of 256 MiB inside the library (one per GPU, held until
+ * the process ends; its address is looked up on the first call on each
+ * device).  Same arguments, kernels and results as rbrp_id_batched.  The
+ * persistent grid is shape->num_wg workgroups (0 -> 512) or as many as the
+ * array holds, whichever is fewer; the queue hands out the IDs, so the
+ * count changes no result.  A shape whose single workgroup needs more than
+ * the array -> RBRP_E_WORKSPACE (validated before any device work).
+ * ``stream`` must belong to the current device (else RBRP_E_INVALID).
+ * Allocates nothing: no hipMalloc, hipFree, memset or allocating library
+ * call.  Every call on one GPU shares that GPU's array and leaves its
+ * contents behind: calls that overlap on one GPU (concurrent streams or
+ * threads) race and must be serialised by the caller.
+ */
+rbrp_status rbrp_id_batched_noalloc(const rbrp_batch_desc* descs,
+                                    const int32_t* order, int32_t count,
+                                    rbrp_dtype dtype, double eps, uint64_t seed,
+                                    const rbrp_options* opt,
+                                    const rbrp_batch_shape* shape,
+                                    int32_t* k_out, int32_t* status_out,
+                                    double* resid_out, void* stream);
 
 /*
  * Autotuner of the batched form.  descs_host [count] is the host copy of the

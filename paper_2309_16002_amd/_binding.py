@@ -119,6 +119,9 @@ SIGNATURES = {
     "rbrp_id_batched": (_c.c_int, [_vp, _vp, _i32, _c.c_int, _dbl, _u64,
                                    _c.POINTER(rbrp_options), _c.POINTER(rbrp_batch_shape),
                                    _vp, _vp, _vp, _vp, _sz, _vp]),
+    "rbrp_id_batched_noalloc": (_c.c_int, [_vp, _vp, _i32, _c.c_int, _dbl, _u64,
+                                           _c.POINTER(rbrp_options),
+                                           _c.POINTER(rbrp_batch_shape), _vp, _vp, _vp, _vp]),
     "rbrp_batch_autotune": (_c.c_int, [_c.POINTER(rbrp_batch_desc), _vp, _i32, _c.c_int,
                                        _dbl, _u64, _c.POINTER(rbrp_options),
                                        _c.POINTER(rbrp_batch_shape), _vp, _vp, _vp, _vp,
@@ -442,6 +445,21 @@ def rbrp_id_batched(plan, eps, seed=0, stream=None, **opts):
                                    _ptr(plan.workspace), plan.workspace.numel(), st)
     if status != RBRP_OK:
         raise RBRPError(status, "rbrp_id_batched")
+    return plan
+
+
+def rbrp_id_batched_noalloc(plan, eps, seed=0, stream=None, **opts):
+    """Launch all IDs of ``plan`` on the library's static scratch array instead
+    of ``plan.workspace`` (no synchronisation, no allocation; outputs in the
+    plan).  Calls that overlap on one GPU race on that array."""
+    o = make_options(**opts)
+    st = stream if stream is not None else _stream_ptr(plan.device)
+    status = lib().rbrp_id_batched_noalloc(_ptr(plan.descs), _ptr(plan.order), plan.count,
+                                           plan.dtype, float(eps), int(seed), ctypes.byref(o),
+                                           ctypes.byref(plan.shape), _ptr(plan.k_out),
+                                           _ptr(plan.status_out), _ptr(plan.resid_out), st)
+    if status != RBRP_OK:
+        raise RBRPError(status, "rbrp_id_batched_noalloc")
     return plan
 
 

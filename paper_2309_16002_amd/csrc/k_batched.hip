@@ -714,6 +714,14 @@ size_t batch_workspace_size(rbrp_dtype dt, const rbrp_batch_shape* sh) {
   return 256 + 256 + (size_t)nwg * g.slice;
 }
 
+int32_t batch_default_wg() { return default_num_wg(); }
+
+int64_t batch_max_wg(rbrp_dtype dt, const rbrp_batch_shape* sh, size_t bytes) {
+  const BatchGeom g = batch_geom(dt, *sh);
+  if (g.slice <= 0 || bytes < 512 + (size_t)g.slice) return 0;
+  return (int64_t)((bytes - 512) / (size_t)g.slice);
+}
+
 bool batch_shape_ok(const rbrp_batch_shape* sh) {
   return sh && sh->m_max >= 1 && sh->m_max <= (int64_t)kBatchMaxTiles * kScanTile &&
          sh->n_max >= 1 && sh->n_max <= kBatchMaxN && sh->b_max >= 1 &&

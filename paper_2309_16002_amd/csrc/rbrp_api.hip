@@ -4,6 +4,7 @@
 #include "rbrp_internal.h"
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include <math.h>
@@ -760,6 +761,79 @@ rbrp_status rbrp_id_batched(const rbrp_batch_desc* descs, const int32_t* order,
   if (count == 0) return RBRP_OK;
   RBRP_HIP(rbrp::launch_batched(descs, order, count, dtype, eps, seed, o, *shape, k_out,
                                 status_out, resid_out, workspace, (hipStream_t)stream));
+  return RBRP_OK;
+}
+
+// ---- batched form on a static scratch array (no allocation) ----
+//
+// The array lives in the library's code object: each GPU that loads the
+// library holds one copy until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it only names the symbol); the device
+// address comes from hipGetSymbolAddress, once per device, with that device
+// current, and is cached here.
+constexpr size_t kNoAllocScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kScratchMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kScratchMaxDevices];
+
+// Device address of ``scratch`` on the current device (looked up on the
+// first call on that device).
+rbrp_status scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return RBRP_E_HIP;
+  if (dev < 0 || dev >= kScratchMaxDevices) return RBRP_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      if (getenv("RBRP_LOG"))
+        fprintf(stderr, "rbrp: hipGetSymbolAddress(scratch) failed on device %d: %s\n", dev,
+                hipGetErrorString(e));
+      return RBRP_E_HIP;
+    }
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return RBRP_OK;
+}
+}  // namespace
+
+rbrp_status rbrp_id_batched_noalloc(const rbrp_batch_desc* descs, const int32_t* order,
+                                    int32_t count, rbrp_dtype dtype, double eps,
+                                    uint64_t seed, const rbrp_options* opt,
+                                    const rbrp_batch_shape* shape, int32_t* k_out,
+                                    int32_t* status_out, double* resid_out, void* stream) {
+  if (dtype != RBRP_F32 && dtype != RBRP_F64) return RBRP_E_INVALID;
+  if (!rbrp::batch_shape_ok(shape)) return RBRP_E_INVALID;
+  // as many persistent workgroups as the array holds, up to the requested
+  // count (the queue hands out the IDs, so the count changes no result); a
+  // shape whose single workgroup needs more than the array is rejected
+  rbrp_batch_shape sh = *shape;
+  const int64_t fit = rbrp::batch_max_wg(dtype, &sh, kNoAllocScratchBytes);
+  if (fit < 1) return RBRP_E_WORKSPACE;
+  const int64_t want = sh.num_wg > 0 ? sh.num_wg : rbrp::batch_default_wg();
+  sh.num_wg = (int32_t)(want < fit ? want : fit);
+  if (stream) {
+    int cur = -1, sdev = -1;
+    if (hipGetDevice(&cur) != hipSuccess ||
+        hipStreamGetDevice((hipStream_t)stream, &sdev) != hipSuccess)
+      return RBRP_E_HIP;
+    if (cur != sdev) return RBRP_E_INVALID;   // the array of the current device only
+  }
+  void* ws = nullptr;
+  rbrp_status v = scratch_address(&ws);
+  if (v != RBRP_OK) return v;
+  rbrp_options o;
+  v = batch_check(count, dtype, eps, opt, &sh, descs, k_out, status_out, ws,
+                  kNoAllocScratchBytes, &o);
+  if (v != RBRP_OK) return v;
+  if (count == 0) return RBRP_OK;
+  RBRP_HIP(rbrp::launch_batched(descs, order, count, dtype, eps, seed, o, sh, k_out,
+                                status_out, resid_out, ws, (hipStream_t)stream));
   return RBRP_OK;
 }
 

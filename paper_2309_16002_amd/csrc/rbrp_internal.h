@@ -233,6 +233,11 @@ enum DeflateMode { kModeF64 = 0, kModeF32 = 1, kModeBF16x3 = 2, kModeBF16 = 3 };
 // ---- batched form (k_batched.hip) ----
 bool batch_shape_ok(const rbrp_batch_shape* sh);
 size_t batch_workspace_size(rbrp_dtype dt, const rbrp_batch_shape* sh);
+// persistent workgroups when the shape gives num_wg = 0
+int32_t batch_default_wg();
+// largest number of persistent workgroups whose workspace fits in ``bytes``
+// (0 if not even one)
+int64_t batch_max_wg(rbrp_dtype dt, const rbrp_batch_shape* sh, size_t bytes);
 size_t batch_lds_needed(rbrp_dtype dt, const rbrp_batch_shape* sh);
 hipError_t launch_batched(const rbrp_batch_desc* descs, const int32_t* order, int32_t count,
                           rbrp_dtype dt, double eps, uint64_t seed, const rbrp_options& o,
