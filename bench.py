@@ -334,12 +334,15 @@ def main():
                   for key in ("ms_init", "ms_select", "ms_filter", "ms_deflate", "ms_interp")}
         return results, total, err, phases
 
-    def deflation_roofline(results, dtype, s_r):
+    def deflation_roofline(results, dtype):
+        """Algorithmic flops and bytes of the deflation launches (the library
+        counts them: 4 m n b' flops per block; the residual read and written
+        in its storage type, d, and the new columns of L) over their HIP-event
+        durations."""
         flops = sum(r.profile["deflate_flops"] for r in results)
         ms_def = sum(r.profile["ms_deflate"] for r in results)
         launches = sum(r.profile["deflate_launches"] for r in results)
-        sum_bp = flops / (4.0 * m * n)
-        nbytes = launches * (2.0 * m * n * s_r + 8.0 * m) + m * s_r * sum_bp
+        nbytes = sum(r.profile["deflate_bytes"] for r in results)
         sec = ms_def * 1e-3
         gbs = nbytes / sec / 1e9 if sec > 0 else 0.0
         tfl = flops / sec / 1e12 if sec > 0 else 0.0
@@ -371,8 +374,7 @@ def main():
     ms_per_step = 1e3 * total / args.steps
     value = m * args.steps / total
     dtype = cfg["dtype"]
-    s_r = 8 if dtype == "f64" else 4
-    roofline = deflation_roofline(results, dtype, s_r)
+    roofline = deflation_roofline(results, dtype)
     roofline["traffic"] = _traffic(args.workload)
     roofline["kernel"] = "k_deflate (P = R Q', R -= P Q'^T, row norms)"
     ks = [r.k for r in results]
@@ -399,7 +401,7 @@ def main():
     if dtype == "f32" and not args.no_bf16:
         res16, tot16, err16, phases16 = run_form("bf16", args.steps, 1)
         v16 = m * args.steps / tot16
-        rf16 = deflation_roofline(res16, "bf16", 4)
+        rf16 = deflation_roofline(res16, "bf16")
         line["bf16_form"] = {
             "value": v16, "unit": "rows/s", "ms_per_step": 1e3 * tot16 / args.steps,
             "speedup_vs_fp32_plain": v16 / value,
@@ -411,8 +413,11 @@ def main():
             "blocks_median": statistics.median(r.blocks for r in res16),
             "blocks_split_median": statistics.median(r.blocks_split for r in res16),
             "blocks_fp32_median": statistics.median(r.blocks_native for r in res16),
-            "controller": "per block the cheapest of BF16, split BF16 and FP32 products "
-                          "that keeps the rounding bound within eps/4",
+            "blocks_bf16_stored_median": statistics.median(r.blocks_bf16_stored for r in res16),
+            "controller": "per block the cheapest of one BF16 product on a BF16-stored "
+                          "residual, one BF16 product or split BF16 products on an FP32 "
+                          "residual, and the FP32 product, that keeps the rounding bound "
+                          "within eps/4",
             "deflation_roofline": rf16,
             "phases_ms": phases16,
         }

@@ -53,10 +53,11 @@ typedef enum { RBRP_F32 = 0, RBRP_F64 = 1 } rbrp_dtype;
 /* Arithmetic of the two deflation GEMMs R Q' and (R Q') Q'^T.
  * NATIVE: the input's type on MFMA (FP64 for F64 input; FP32 for F32 input,
  *         the "plain" single-precision form).
- * BF16:   BF16 MFMA operands with FP32 accumulation on an FP32 residual;
- *         per block either split into hi+lo BF16 parts (three products) or
- *         one BF16 product, chosen by the error budget of rbrp_options.theta
- *         (the FP32 product where neither fits the budget).
+ * BF16:   BF16 MFMA operands with FP32 accumulation; per block one BF16
+ *         product on a residual stored in BF16 (half the bytes), one BF16
+ *         product or hi+lo split BF16 parts (three products) on an FP32
+ *         residual, or the FP32 product, the cheapest that the error budget
+ *         of rbrp_options.theta allows.
  * In every mode the residual norms, the projection and reorthogonalisation
  * of the basis, the block CPQR and the solve for W are FP64. */
 typedef enum { RBRP_PREC_NATIVE = 0, RBRP_PREC_BF16 = 1 } rbrp_precision;
@@ -75,11 +76,13 @@ typedef struct {
                           (Alg. 3); < 0 -> 1                                  */
   double theta;        /* BF16 mode.  > 0: split products while the tracked
                           relative residual is above theta, one BF16 product
-                          below it.  <= 0 (the default): every block takes
-                          the cheapest of one BF16 product, the split BF16
-                          products and the FP32 product whose contribution,
-                          if kept for all later blocks, holds the error bound
-                          err_bound (rbrp_stats) within eps / 4            */
+                          below it (FP32 residual).  <= 0 (the default):
+                          every block takes the cheapest of one BF16 product
+                          with a BF16-stored residual, one BF16 product and
+                          the split BF16 products on an FP32 residual, and
+                          the FP32 product, whose contribution, if kept for
+                          the later blocks, holds the error bound err_bound
+                          (rbrp_stats) within eps / 4                    */
   int32_t profile;     /* 1: time the phases with HIP events on ``stream`` and
                           report them in rbrp_stats; 2: time only the
                           deflation launches (ms_deflate, deflate_launches)    */
@@ -134,6 +137,13 @@ typedef struct {
   int32_t deflate_launches;
   int32_t blocks_native;   /* BF16 mode: blocks the controller deflated with
                               the FP32 product                              */
+  double deflate_bytes;    /* algorithmic HBM bytes of the deflations: per
+                              launch the residual read and written (m n
+                              values each, in its storage type), d written;
+                              per block the new columns of L              */
+  int32_t blocks_bf16_stored; /* BF16 mode: blocks whose output residual was
+                              stored in BF16                              */
+  int32_t reserved;
   int32_t bprime[256];     /* b' of the first 256 blocks                       */
 } rbrp_stats;
 
@@ -207,9 +217,14 @@ const char* rbrp_status_string(rbrp_status s);
  * that of the dropped lo*lo product (2^-16 / sqrt 3, split only), u_op the
  * relative error bound of the product R Q' (2u; 3 * 2^-16 split), s_a the
  * accumulator's (2^-24 / sqrt 3; 2^-53 / sqrt 3 for FP64) and kstep the
- * columns one MFMA step adds (4 for FP64/FP32, 32 for BF16).
+ * columns one MFMA step adds (4 for FP64/FP32, 32 for BF16).  A residual
+ * stored in BF16 after the block adds (2^-8 / sqrt 3)^2 r_new^2: its
+ * rounding lies in every direction, and later blocks may move all of it
+ * into L.
  * The bound after block t is err_bound = 3 sqrt(sum of v over blocks 1..t).
- * mode: 0 FP64, 1 FP32, 2 split BF16 (hi + lo, three products), 3 BF16.
+ * mode: 0 FP64, 1 FP32, 2 split BF16 (hi + lo, three products), 3 BF16,
+ * 4 BF16 with the output residual stored in BF16 (5: the same, from a
+ * BF16-stored residual).
  * Returns a negative value for an unknown mode or bprime < 0.
  */
 double rbrp_err_bound_increment(int32_t mode, int32_t bprime, double r_prev_sq,

@@ -56,6 +56,9 @@ class rbrp_stats(ctypes.Structure):
         ("deflate_flops", ctypes.c_double),
         ("deflate_launches", ctypes.c_int32),
         ("blocks_native", ctypes.c_int32),
+        ("deflate_bytes", ctypes.c_double),
+        ("blocks_bf16_stored", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
         ("bprime", ctypes.c_int32 * 256),
     ]
 
@@ -224,6 +227,7 @@ class IDResult:
     profile: dict = None
     err_bound: float = 0.0       # bound on the rounding in the tracked residual
     blocks_native: int = 0       # BF16 form: blocks deflated with the FP32 product
+    blocks_bf16_stored: int = 0  # BF16 form: blocks whose residual was stored in BF16
 
 
 def workspace_size(m, n, b, dtype="f32", **opts):
@@ -274,13 +278,15 @@ def rbrp_id(X, eps, b, seed=0, *, want_w=True, workspace=None, out_S=None, out_W
     if o.profile:
         prof = dict(ms_init=st.ms_init, ms_select=st.ms_select, ms_filter=st.ms_filter,
                     ms_deflate=st.ms_deflate, ms_interp=st.ms_interp,
-                    deflate_flops=st.deflate_flops, deflate_launches=st.deflate_launches)
+                    deflate_flops=st.deflate_flops, deflate_launches=st.deflate_launches,
+                    deflate_bytes=st.deflate_bytes)
     return IDResult(S[:kk], kk, W[:, :kk] if W is not None else None, status, st.blocks,
                     st.blocks_split, [int(x) for x in st.bprime[:nb]], st.resid_tracked,
-                    st.norm_x_fro, prof, st.err_bound, st.blocks_native)
+                    st.norm_x_fro, prof, st.err_bound, st.blocks_native,
+                    st.blocks_bf16_stored)
 
 
-DEFLATE_MODES = {"f64": 0, "f32": 1, "bf16x3": 2, "bf16": 3}
+DEFLATE_MODES = {"f64": 0, "f32": 1, "bf16x3": 2, "bf16": 3, "bf16_stored": 4}
 
 
 def err_bound_increment(mode, bprime, r_prev_sq, r_new_sq):

@@ -125,9 +125,17 @@ __device__ __forceinline__ void sched_fence() {
   if constexpr (ON) __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int MODE, int RT, int CT, int BT, int NB, int DEPTH0>
+// Storage of the residual in a BF16-product launch (RIO): 0 R in its own
+// type in and out; 1 FP32 in, BF16 out (the block that switches the storage);
+// 2 BF16 in and out.  BF16 R is kept in a column order permuted inside each
+// group of 32 columns: storage position 8 h + 4 p + j holds column
+// 16 p + 4 h + j (h = 0..3, p = 0..1, j = 0..3), so that the 16 bytes at
+// position 8 h of a row are the 8 values lane (16 h + row) feeds the BF16
+// MFMA in phase 1 and holds in its two accumulators in phase 2.
+template <int MODE, int RT, int CT, int BT, int NB, int DEPTH0, int RIO = 0>
 __device__ __forceinline__ void deflate_body(
-    typename DT<MODE>::T* __restrict__ Rw, uint32_t ldr32, int64_t m, int nw, int w, int lane,
+    typename DT<MODE>::T* __restrict__ Rw, uint16_t* __restrict__ R16w, uint32_t ldr32,
+    int64_t m, int nw, int w, int lane,
     const void* __restrict__ fragB1, const void* __restrict__ fragA2, int64_t frag_stride,
     int g0, int bp, typename DT<MODE>::T* __restrict__ Lp, uint32_t ldl32, int32_t t,
     const int32_t* __restrict__ sb_s, typename DT<MODE>::T* __restrict__ Ps,
@@ -163,6 +171,28 @@ __device__ __forceinline__ void deflate_body(
     for (int rt = 0; rt < RT; ++rt)
       Rreg[rt][ct] = *reinterpret_cast<const V*>(Rw + (uint32_t)(16 * rt + l16) * ldr32 +
                                                  16 * ct + 4 * lhi);
+  };
+  // chunks 2 c2 and 2 c2 + 1 (one 32-column group)
+  auto load_pair = [&](int c2) {
+    if constexpr (RIO == 2) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const uint4 u = *reinterpret_cast<const uint4*>(
+            R16w + (uint32_t)(16 * rt + l16) * ldr32 + 32 * c2 + 8 * lhi);
+        const uint32_t wv[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t x = wv[j >> 1];
+          const uint32_t bits = (j & 1) ? (x & 0xFFFF0000u) : (x << 16);
+          Rreg[rt][2 * c2][j] = __uint_as_float(bits);
+          const uint32_t y = wv[2 + (j >> 1)];
+          Rreg[rt][2 * c2 + 1][j] = __uint_as_float((j & 1) ? (y & 0xFFFF0000u) : (y << 16));
+        }
+      }
+    } else {
+      load_r(2 * c2);
+      load_r(2 * c2 + 1);
+    }
   };
 
   // ---- phase 1: partial P = R_slice Q'_slice, R streamed in ----
@@ -204,8 +234,7 @@ __device__ __forceinline__ void deflate_body(
 #pragma unroll
     for (int k = 0; k < DEPTH; ++k) {
       if (k < C2) {
-        load_r(2 * k);
-        load_r(2 * k + 1);
+        load_pair(k);
 #pragma unroll
         for (int bt = 0; bt < NB; ++bt) {
           const uint32_t o = (uint32_t)((k * BT + bt) * 64) + lane;
@@ -242,8 +271,7 @@ __device__ __forceinline__ void deflate_body(
         }
       }
       if (c2 + DEPTH < C2) {
-        load_r(2 * (c2 + DEPTH));
-        load_r(2 * (c2 + DEPTH) + 1);
+        load_pair(c2 + DEPTH);
 #pragma unroll
         for (int bt = 0; bt < NB; ++bt) {
           const uint32_t o = (uint32_t)(((c2 + DEPTH) * BT + bt) * 64) + lane;
@@ -310,6 +338,27 @@ __device__ __forceinline__ void deflate_body(
       }
       *reinterpret_cast<V*>(Rw + (uint32_t)(16 * rt + l16) * ldr32 + 16 * ct + 4 * lhi) =
           Rreg[rt][ct];
+    }
+  };
+  // BF16 storage: chunks 2 c2 and 2 c2 + 1 rounded to nearest even and
+  // stored as one 16-byte group; the norms are those of the stored values
+  auto finish_pair16 = [&](int c2) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      uint32_t wv[4];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          const __bf16 a = (__bf16)Rreg[rt][2 * c2 + h][2 * jj];
+          const __bf16 b = (__bf16)Rreg[rt][2 * c2 + h][2 * jj + 1];
+          const double va = (double)(float)a, vb = (double)(float)b;
+          nrm[rt] += va * va + vb * vb;
+          wv[2 * h + jj] = (uint32_t)__builtin_bit_cast(uint16_t, a) |
+                           ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+        }
+      *reinterpret_cast<uint4*>(R16w + (uint32_t)(16 * rt + l16) * ldr32 + 32 * c2 + 8 * lhi) =
+          make_uint4(wv[0], wv[1], wv[2], wv[3]);
     }
   };
   if constexpr (!BF) {
@@ -407,7 +456,8 @@ __device__ __forceinline__ void deflate_body(
         }
       }
       sched_fence<FENCE>();
-      finish_chunk(ct);
+      if constexpr (RIO == 0) finish_chunk(ct);
+      else if (ct & 1) finish_pair16(ct >> 1);
     }
   }
 
@@ -447,9 +497,11 @@ __device__ __forceinline__ void deflate_body(
   }
 }
 
-template <int MODE, int RT, int CT, int BT, int NWMAX, int DEPTH = kDepth, int WPE = 2>
+template <int MODE, int RT, int CT, int BT, int NWMAX, int DEPTH = kDepth, int RIO = 0,
+          int WPE = 2>
 __global__ __launch_bounds__(64 * NWMAX) __attribute__((amdgpu_waves_per_eu(WPE))) void k_deflate(
-    typename DT<MODE>::T* __restrict__ R, int64_t ldr, int64_t m, int nw,
+    typename DT<MODE>::T* __restrict__ R, uint16_t* __restrict__ R16, int64_t ldr, int64_t m,
+    int nw,
     const void* __restrict__ fragB1, const void* __restrict__ fragA2,
     int64_t frag_stride, const int32_t* __restrict__ bprime_p,
     typename DT<MODE>::T* __restrict__ L, int64_t ldl, int64_t kS,
@@ -470,6 +522,7 @@ __global__ __launch_bounds__(64 * NWMAX) __attribute__((amdgpu_waves_per_eu(WPE)
   const int64_t r0 = (int64_t)blockIdx.x * MP;
   const int g0 = w * CT;                   // first global column tile of the wave
   T* __restrict__ Rw = R + r0 * ldr + 16 * (int64_t)g0;   // this wave's panel slice
+  uint16_t* __restrict__ R16w = RIO ? R16 + r0 * ldr + 16 * (int64_t)g0 : nullptr;
   T* __restrict__ Lp = L + r0 * ldl + kS;
   // skeleton flags of the panel's rows (for the L rows and the norms)
   if (threadIdx.x < MP) {
@@ -480,7 +533,8 @@ __global__ __launch_bounds__(64 * NWMAX) __attribute__((amdgpu_waves_per_eu(WPE)
   if (bp <= 0) return;
   const int nbt = (bp + 15) >> 4;          // active 16-wide tiles of b'
 #define RBRP_BODY(NBV)                                                                   \
-  deflate_body<MODE, RT, CT, BT, NBV, DEPTH>(Rw, (uint32_t)ldr, m, nw, w, lane, fragB1, fragA2,  \
+  deflate_body<MODE, RT, CT, BT, NBV, DEPTH, RIO>(Rw, R16w, (uint32_t)ldr, m, nw, w, lane,      \
+                                      fragB1, fragA2,                                      \
                                       frag_stride, g0, bp, Lp, (uint32_t)ldl, t, sb_s, Ps, \
                                       Ns, r0, d, part_sum, part_max)
   if constexpr (MODE == kModeBF16x3 || MODE == kModeBF16) {
@@ -622,7 +676,7 @@ int64_t deflate_pad_cols(int64_t n) {
 static int bt_for(int mode, int bmax) {
   int bt = 1;
   while (16 * bt < bmax) bt <<= 1;
-  if ((mode == kModeBF16x3 || mode == kModeBF16) && bt < 2) bt = 2;
+  if (is_bf16_mode(mode) && bt < 2) bt = 2;
   return bt;
 }
 
@@ -646,9 +700,9 @@ int64_t frag_elems(int mode, int64_t ldr, int bmax) {
   return G * bt * 64 * 4;
 }
 
-template <int MODE, int RT, int CT, int BT, int NWMAX>
+template <int MODE, int RT, int CT, int BT, int NWMAX, int RIO>
 static hipError_t run_deflate(const DeflateCfg& c, int64_t grid, hipStream_t s,
-                              void* R, int64_t ldr, int64_t m, const void* fB,
+                              void* R, void* R16, int64_t ldr, int64_t m, const void* fB,
                               const void* fA, int64_t fstride, const int32_t* bp,
                               void* L, int64_t ldl, int64_t kS, const int32_t* sel,
                               int32_t t, double* d, double* ps, double* pm) {
@@ -661,30 +715,30 @@ static hipError_t run_deflate(const DeflateCfg& c, int64_t grid, hipStream_t s,
   const size_t lds = c.nw * slot + (size_t)c.nw * 16 * RT * sizeof(double);
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_deflate<MODE, RT, CT, BT, NWMAX, DP>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_deflate<MODE, RT, CT, BT, NWMAX, DP, RIO>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        160 * 1024 - 1024);
     if (e != hipSuccess) return e;
     attr = true;
   }
   if (lds > 160 * 1024 - 1024) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_deflate<MODE, RT, CT, BT, NWMAX, DP>), dim3((unsigned)grid),
-                     dim3(64 * c.nw), lds, s, (T*)R, ldr, m, c.nw, fB, fA, fstride,
-                     bp, (T*)L, ldl, kS, sel, t, d, ps, pm);
+  hipLaunchKernelGGL((k_deflate<MODE, RT, CT, BT, NWMAX, DP, RIO>), dim3((unsigned)grid),
+                     dim3(64 * c.nw), lds, s, (T*)R, (uint16_t*)R16, ldr, m, c.nw, fB, fA,
+                     fstride, bp, (T*)L, ldl, kS, sel, t, d, ps, pm);
   return hipGetLastError();
 }
 
-template <int MODE, int BT>
+template <int MODE, int BT, int RIO>
 static hipError_t dispatch_ct(const DeflateCfg& c, int64_t mr, hipStream_t s, void* R,
-                              int64_t ldr, int64_t m, const void* fB, const void* fA,
-                              int64_t fstride, const int32_t* bp, void* L, int64_t ldl,
-                              int64_t kS, const int32_t* sel, int32_t t, double* d,
-                              double* ps, double* pm) {
+                              void* R16, int64_t ldr, int64_t m, const void* fB,
+                              const void* fA, int64_t fstride, const int32_t* bp, void* L,
+                              int64_t ldl, int64_t kS, const int32_t* sel, int32_t t,
+                              double* d, double* ps, double* pm) {
 #define RBRP_DEF_CASE(CTV, RTV, NWV)                                                   \
   if (c.ct == CTV && c.rt == RTV && c.nwmax == NWV)                                   \
-    return run_deflate<MODE, RTV, CTV, BT, NWV>(c, mr / (16 * RTV), s, R, ldr, m, fB,  \
-                                                fA, fstride, bp, L, ldl, kS, sel, t, d, \
-                                                ps, pm);
+    return run_deflate<MODE, RTV, CTV, BT, NWV, RIO>(c, mr / (16 * RTV), s, R, R16, ldr, \
+                                                     m, fB, fA, fstride, bp, L, ldl, kS, \
+                                                     sel, t, d, ps, pm);
   if constexpr (MODE == kModeF64) {
     RBRP_DEF_CASE(4, 2, 4)
     RBRP_DEF_CASE(8, 2, 4)
@@ -702,32 +756,32 @@ static hipError_t dispatch_ct(const DeflateCfg& c, int64_t mr, hipStream_t s, vo
   return hipErrorInvalidConfiguration;
 }
 
-template <int MODE>
+template <int MODE, int RIO>
 static hipError_t dispatch_bt(int bt, const DeflateCfg& c, int64_t mr, hipStream_t s,
-                              void* R, int64_t ldr, int64_t m, const void* fB,
+                              void* R, void* R16, int64_t ldr, int64_t m, const void* fB,
                               const void* fA, int64_t fstride, const int32_t* bp,
                               void* L, int64_t ldl, int64_t kS, const int32_t* sel,
                               int32_t t, double* d, double* ps, double* pm) {
   switch (bt) {
     case 1:
       if constexpr (MODE == kModeF64 || MODE == kModeF32)
-        return dispatch_ct<MODE, 1>(c, mr, s, R, ldr, m, fB, fA, fstride, bp, L, ldl, kS,
-                                    sel, t, d, ps, pm);
+        return dispatch_ct<MODE, 1, RIO>(c, mr, s, R, R16, ldr, m, fB, fA, fstride, bp, L,
+                                         ldl, kS, sel, t, d, ps, pm);
       break;
     case 2:
-      return dispatch_ct<MODE, 2>(c, mr, s, R, ldr, m, fB, fA, fstride, bp, L, ldl, kS, sel,
-                                  t, d, ps, pm);
+      return dispatch_ct<MODE, 2, RIO>(c, mr, s, R, R16, ldr, m, fB, fA, fstride, bp, L, ldl,
+                                       kS, sel, t, d, ps, pm);
     case 4:
-      return dispatch_ct<MODE, 4>(c, mr, s, R, ldr, m, fB, fA, fstride, bp, L, ldl, kS, sel,
-                                  t, d, ps, pm);
+      return dispatch_ct<MODE, 4, RIO>(c, mr, s, R, R16, ldr, m, fB, fA, fstride, bp, L, ldl,
+                                       kS, sel, t, d, ps, pm);
     case 8:
-      return dispatch_ct<MODE, 8>(c, mr, s, R, ldr, m, fB, fA, fstride, bp, L, ldl, kS, sel,
-                                  t, d, ps, pm);
+      return dispatch_ct<MODE, 8, RIO>(c, mr, s, R, R16, ldr, m, fB, fA, fstride, bp, L, ldl,
+                                       kS, sel, t, d, ps, pm);
   }
   return hipErrorInvalidConfiguration;
 }
 
-hipError_t launch_deflate(int mode, void* R, int64_t mr, int64_t ldr, int64_t m,
+hipError_t launch_deflate(int mode, void* R, void* R16, int64_t mr, int64_t ldr, int64_t m,
                           const void* fragB1, const void* fragA2,
                           const int32_t* bprime, int bmax, void* L, int64_t ldl,
                           int64_t kS, const int32_t* sel_block, int32_t t, double* d,
@@ -735,23 +789,51 @@ hipError_t launch_deflate(int mode, void* R, int64_t mr, int64_t ldr, int64_t m,
   DeflateCfg c;
   if (!pick_cfg(mode, ldr, &c)) return hipErrorInvalidConfiguration;
   if (mr % (16 * c.rt)) return hipErrorInvalidValue;
+  if (mode_stores_bf16(mode) && (!R16 || ldr % 32)) return hipErrorInvalidValue;
   const int bt = bt_for(mode, bmax);
-  const int64_t fstride = frag_elems(mode, ldr, bmax) / ((mode == kModeBF16x3 || mode == kModeBF16) ? 8 : 4);
+  const int64_t fstride = frag_elems(mode, ldr, bmax) / (is_bf16_mode(mode) ? 8 : 4);
+#define RBRP_ARGS bt, c, mr, s, R, R16, ldr, m, fragB1, fragA2, fstride, bprime, L, ldl, kS, \
+                  sel_block, t, d, part_sum, part_max
   switch (mode) {
-    case kModeF64:
-      return dispatch_bt<kModeF64>(bt, c, mr, s, R, ldr, m, fragB1, fragA2, fstride, bprime,
-                                   L, ldl, kS, sel_block, t, d, part_sum, part_max);
-    case kModeF32:
-      return dispatch_bt<kModeF32>(bt, c, mr, s, R, ldr, m, fragB1, fragA2, fstride, bprime,
-                                   L, ldl, kS, sel_block, t, d, part_sum, part_max);
-    case kModeBF16x3:
-      return dispatch_bt<kModeBF16x3>(bt, c, mr, s, R, ldr, m, fragB1, fragA2, fstride,
-                                      bprime, L, ldl, kS, sel_block, t, d, part_sum, part_max);
-    case kModeBF16:
-      return dispatch_bt<kModeBF16>(bt, c, mr, s, R, ldr, m, fragB1, fragA2, fstride, bprime,
-                                    L, ldl, kS, sel_block, t, d, part_sum, part_max);
+    case kModeF64: return dispatch_bt<kModeF64, 0>(RBRP_ARGS);
+    case kModeF32: return dispatch_bt<kModeF32, 0>(RBRP_ARGS);
+    case kModeBF16x3: return dispatch_bt<kModeBF16x3, 0>(RBRP_ARGS);
+    case kModeBF16: return dispatch_bt<kModeBF16, 0>(RBRP_ARGS);
+    case kModeBF16W: return dispatch_bt<kModeBF16, 1>(RBRP_ARGS);
+    case kModeBF16R: return dispatch_bt<kModeBF16, 2>(RBRP_ARGS);
   }
+#undef RBRP_ARGS
   return hipErrorInvalidValue;
+}
+
+// BF16 residual (permuted 32-column groups) back to FP32 in natural column
+// order, one thread per 8 stored values.
+__global__ __launch_bounds__(256) void k_r16_to_r32(const uint16_t* __restrict__ R16,
+                                                    float* __restrict__ R, int64_t total8) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total8) return;
+  const uint4 u = reinterpret_cast<const uint4*>(R16)[e];
+  const uint32_t wv[4] = {u.x, u.y, u.z, u.w};
+  // stored positions 8 h .. 8 h + 7 of a 32-column group: h = e % 4
+  const int64_t grp = e >> 2;
+  const int h = (int)(e & 3);
+  float* dst = R + grp * 32;
+#pragma unroll
+  for (int pj = 0; pj < 8; ++pj) {
+    const uint32_t x = wv[pj >> 1];
+    const uint32_t bits = (pj & 1) ? (x & 0xFFFF0000u) : (x << 16);
+    const int p = pj >> 2, j = pj & 3;
+    dst[16 * p + 4 * h + j] = __uint_as_float(bits);
+  }
+}
+
+hipError_t launch_r16_to_r32(const void* R16, void* R, int64_t mr, int64_t ldr,
+                             hipStream_t s) {
+  if (ldr % 32) return hipErrorInvalidValue;
+  const int64_t total8 = mr * ldr / 8;
+  hipLaunchKernelGGL(k_r16_to_r32, dim3((unsigned)ceil_div(total8, 256)), dim3(256), 0, s,
+                     (const uint16_t*)R16, (float*)R, total8);
+  return hipGetLastError();
 }
 
 hipError_t launch_make_frags(const double* Qt_new, int64_t ldq, const int32_t* bprime,
@@ -759,8 +841,8 @@ hipError_t launch_make_frags(const double* Qt_new, int64_t ldq, const int32_t* b
                              void* fragA2, hipStream_t s) {
   const int bt = bt_for(mode, bmax);
   const int64_t G = n_pad / 16;
-  const bool bf = (mode == kModeBF16x3 || mode == kModeBF16);
-  const int64_t total = bf ? G * bt * 64 * 4 : G * bt * 64 * 4;
+  const bool bf = is_bf16_mode(mode);
+  const int64_t total = G * bt * 64 * 4;
   // BF16: (G/2)*bt*64*8 = G*bt*256 elements (B) and G*(bt/2)*64*8 (A): same count
   const int64_t fstride = bf ? total / 8 : total / 4;
   const unsigned grid = (unsigned)ceil_div(total, 256);
@@ -775,6 +857,8 @@ hipError_t launch_make_frags(const double* Qt_new, int64_t ldq, const int32_t* b
       break;
     case kModeBF16x3:
     case kModeBF16:
+    case kModeBF16W:
+    case kModeBF16R:
       hipLaunchKernelGGL(k_make_frags<kModeBF16x3>, dim3(grid), dim3(256), 0, s, Qt_new,
                          ldq, bprime, G, bt, fragB1, fragA2, fstride);
       break;

@@ -44,6 +44,7 @@ struct Plan {
 struct Work {
   DevScalars* sc;
   void* R;
+  void* R16;   // BF16 residual of the BF16 form (permuted 32-column groups)
   double* d;
   double* part_sum;
   double* part_max;
@@ -119,6 +120,7 @@ size_t layout(const Plan& p, char* base, Work* w) {
   const int mode = p.bf16 ? kModeBF16x3 : p.native_mode;
   w->sc = cv.take<DevScalars>(1);
   w->R = cv.take<char>((size_t)p.mr * p.ldr * rs);
+  w->R16 = p.bf16 ? cv.take<char>((size_t)p.mr * p.ldr * 2) : nullptr;
   w->d = cv.take<double>(p.mr);
   w->part_sum = cv.take<double>(p.nparts);
   w->part_max = cv.take<double>(p.nparts);
@@ -174,21 +176,30 @@ DevScalars* host_scalars() {
 constexpr double kErrLambda = 3.0;
 constexpr double kErrBudget = 0.25;   // default controller: E <= eps / 4
 
-struct ModeDev { double sq, sx, sa, uop; int kstep; };
+// ss: deviation of the storage rounding of the block's output residual
+// (BF16 storage; 0 when R keeps FP32).
+struct ModeDev { double sq, sx, sa, uop, ss; int kstep; };
 
 bool mode_dev(int mode, ModeDev* d) {
   const double r3 = 1.0 / sqrt(3.0);
   const double u64 = ldexp(1.0, -53), u32 = ldexp(1.0, -24), ub = ldexp(1.0, -8);
   switch (mode) {
-    case kModeF64: *d = {u64 * r3, 0.0, u64 * r3, 2 * u64, 4}; return true;
-    case kModeF32: *d = {u32 * r3, 0.0, u32 * r3, 2 * u32, 4}; return true;
-    case kModeBF16x3: *d = {ub * ub * r3, ub * ub * r3, u32 * r3, 3 * ub * ub, 32}; return true;
-    case kModeBF16: *d = {ub * r3, 0.0, u32 * r3, 2 * ub, 32}; return true;
+    case kModeF64: *d = {u64 * r3, 0.0, u64 * r3, 2 * u64, 0.0, 4}; return true;
+    case kModeF32: *d = {u32 * r3, 0.0, u32 * r3, 2 * u32, 0.0, 4}; return true;
+    case kModeBF16x3:
+      *d = {ub * ub * r3, ub * ub * r3, u32 * r3, 3 * ub * ub, 0.0, 32};
+      return true;
+    case kModeBF16: *d = {ub * r3, 0.0, u32 * r3, 2 * ub, 0.0, 32}; return true;
+    case kModeBF16W:
+    case kModeBF16R: *d = {ub * r3, 0.0, u32 * r3, 2 * ub, ub * r3, 32}; return true;
   }
   return false;
 }
 
 // Variance increment of one block (relative to ||X||_F^2); -1 on bad input.
+// A residual stored in BF16 adds the rounding of every stored value: it lies
+// in all directions, so the part of it that later blocks move into L (and
+// out of the tracked norm) is at most all of it, sd ss |R_new|.
 double err_var_increment(int mode, int bprime, double r_prev_sq, double r_new_sq) {
   ModeDev md;
   if (!mode_dev(mode, &md) || bprime < 0) return -1.0;
@@ -196,18 +207,23 @@ double err_var_increment(int mode, int bprime, double r_prev_sq, double r_new_sq
   const double rp2 = fmax(r_prev_sq, 0.0);
   return (md.sq * md.sq + md.sx * md.sx) * p2 +
          (md.sq * md.uop * md.sq * md.uop +
-          md.sa * md.sa * ((double)bprime / md.kstep + 1.0)) * rp2;
+          md.sa * md.sa * ((double)bprime / md.kstep + 1.0)) * rp2 +
+         md.ss * md.ss * fmax(r_new_sq, 0.0);
 }
 
-// Worst contribution of keeping ``mode`` for every later block, starting from
-// the relative squared residual r_sq: the later blocks remove at most r_sq in
-// total, and the terms in |R| are allowed for up to 64 more blocks.
-double err_var_future(int mode, int b, double r_sq) {
+// Contribution of keeping ``mode`` for every later block, starting from the
+// relative squared residual r_sq: the later blocks remove at most r_sq in
+// total; the product terms in |R| are allowed for up to 64 more blocks, the
+// storage term for n_future blocks (the controller's estimate of the blocks
+// left; a wrong estimate costs time, not accuracy, since the bound itself
+// sums the increments of the blocks actually run).
+double err_var_future(int mode, int b, double r_sq, int n_future) {
   ModeDev md;
   if (!mode_dev(mode, &md)) return 1e300;
   return (md.sq * md.sq + md.sx * md.sx) * r_sq +
          64.0 * (md.sq * md.uop * md.sq * md.uop +
-                 md.sa * md.sa * ((double)b / md.kstep + 1.0)) * r_sq;
+                 md.sa * md.sa * ((double)b / md.kstep + 1.0)) * r_sq +
+         (double)n_future * md.ss * md.ss * r_sq;
 }
 
 #define RBRP_HIP(expr)                             \
@@ -361,6 +377,8 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
   prof.level = (o.profile == 1 || o.profile == 2) ? o.profile : 0;
   prof.s = s;
   double flops = 0.0;
+  double dbytes = 0.0;   // algorithmic HBM bytes of the deflation launches
+  bool r16 = false;      // the residual is held in BF16 (BF16 form)
 
   RBRP_HIP(hipMemsetAsync(w.sc, 0, sizeof(DevScalars), s));
   RBRP_HIP(hipMemsetAsync(w.sel_block, 0xFF, sizeof(int32_t) * p.m, s));
@@ -482,24 +500,33 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
                            s));
     // deflation of the residual, in launches of at most kDeflateMaxB columns
     int mode = p.native_mode;
+    bool to_fp32_storage = false;
     if (p.bf16) {
       const double r_sq = sum_d / D0;
       if (theta > 0.0) {
         mode = sqrt(r_sq) > theta ? kModeBF16x3 : kModeBF16;
       } else {
-        // cheapest product whose contribution, kept for every later block,
-        // holds the bound within the budget
+        // the cheapest deflation whose contribution, kept for every later
+        // block, holds the bound within the budget: one BF16 product on a
+        // BF16-stored residual, then on the FP32 residual, the split
+        // products, the FP32 product
         const double lim = kErrBudget * eps / kErrLambda;
+        const int64_t left = (k_max - kS + b - 1) / b;
+        const int n_future = (int)(left < 1 ? 1 : (left > 64 ? 64 : left));
         mode = p.native_mode;
-        for (int cand : {kModeBF16, kModeBF16x3}) {
-          if (err_var + err_var_future(cand, b, r_sq) <= lim * lim) {
+        for (int cand : {r16 ? kModeBF16R : kModeBF16W, kModeBF16, kModeBF16x3}) {
+          if (err_var + err_var_future(cand, b, r_sq, n_future) <= lim * lim) {
             mode = cand;
             break;
           }
         }
       }
+      // a BF16-stored residual that the budget no longer allows goes back to
+      // FP32 (exactly: every BF16 value is an FP32 value)
+      if (r16 && !mode_reads_bf16(mode)) to_fp32_storage = true;
       if (mode == kModeBF16x3) st.blocks_split++;
       if (mode == p.native_mode) st.blocks_native++;
+      if (mode_stores_bf16(mode)) st.blocks_bf16_stored++;
     }
     int nchunk = 1;
     if (b > kDeflateMaxB) {
@@ -507,19 +534,32 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
       if (rs != RBRP_OK) return rs;
       nchunk = h->bprime > kDeflateMaxB ? 2 : 1;
     }
+    if (to_fp32_storage) {
+      RBRP_HIP(launch_r16_to_r32(w.R16, w.R, p.mr, ldr, s));
+      r16 = false;
+    }
     prof.end();
+    const double s_in = mode_reads_bf16(mode) ? 2.0 : (p.r_f64 ? 8.0 : 4.0);
     for (int c = 0; c < nchunk; ++c) {
       const int32_t* bcnt = b > kDeflateMaxB ? &w.sc->bchunk[c] : &w.sc->bprime;
+      // the first launch of a block that switches to BF16 storage writes the
+      // BF16 residual, a second one reads it
+      const int cm = (mode == kModeBF16W && c > 0) ? kModeBF16R : mode;
       prof.begin(2);
       RBRP_HIP(launch_make_frags(Qn + (int64_t)c * kDeflateMaxB * ldr, ldr, bcnt, ldr, p.bdef,
-                                 mode, w.fragB1, w.fragA2, s));
+                                 cm, w.fragB1, w.fragA2, s));
       prof.end();
       prof.begin(3);
-      RBRP_HIP(launch_deflate(mode, w.R, p.mr, ldr, m, w.fragB1, w.fragA2, bcnt, p.bdef, w.L,
-                              p.ldl, kS + (int64_t)c * kDeflateMaxB, w.sel_block, t, w.d,
+      RBRP_HIP(launch_deflate(cm, w.R, w.R16, p.mr, ldr, m, w.fragB1, w.fragA2, bcnt, p.bdef,
+                              w.L, p.ldl, kS + (int64_t)c * kDeflateMaxB, w.sel_block, t, w.d,
                               w.part_sum, w.part_max, s));
       prof.end();
+      // algorithmic bytes: R read and written, d written (L below)
+      const double sr = mode_reads_bf16(cm) ? 2.0 : s_in;
+      const double sw = mode_stores_bf16(cm) ? 2.0 : (p.r_f64 ? 8.0 : 4.0);
+      dbytes += (double)m * (double)n * (sr + sw) + 8.0 * (double)m;
     }
+    if (mode_stores_bf16(mode)) r16 = true;
     RBRP_HIP(launch_reduce(w.part_sum, w.part_max, p.mr / def_rows, w.sc, 0, s));
     // This block's scalars are copied out first; the next block's selection
     // needs only d, S and the block size, so when the size is certain (b
@@ -536,6 +576,7 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     RBRP_HIP(hipEventSynchronize(ev_scalars));
     const int bp = h->bprime;
     flops += 4.0 * (double)m * (double)n * (double)(bp > 0 ? bp : 0);
+    dbytes += (double)m * (double)(bp > 0 ? bp : 0) * (p.r_f64 ? 8.0 : 4.0);   // L columns
     if (t <= 256) st.bprime[t - 1] = bp;
     st.blocks = t;
     if (h->stop_rank || bp <= 0) break;
@@ -544,9 +585,11 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     sum_last = sum_d;
     kS += bp;
     {
-      // a second deflation launch rounds the accumulator once more per row
-      const double v =
-          err_var_increment(mode, bp + 32 * (nchunk - 1), sum_d / D0, h->sum_d / D0);
+      // a second deflation launch rounds the accumulator once more per row,
+      // and with BF16 storage rounds the (larger) intermediate residual too
+      double v = err_var_increment(mode, bp + 32 * (nchunk - 1), sum_d / D0, h->sum_d / D0);
+      if (v > 0.0 && nchunk > 1 && mode_stores_bf16(mode))
+        v += (nchunk - 1) * err_var_increment(mode, 0, 0.0, sum_d / D0);
       if (v > 0.0) err_var += v;
     }
     sum_d = h->sum_d;
@@ -600,6 +643,7 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     st.ms_interp = ms5[4];
     st.deflate_launches = nd;
     st.deflate_flops = flops;
+    st.deflate_bytes = dbytes;
   }
   if (stats_host) *stats_host = st;
   return final_status;

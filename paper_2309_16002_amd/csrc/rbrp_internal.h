@@ -209,13 +209,18 @@ hipError_t launch_make_frags(const double* Qt_new, int64_t ldq,
 // Fused deflation of one block (the hot kernel):
 // P = R Q', L[:, kS:kS+b'] = P (rows of earlier skeletons zeroed),
 // R <- R - P Q'^T, d_i = ||R_i||^2 (0 on skeletons), partial sums / maxima.
-hipError_t launch_deflate(int mode, void* R, int64_t mr, int64_t ldr,
+// R16: the BF16 residual (mr x ldr, permuted 32-column groups) that modes
+// kModeBF16W write and kModeBF16R read and write; may be NULL otherwise.
+hipError_t launch_deflate(int mode, void* R, void* R16, int64_t mr, int64_t ldr,
                           int64_t m, const void* fragB1, const void* fragA2,
                           const int32_t* bprime, int bmax, void* L,
                           int64_t ldl, int64_t kS, const int32_t* sel_block,
                           int32_t t, double* d, double* part_sum,
                           double* part_max, hipStream_t s);
 int64_t deflate_num_partials(int64_t mr);
+// BF16 residual back to the FP32 residual (natural column order).
+hipError_t launch_r16_to_r32(const void* R16, void* R, int64_t mr, int64_t ldr,
+                             hipStream_t s);
 int deflate_supported(int mode, int64_t ldr, int bmax);
 int deflate_rows_per_wg(int mode, int64_t ldr);
 int64_t deflate_pad_cols(int64_t n);
@@ -228,7 +233,14 @@ hipError_t launch_interp(const void* L, int l_f64, int64_t ldl, int64_t m,
 size_t interp_workspace_doubles(int64_t m, int64_t k, int refine);
 
 // Deflation arithmetic modes.
-enum DeflateMode { kModeF64 = 0, kModeF32 = 1, kModeBF16x3 = 2, kModeBF16 = 3 };
+// Deflation modes: the products' arithmetic and, for BF16 products, the
+// residual's storage (W: FP32 in, BF16 out; R: BF16 in and out).
+enum DeflateMode {
+  kModeF64 = 0, kModeF32 = 1, kModeBF16x3 = 2, kModeBF16 = 3, kModeBF16W = 4, kModeBF16R = 5
+};
+inline bool is_bf16_mode(int mode) { return mode >= kModeBF16x3 && mode <= kModeBF16R; }
+inline bool mode_stores_bf16(int mode) { return mode == kModeBF16W || mode == kModeBF16R; }
+inline bool mode_reads_bf16(int mode) { return mode == kModeBF16R; }
 
 // ---- batched form (k_batched.hip) ----
 bool batch_shape_ok(const rbrp_batch_shape* sh);

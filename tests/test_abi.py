@@ -218,6 +218,9 @@ def test_rows_beyond_the_sampler_limit_are_rejected_before_device_work(L):
 
 def test_stats_layout():
     # blocks, blocks_split, resid_tracked, err_bound, norm_x_fro, five phase
-    # times, deflate_flops, deflate_launches, blocks_native, bprime[256]
-    assert ctypes.sizeof(B.rbrp_stats) == 8 + 8 * 9 + 8 + 4 * 256
+    # times, deflate_flops, deflate_launches, blocks_native, deflate_bytes,
+    # blocks_bf16_stored, reserved, bprime[256]
+    assert ctypes.sizeof(B.rbrp_stats) == 8 + 8 * 9 + 8 + 8 + 8 + 4 * 256
     assert B.rbrp_stats.err_bound.offset == 16
+    assert B.rbrp_stats.deflate_bytes.offset == 88
+    assert B.rbrp_stats.bprime.offset == 104

@@ -43,21 +43,24 @@ def _split(x):
 
 def _deflate(R, Qn, mode):
     """One emulated deflation step of the FP32 residual R by the FP64 block Qn
-    (n x b'), products with FP32 accumulation."""
+    (n x b'), products with FP32 accumulation.  Returns the new residual (as
+    stored: FP32, or BF16 values for the stored-BF16 mode) and the product
+    P = R Q' (the block's new columns of L)."""
     Qf = Qn.astype(np.float32)
     if mode == "f32":
         P = R @ Qf
-        return (R - P @ Qf.T).astype(np.float32)
-    if mode == "bf16":
+        return (R - P @ Qf.T).astype(np.float32), P
+    if mode in ("bf16", "bf16_stored"):
         Rb, Qb = _bf16(R), _bf16(Qf)
         P = Rb @ Qb
-        return (R - _bf16(P) @ Qb.T).astype(np.float32)
+        Rn = (R - _bf16(P) @ Qb.T).astype(np.float32)
+        return (_bf16(Rn) if mode == "bf16_stored" else Rn), P
     assert mode == "bf16x3"
     Rh, Rl = _split(R)
     Qh, Ql = _split(Qf)
     P = Rh @ Qh + Rh @ Ql + Rl @ Qh
     Ph, Pl = _split(P)
-    return (R - (Ph @ Qh.T + Ph @ Ql.T + Pl @ Qh.T)).astype(np.float32)
+    return (R - (Ph @ Qh.T + Ph @ Ql.T + Pl @ Qh.T)).astype(np.float32), P
 
 
 def _emulate(X32, eps, b, seed, modes):
@@ -67,13 +70,21 @@ def _emulate(X32, eps, b, seed, modes):
     R = X32.copy()
     r2_prev = 1.0
     var = 0.0
+    eL2 = 0.0
+    in_S = np.zeros(X.shape[0], dtype=bool)
     out = []
     k = 0
-    for t, (_, bp) in enumerate(ref.blocks):
+    for t, (S_t, bp) in enumerate(ref.blocks):
         mode = modes(t, r2_prev)
         Qn = ref.Qt[k:k + bp].T
         k += bp
-        R = _deflate(R, Qn, mode)
+        R, P = _deflate(R, Qn, mode)
+        # error of the block's columns of L (rows of earlier skeletons are zero
+        # on both sides): it enters the ID error X - W X_S = X (I - Q Q^T) + E_L Q^T
+        dP = P.astype(np.float64) - X @ Qn
+        dP[in_S] = 0.0
+        eL2 += float(np.sum(dP * dP))
+        in_S[ref.S[:k]] = True
         R64 = R.astype(np.float64)
         r2 = float(np.sum(R64 * R64)) / D0
         v = rb.err_bound_increment(mode, bp, r2_prev, r2)
@@ -85,23 +96,28 @@ def _emulate(X32, eps, b, seed, modes):
         Dlt = R64 - Rtrue
         Dperp = Dlt - (Dlt @ Qk) @ Qk.T
         nx = np.sqrt(D0)
+        rho_true = np.linalg.norm(Rtrue) / nx
         out.append(dict(t=t + 1, mode=mode, E=E, perp=np.linalg.norm(Dperp) / nx,
                         par=np.linalg.norm(Dlt - Dperp) / nx, rho=np.sqrt(r2),
-                        rho_true=np.linalg.norm(Rtrue) / nx))
+                        rho_true=rho_true, eL=np.sqrt(eL2 / D0),
+                        id_err=np.sqrt(rho_true ** 2 + eL2 / D0)))
         r2_prev = r2
     return out
 
 
 def _check(rows):
     for r in rows:
-        print(f"  block {r['t']:2d} {r['mode']:6s} rho={r['rho']:.3e} true={r['rho_true']:.3e} "
-              f"perp={r['perp']:.2e} par={r['par']:.2e} E={r['E']:.2e}")
+        print(f"  block {r['t']:2d} {r['mode']:11s} rho={r['rho']:.3e} true={r['rho_true']:.3e} "
+              f"perp={r['perp']:.2e} par={r['par']:.2e} eL={r['eL']:.2e} E={r['E']:.2e}")
         assert r["perp"] <= r["E"]
         assert r["rho_true"] <= r["rho"] + r["E"]
+        # the ID error with the rounded columns of L, which the stopping rule
+        # rho + E <= eps must cover
+        assert r["id_err"] <= r["rho"] + r["E"]
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
-@pytest.mark.parametrize("mode", ["f32", "bf16x3", "bf16"])
+@pytest.mark.parametrize("mode", ["f32", "bf16x3", "bf16", "bf16_stored"])
 def test_bound_covers_emulated_rounding_power_spectrum(mode, seed):
     X = svd_matrix(2500, 256, power_spectrum(256, 1.5), seed=200 + seed).astype(np.float32)
     rows = _emulate(X, 1e-4, 32, seed, lambda t, r2: mode)
@@ -123,6 +139,18 @@ def test_bound_covers_controller_sequence_gmm(seed):
     _check(rows)
 
 
+@pytest.mark.parametrize("seed", [6, 7])
+def test_bound_covers_bf16_storage_after_switch(seed):
+    # FP32 products while the residual is large, then one BF16 product on a
+    # BF16-stored residual (the default controller's sequence at small rho)
+    eps = 1e-4
+    X = svd_matrix(3000, 256, power_spectrum(256, 1.5), seed=300 + seed).astype(np.float32)
+    rows = _emulate(X, eps, 32, seed,
+                    lambda t, r2: "f32" if np.sqrt(r2) > 2e-3 else "bf16_stored")
+    assert {r["mode"] for r in rows} == {"f32", "bf16_stored"}
+    _check(rows)
+
+
 def test_increment_formula_properties():
     # cheaper products carry larger increments; no increment without work
     args = (64, 0.25, 0.09)
@@ -137,4 +165,8 @@ def test_increment_formula_properties():
     assert rb.err_bound_increment("bf16", 64, 0.1, 0.2) < rb.err_bound_increment(
         "bf16", 64, 0.2, 0.1)
     assert rb.err_bound_increment(9, 64, 0.1, 0.05) < 0.0
+    # BF16 storage adds the rounding of the stored residual, (u^2 / 3) r_new^2
+    vs = rb.err_bound_increment("bf16_stored", *args)
+    assert vs == pytest.approx(v[3] + u * u / 3 * args[2], rel=1e-12)
+    assert rb.err_bound_increment(5, *args) == vs
     assert rb.err_bound_increment("f32", -1, 0.1, 0.05) < 0.0

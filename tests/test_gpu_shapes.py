@@ -5,7 +5,8 @@ oracle's first block and FP64 error checks.
   FP32 products and the BF16 form.  n = 2048 runs the eight-wave deflation
   panels of 16 column tiles on 32-row panels with eight 16-wide b' tiles,
   in every product mode the BF16 form's controller picks (FP32 for the first
-  block at eps = 1e-4, split BF16, then one BF16 product).
+  block at eps = 1e-4, split BF16, then one BF16 product on the FP32 residual
+  and finally on a BF16-stored residual).
 * n = 1000, b = 64 (the adversarial GMM workload's shape) in the BF16 form:
   four-wave panels of 16 column tiles with four b' tiles.
 
@@ -89,7 +90,8 @@ def _check(rb, X, eps, b, seed, precision):
     assert torch.equal(res.W[torch.as_tensor(S, device="cuda")], eye)
     e_true, e_opt = _errors(Xg.double(), res.W, S)
     print(f"  k={res.k} blocks={res.blocks} split={res.blocks_split} "
-          f"native={res.blocks_native} e_true={e_true:.4e} e_opt={e_opt:.4e} "
+          f"native={res.blocks_native} bf16_stored={res.blocks_bf16_stored} "
+          f"e_true={e_true:.4e} e_opt={e_opt:.4e} "
           f"tracked={res.resid_tracked:.4e} E={res.err_bound:.2e}", flush=True)
     assert e_true <= eps
     assert res.resid_tracked + res.err_bound <= eps
@@ -112,6 +114,8 @@ def test_n2048_b128(rb, power2048, precision):
         # split BF16 while the residual is large, one product after
         assert res.blocks_native >= 1 and res.blocks_split >= 1
         assert res.blocks_native + res.blocks_split < res.blocks
+        # the last blocks on a BF16-stored residual (half the bytes)
+        assert res.blocks_bf16_stored >= 1
 
 
 def test_n1000_b64_bf16(rb, gmm1000):
