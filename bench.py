@@ -73,9 +73,11 @@ def _kernel_sha():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _traffic(workload):
-    """HBM bytes per deflation launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
+def _traffic(workload, form="fp32"):
+    """HBM bytes per deflation launch (FETCH_SIZE + WRITE_SIZE, calibrated
+    against a copy kernel) from the committed rocprofv3 counter summary of
+    this workload, for the FP32 plain form or the BF16 form's mix of
+    launches; None unless it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", f"deflate_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -86,7 +88,7 @@ def _traffic(workload):
         return None
     if rec.get("kernel_sha") != _kernel_sha():
         return None
-    return rec.get("bytes_per_launch")
+    return (rec.get(form) or {}).get("bytes_per_launch")
 
 
 def make_input(name):
@@ -402,6 +404,7 @@ def main():
         res16, tot16, err16, phases16 = run_form("bf16", args.steps, 1)
         v16 = m * args.steps / tot16
         rf16 = deflation_roofline(res16, "bf16")
+        rf16["traffic"] = _traffic(args.workload, "bf16_form")
         line["bf16_form"] = {
             "value": v16, "unit": "rows/s", "ms_per_step": 1e3 * tot16 / args.steps,
             "speedup_vs_fp32_plain": v16 / value,
