@@ -17,8 +17,9 @@ adaptive interpolative decomposition", arXiv:2309.16002) in NumPy/FP64:
                   and the greedy (RBGP, Remark 4.3) selection variant.
 * ``srp``      -- Algorithm 1 (sequential random pivoting), used as an
                   independent special case (RBRP with b = 1).
-* ``interp``   -- interpolation matrix: W = X X_S^+ (eq. stable_id) and
-                  Algorithm 3 (W from L).
+* ``interp``   -- interpolation matrix: W = X X_S^+ (eq. stable_id),
+                  Algorithm 3 (W from L), and Remark 5.2's truncated-SVD
+                  pseudo-inverse of L_1.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The GPU library never calls it, and it
@@ -37,11 +38,11 @@ from .sampler import fixed_point_weights, sample_block
 from .cpqr import cpqr, truncation_rank, tails_from_r
 from .rbrp import rbrp, RBRPResult
 from .srp import srp
-from .interp import w_lstsq, w_from_l, relative_id_error
+from .interp import w_lstsq, w_from_l, w_svd_pinv, relative_id_error
 from .trim import trim_rank, projection_error_sq
 
 __all__ = [
     "philox4x64_10", "philox_word0", "fixed_point_weights", "sample_block",
     "cpqr", "truncation_rank", "tails_from_r", "rbrp", "RBRPResult", "srp",
-    "w_lstsq", "w_from_l", "relative_id_error", "trim_rank", "projection_error_sq",
+    "w_lstsq", "w_from_l", "w_svd_pinv", "relative_id_error", "trim_rank", "projection_error_sq",
 ]
