@@ -48,7 +48,7 @@ def test_diagonal_factor_closed_form():
     rng = np.random.default_rng(5)
     # 2e-12 lies between the absolute 1e-12 and the relative 1e-12 * 3: the
     # relative reading drops it
-    d = np.array([2.0, -1.0, 2e-12, 0.5, -4e-14, 1e-9])
+    d = np.array([3.0, -1.0, 2e-12, 0.5, -4e-14, 1e-9])
     L1 = np.diag(d)
     L2 = rng.standard_normal((40, d.size))
     L, S, rest = _embed(L1, L2, 6)
