@@ -245,6 +245,10 @@ def main():
     ap.add_argument("--trim", action="store_true",
                     help="rank trimming: cut k to the shortest prefix of the selection "
                          "that meets eps (an option of rbrp_id; off in the default line)")
+    ap.add_argument("--w-method", default="substitution", choices=["substitution", "svd"],
+                    help="interpolation matrix: blocked substitution with one refinement "
+                         "step (Alg. 3, the default) or the truncated-SVD pseudo-inverse of "
+                         "L_1 (Remark 5.2)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device-to-device copy of MB megabytes (the "
                          "reference for HBM byte counters) and exit")
@@ -303,7 +307,7 @@ def main():
             return rb.rbrp_id(Xg, cfg["eps"], cfg["b"], seed, workspace=ws, out_S=S_buf,
                               out_W=W_buf, precision=precision, profile=profile,
                               k_max=k_max, fixed_rank=fixed, trim=args.trim,
-                              greedy=args.greedy)
+                              greedy=args.greedy, w_method=args.w_method)
         for i in range(warmup):
             step(1000 + i)
             print(f"[bench] {precision} warmup {i + 1}/{warmup} done", file=sys.stderr,
@@ -390,6 +394,8 @@ def main():
                    **({"fixed_rank": k_max} if fixed else {}),
                    **({"trim": True} if args.trim else {}),
                    **({"greedy": True} if args.greedy else {}),
+                   **({"w_method": "truncated-SVD pseudo-inverse"}
+                      if args.w_method == "svd" else {}),
                    "deflation": "fp64-mfma" if dtype == "f64" else "fp32-mfma (plain)",
                    "parallelism": "single-gpu"},
         "roofline": roofline,

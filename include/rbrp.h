@@ -113,6 +113,15 @@ typedef struct {
                           block can be compared with its, whatever the
                           deflation's precision.  NULL / 0: off           */
   int32_t replay_blocks;
+  int32_t w_method;    /* 0: W = L_2 L_1^{-1} by blocked substitution with
+                          w_refine refinement steps (Alg. 3; the default).
+                          1: W = L_2 L_1^+ through the truncated SVD of L_1
+                          (Remark 5.2): singular values below
+                          w_clip * sigma_max(L_1) and their singular vectors
+                          are dropped (one-sided Jacobi SVD in FP64, then
+                          W = L L_1^+ as one product; w_refine is ignored).
+                          W(S,:) = I in both                              */
+  double w_clip;       /* w_method 1: relative clip; <= 0 -> 1e-12        */
 } rbrp_options;
 
 /* Per-call statistics (optional, host memory). */
@@ -143,7 +152,8 @@ typedef struct {
                               per block the new columns of L              */
   int32_t blocks_bf16_stored; /* BF16 mode: blocks whose output residual was
                               stored in BF16                              */
-  int32_t reserved;
+  int32_t w_rank;          /* singular values of L_1 kept (w_method 1); k
+                              with substitution                          */
   int32_t bprime[256];     /* b' of the first 256 blocks                       */
 } rbrp_stats;
 
@@ -288,7 +298,8 @@ rbrp_status rbrp_block_cpqr(const double* Vt, int64_t n, int32_t nb,
  * a hierarchical-matrix compression, the fast-direct-solver use the paper
  * motivates in section 6) in one persistent launch.  Each ID runs the same
  * Alg. 2 + Alg. 3 as rbrp_id with options tau_b, fixed_rank and w_refine
- * (greedy selection and the BF16 form are not provided here); the Philox
+ * (greedy selection, the BF16 form and the truncated-SVD W are not provided
+ * here: RBRP_E_UNSUPPORTED); the Philox
  * counter of ID i is (j, t, i, 0), i = its index in ``descs``.  The deflation
  * products run in the input's precision on the vector ALUs; norms, basis and
  * W are FP64.  No host synchronisation, no allocation and no memset: the call

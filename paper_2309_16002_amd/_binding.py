@@ -38,6 +38,8 @@ class rbrp_options(ctypes.Structure):
         ("trim", ctypes.c_int32),
         ("replay_d", ctypes.c_void_p),
         ("replay_blocks", ctypes.c_int32),
+        ("w_method", ctypes.c_int32),
+        ("w_clip", ctypes.c_double),
     ]
 
 
@@ -58,7 +60,7 @@ class rbrp_stats(ctypes.Structure):
         ("blocks_native", ctypes.c_int32),
         ("deflate_bytes", ctypes.c_double),
         ("blocks_bf16_stored", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("w_rank", ctypes.c_int32),
         ("bprime", ctypes.c_int32 * 256),
     ]
 
@@ -189,8 +191,12 @@ def _check_matrix(X):
         raise ValueError("X must be a 2-D row-major tensor (unit column stride)")
 
 
+W_METHODS = {"substitution": 0, "svd": 1}
+
+
 def make_options(k_max=0, tau_b=None, fixed_rank=False, greedy=False, precision="native",
-                 theta=0.0, w_refine=-1, profile=False, trim=False, replay_d=None):
+                 theta=0.0, w_refine=-1, profile=False, trim=False, replay_d=None,
+                 w_method="substitution", w_clip=0.0):
     o = rbrp_options()
     lib().rbrp_default_options(ctypes.byref(o))
     o.tau_b = -1.0 if tau_b is None else float(tau_b)
@@ -202,6 +208,8 @@ def make_options(k_max=0, tau_b=None, fixed_rank=False, greedy=False, precision=
     o.w_refine = int(w_refine)
     o.profile = 2 if profile == "deflate" else int(bool(profile))
     o.trim = int(bool(trim))
+    o.w_method = W_METHODS[w_method]
+    o.w_clip = float(w_clip)
     if replay_d is not None:
         # test hook: [blocks, m] FP64 device tensor of the norms each block
         # samples from (the caller keeps it alive for the call)
@@ -228,6 +236,7 @@ class IDResult:
     err_bound: float = 0.0       # bound on the rounding in the tracked residual
     blocks_native: int = 0       # BF16 form: blocks deflated with the FP32 product
     blocks_bf16_stored: int = 0  # BF16 form: blocks whose residual was stored in BF16
+    w_rank: int = 0              # singular values of L_1 kept (w_method="svd"), else k
 
 
 def workspace_size(m, n, b, dtype="f32", **opts):
@@ -283,7 +292,7 @@ def rbrp_id(X, eps, b, seed=0, *, want_w=True, workspace=None, out_S=None, out_W
     return IDResult(S[:kk], kk, W[:, :kk] if W is not None else None, status, st.blocks,
                     st.blocks_split, [int(x) for x in st.bprime[:nb]], st.resid_tracked,
                     st.norm_x_fro, prof, st.err_bound, st.blocks_native,
-                    st.blocks_bf16_stored)
+                    st.blocks_bf16_stored, st.w_rank)
 
 
 DEFLATE_MODES = {"f64": 0, "f32": 1, "bf16x3": 2, "bf16": 3, "bf16_stored": 4}

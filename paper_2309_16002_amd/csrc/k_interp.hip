@@ -38,6 +38,13 @@ __global__ __launch_bounds__(256) void k_identity_rows(const int64_t* __restrict
   for (int64_t p = threadIdx.x; p < k; p += 256) W[row * ldw + p] = (p == j) ? 1.0 : 0.0;
 }
 
+hipError_t launch_identity_rows(const int64_t* S, int64_t k, double* W, int64_t ldw,
+                                hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_identity_rows, dim3((unsigned)k), dim3(256), 0, s, S, k, W, ldw);
+  return hipGetLastError();
+}
+
 size_t interp_workspace_doubles(int64_t m, int64_t k, int refine) {
   // L1 and Bt (k x k each); with refinement a 64-column scratch per row
   return (size_t)(2 * k * k + (refine > 0 ? round_up(m, 128) * 64 : 0));

@@ -39,6 +39,7 @@ struct Plan {
   bool bf16;
   bool r_f64;
   int32_t refine;    // refinement steps of the W solve
+  bool w_pinv;       // W through the truncated-SVD pseudo-inverse of L_1
 };
 
 struct Work {
@@ -107,6 +108,9 @@ bool make_plan(rbrp_dtype dt, int64_t m, int64_t n, int32_t b, const rbrp_option
   p->r_f64 = dt == RBRP_F64;
   p->native_mode = p->r_f64 ? kModeF64 : kModeF32;
   p->refine = o.w_refine < 0 ? 1 : o.w_refine;
+  if (o.w_method != 0 && o.w_method != 1) return false;
+  if (!(o.w_clip < 1.0)) return false;   // NaN or 1 and above: nothing could be kept
+  p->w_pinv = o.w_method == 1;
   p->ntiles = scan_num_tiles(m);
   const int64_t a = norms_num_partials(p->mr), c = deflate_num_partials(p->mr);
   p->nparts = a > c ? a : c;
@@ -145,7 +149,9 @@ size_t layout(const Plan& p, char* base, Work* w) {
   w->fragB1 = cv.take<char>(frag_bytes(mode, p.ldr, p.bdef));
   w->fragA2 = cv.take<char>(frag_bytes(mode, p.ldr, p.bdef));
   w->L = cv.take<char>((size_t)p.m * p.ldl * rs);
-  w->interp = cv.take<double>(interp_workspace_doubles(p.m, p.k_max, p.refine));
+  const size_t nint = p.w_pinv ? pinv_workspace_doubles(p.k_max)
+                               : interp_workspace_doubles(p.m, p.k_max, p.refine);
+  w->interp = cv.take<double>(nint);
   return cv.off + kAlign;
 }
 
@@ -626,9 +632,16 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
   *k_host = kS;
   st.resid_tracked = sqrt(fmax(sum_d, 0.0) / D0);
   st.err_bound = err_bound();
+  st.w_rank = (int32_t)kS;
   if (W && kS > 0) {
     prof.begin(4);
-    RBRP_HIP(launch_interp(w.L, p.r_f64, p.ldl, m, kS, S, W, ldw, refine, w.interp, s));
+    if (p.w_pinv) {
+      const double clip = o.w_clip > 0.0 ? o.w_clip : 1e-12;
+      RBRP_HIP(launch_interp_pinv(w.L, p.r_f64, p.ldl, m, kS, S, W, ldw, clip, w.interp,
+                                  &st.w_rank, s));
+    } else {
+      RBRP_HIP(launch_interp(w.L, p.r_f64, p.ldl, m, kS, S, W, ldw, refine, w.interp, s));
+    }
     prof.end();
   }
   RBRP_HIP(hipStreamSynchronize(s));
@@ -787,7 +800,8 @@ static rbrp_status batch_check(int32_t count, rbrp_dtype dtype, double eps,
   rbrp_default_options(o);
   if (opt) *o = *opt;
   if (!(o->tau_b <= 1.0)) return RBRP_E_INVALID;
-  if (o->greedy || o->precision != RBRP_PREC_NATIVE) return RBRP_E_UNSUPPORTED;
+  if (o->greedy || o->precision != RBRP_PREC_NATIVE || o->w_method != 0)
+    return RBRP_E_UNSUPPORTED;
   if (ws_bytes < rbrp::batch_workspace_size(dtype, shape)) return RBRP_E_WORKSPACE;
   if (rbrp::batch_lds_needed(dtype, shape) > 128 * 1024) return RBRP_E_UNSUPPORTED;
   return RBRP_OK;

@@ -231,6 +231,17 @@ hipError_t launch_interp(const void* L, int l_f64, int64_t ldl, int64_t m,
                          int64_t k, const int64_t* S, double* W, int64_t ldw,
                          int refine, double* ws, hipStream_t s);
 size_t interp_workspace_doubles(int64_t m, int64_t k, int refine);
+// W(S,:) = I (exact identity rows of the skeletons).
+hipError_t launch_identity_rows(const int64_t* S, int64_t k, double* W, int64_t ldw,
+                                hipStream_t s);
+// Interpolation matrix through the truncated-SVD pseudo-inverse of L_1
+// (Remark 5.2): singular values below clip * sigma_max dropped; kept_host
+// (host, written when the stream reaches it) the number kept.  Synchronises
+// the stream once per Jacobi sweep.
+hipError_t launch_interp_pinv(const void* L, int l_f64, int64_t ldl, int64_t m, int64_t k,
+                              const int64_t* S, double* W, int64_t ldw, double clip,
+                              double* ws, int32_t* kept_host, hipStream_t s);
+size_t pinv_workspace_doubles(int64_t k);
 
 // Deflation arithmetic modes.
 // Deflation modes: the products' arithmetic and, for BF16 products, the

@@ -183,8 +183,23 @@ def test_default_options_and_binding_mapping(L):
     buf = (ctypes.c_uint8 * 256)(*([0xAB] * 256))
     L.rbrp_default_options(ctypes.cast(buf, ctypes.POINTER(B.rbrp_options)))
     c_size = max(i for i in range(256) if buf[i] != 0xAB) + 1
-    assert c_size == ctypes.sizeof(B.rbrp_options) == 64
+    assert c_size == ctypes.sizeof(B.rbrp_options) == 72
     assert B.rbrp_options.replay_d.offset == 48 and B.rbrp_options.replay_blocks.offset == 56
+    assert B.rbrp_options.w_method.offset == 60 and B.rbrp_options.w_clip.offset == 64
+    assert o.w_method == 0 and o.w_clip == 0.0
+
+
+def test_w_method_validation(L):
+    # an unknown method or a clip of 1 or more is rejected by the size query
+    # and by rbrp_id before any device work
+    assert rb.workspace_size(1000, 100, 16, "f32", w_method="svd") > 0
+    for bad in (dict(w_method=2), dict(w_clip=1.0), dict(w_clip=float("nan"))):
+        o = B.make_options()
+        for key, val in bad.items():
+            setattr(o, key, val)
+        assert L.rbrp_workspace_size(0, 1000, 100, 16, ctypes.byref(o)) == 0
+        st, k = _call_id(L, opt=o)
+        assert st == B.RBRP_E_INVALID and k == -7
 
 
 def test_replay_hook_validation(L):
@@ -219,7 +234,7 @@ def test_rows_beyond_the_sampler_limit_are_rejected_before_device_work(L):
 def test_stats_layout():
     # blocks, blocks_split, resid_tracked, err_bound, norm_x_fro, five phase
     # times, deflate_flops, deflate_launches, blocks_native, deflate_bytes,
-    # blocks_bf16_stored, reserved, bprime[256]
+    # blocks_bf16_stored, w_rank, bprime[256]
     assert ctypes.sizeof(B.rbrp_stats) == 8 + 8 * 9 + 8 + 8 + 8 + 4 * 256
     assert B.rbrp_stats.err_bound.offset == 16
     assert B.rbrp_stats.deflate_bytes.offset == 88
