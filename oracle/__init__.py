@@ -17,6 +17,9 @@ adaptive interpolative decomposition", arXiv:2309.16002) in NumPy/FP64:
                   and the greedy (RBGP, Remark 4.3) selection variant.
 * ``srp``      -- Algorithm 1 (sequential random pivoting), used as an
                   independent special case (RBRP with b = 1).
+* ``sketchy``  -- sketchy pivoting with LU and partial pivoting on the sketch
+                  Y = X Omega (SkLUPP) and the oversampled sketchy
+                  interpolation matrix (OSID, Algorithm 4).
 * ``interp``   -- interpolation matrix: W = X X_S^+ (eq. stable_id),
                   Algorithm 3 (W from L), and Remark 5.2's truncated-SVD
                   pseudo-inverse of L_1.
@@ -40,9 +43,11 @@ from .rbrp import rbrp, RBRPResult
 from .srp import srp
 from .interp import w_lstsq, w_from_l, w_svd_pinv, relative_id_error
 from .trim import trim_rank, projection_error_sq
+from .sketchy import sketch, lupp_pivots, osid, sketchy_id
 
 __all__ = [
     "philox4x64_10", "philox_word0", "fixed_point_weights", "sample_block",
     "cpqr", "truncation_rank", "tails_from_r", "rbrp", "RBRPResult", "srp",
     "w_lstsq", "w_from_l", "w_svd_pinv", "relative_id_error", "trim_rank", "projection_error_sq",
+    "sketch", "lupp_pivots", "osid", "sketchy_id",
 ]

@@ -24,16 +24,20 @@ Workloads (the paper's n x d data matrix is written m x n here):
                       remark).
 * ``random_features`` cos(x Omega + c) for x from a GMM in R^64.
 * ``exact_rank``      a matrix of exact rank r.
+* ``gaussian_exp``    the Gaussian-exp matrix of section 6: Haar factors and a
+                      spectrum flat for 100 values, then 0.8^(i-100) floored
+                      at 1e-5.
 """
 
 from .generators import (
     haar, svd_matrix, geometric_spectrum, power_spectrum, adversarial_gmm,
     gmm_example41, example23, kernel_blocks, random_features, exact_rank,
-    config_matrix, CONFIGS,
+    gaussian_exp, gaussian_exp_spectrum, config_matrix, CONFIGS,
 )
 
 __all__ = [
     "haar", "svd_matrix", "geometric_spectrum", "power_spectrum",
     "adversarial_gmm", "gmm_example41", "example23", "kernel_blocks",
-    "random_features", "exact_rank", "config_matrix", "CONFIGS",
+    "random_features", "exact_rank", "gaussian_exp", "gaussian_exp_spectrum",
+    "config_matrix", "CONFIGS",
 ]

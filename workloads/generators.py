@@ -42,6 +42,21 @@ def svd_matrix(m, n, s, seed, dtype=np.float64):
     return np.ascontiguousarray(X.astype(dtype))
 
 
+def gaussian_exp_spectrum(r, flat=100, decay=0.8, floor=1e-5):
+    """s_i = 1 for i <= flat, max(decay^(i - flat), floor) after (i = 1..r)."""
+    i = np.arange(1, r + 1, dtype=np.float64)
+    return np.where(i <= flat, 1.0, np.maximum(decay ** (i - flat), floor))
+
+
+def gaussian_exp(m=1000, n=1000, seed=1006, dtype=np.float64, flat=100, decay=0.8,
+                 floor=1e-5):
+    """The Gaussian-exp matrix of the paper's experiments (section 6): Haar U,
+    V and an exponentially decaying spectrum, flat for the first ``flat``
+    values and floored at ``floor``; 1000 x 1000 in the paper."""
+    r = min(m, n)
+    return svd_matrix(m, n, gaussian_exp_spectrum(r, flat, decay, floor), seed, dtype)
+
+
 def exact_rank(m, n, r, seed, dtype=np.float64, decay=0.9):
     """A matrix of exact rank r (Haar factors, s_i = decay^i)."""
     return svd_matrix(m, n, geometric_spectrum(r, decay), seed, dtype)
