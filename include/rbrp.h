@@ -294,6 +294,37 @@ rbrp_status rbrp_block_cpqr(const double* Vt, int64_t n, int32_t nb,
                             size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Sketchy pivoting with LU and partial pivoting (SkLUPP) and the oversampled
+ * sketchy interpolation matrix (OSID, Algorithm 4): the fixed-rank
+ * comparison method of section 3 ("sketchy pivoting") and section 5.
+ *
+ *   Y = X Omega                (m x l, FP64; X in its own type)
+ *   S = the first k pivot rows of Gaussian elimination with partial pivoting
+ *       on Y(:, 0:k) (the active row with the largest |entry| of the current
+ *       column, ties to the lowest row; a column with no nonzero active entry
+ *       pivots on its lowest active row and eliminates nothing)
+ *   W = Y Y(S,:)^+ by Alg. 4: Y(S,:)^T = Q R (Householder), W = (Y Q) R^{-T},
+ *       W(S,:) = I            (only when W is not NULL)
+ *
+ * X      [m x n] row-major, ld ldx, F32 or F64; read only.  m <= 4096 * 2048.
+ * k, l   1 <= k <= min(m, l), l <= 65536 (l = 3k is the paper's choice).
+ * Omega  device, FP64 [n x l] row-major, ld ldo >= l: the embedding (the
+ *        paper draws it Gaussian; the caller supplies it).
+ * S      device int64 [k]: skeleton rows in pivot order.
+ * W      device FP64 [m x ldw], ldw >= k, or NULL (skeletons only).
+ * Y(S,:) must have full rank k for W (a zero diagonal of R gives
+ * non-finite W).  Validation as for rbrp_id; stream-ordered, no host
+ * synchronisation.
+ * ------------------------------------------------------------------------ */
+size_t rbrp_sketchy_workspace_size(rbrp_dtype dtype, int64_t m, int64_t n,
+                                   int32_t k, int32_t l);
+rbrp_status rbrp_sketchy_id(const void* X, rbrp_dtype dtype, int64_t m,
+                            int64_t n, int64_t ldx, int32_t k, int32_t l,
+                            const double* Omega, int64_t ldo, int64_t* S,
+                            double* W, int64_t ldw, void* workspace,
+                            size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched form: many independent IDs (for instance the off-diagonal blocks of
  * a hierarchical-matrix compression, the fast-direct-solver use the paper
  * motivates in section 6) in one persistent launch.  Each ID runs the same

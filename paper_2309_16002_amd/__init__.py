@@ -9,5 +9,5 @@ The computation runs in the HIP library ``lib/librbrp.so`` (C ABI in
 from ._binding import (  # noqa: F401
     LIB_PATH, BatchPlan, IDResult, RBRPError, batch_autotune, block_cpqr, err_bound_increment,
     lib, rbrp_id, rbrp_id_batched, rbrp_id_batched_noalloc, row_norms, sample_block,
-    status_string, workspace_size,
+    sketchy_id, status_string, workspace_size,
 )

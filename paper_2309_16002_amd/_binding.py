@@ -120,6 +120,9 @@ SIGNATURES = {
     "rbrp_block_cpqr_workspace_size": (_sz, [_i64, _i32]),
     "rbrp_block_cpqr": (_c.c_int, [_vp, _i64, _i32, _i64, _dbl, _vp, _vp, _vp, _i64,
                                    _c.POINTER(_i32), _vp, _sz, _vp]),
+    "rbrp_sketchy_workspace_size": (_sz, [_c.c_int, _i64, _i64, _i32, _i32]),
+    "rbrp_sketchy_id": (_c.c_int, [_vp, _c.c_int, _i64, _i64, _i64, _i32, _i32, _vp, _i64,
+                                   _vp, _vp, _i64, _vp, _sz, _vp]),
     "rbrp_batch_workspace_size": (_sz, [_c.c_int, _c.POINTER(rbrp_batch_shape)]),
     "rbrp_id_batched": (_c.c_int, [_vp, _vp, _i32, _c.c_int, _dbl, _u64,
                                    _c.POINTER(rbrp_options), _c.POINTER(rbrp_batch_shape),
@@ -296,6 +299,35 @@ def rbrp_id(X, eps, b, seed=0, *, want_w=True, workspace=None, out_S=None, out_W
 
 
 DEFLATE_MODES = {"f64": 0, "f32": 1, "bf16x3": 2, "bf16": 3, "bf16_stored": 4}
+
+
+def sketchy_id(X, Omega, k, *, want_w=True, workspace=None):
+    """Sketchy pivoting (LU with partial pivoting on Y = X Omega) and the
+    oversampled sketchy interpolation matrix (Algorithm 4).  Omega: FP64
+    [n, l] GPU tensor (the caller's embedding).  Returns (S [k] int64, W
+    [m, k] float64 or None)."""
+    torch = _torch()
+    _check_matrix(X)
+    L = lib()
+    m, n = X.shape
+    if (Omega.dtype != torch.float64 or not Omega.is_cuda or Omega.dim() != 2
+            or Omega.shape[0] != n or Omega.stride(1) != 1):
+        raise ValueError("Omega must be a row-major float64 [n, l] GPU tensor")
+    l = Omega.shape[1]
+    dt = _dtype_code(X)
+    ws_bytes = L.rbrp_sketchy_workspace_size(dt, m, n, int(k), int(l))
+    if ws_bytes == 0:
+        raise RBRPError(RBRP_E_INVALID, "rbrp_sketchy_workspace_size")
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=X.device)
+    S = torch.empty(int(k), dtype=torch.int64, device=X.device)
+    W = torch.empty((m, int(k)), dtype=torch.float64, device=X.device) if want_w else None
+    status = L.rbrp_sketchy_id(_ptr(X), dt, m, n, _ld(X), int(k), int(l), _ptr(Omega),
+                               _ld(Omega), _ptr(S), _ptr(W), int(k), _ptr(workspace), ws_bytes,
+                               _stream_ptr(X.device))
+    if status != RBRP_OK:
+        raise RBRPError(status, "rbrp_sketchy_id")
+    return S, W
 
 
 def err_bound_increment(mode, bprime, r_prev_sq, r_new_sq):

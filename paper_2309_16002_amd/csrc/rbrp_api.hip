@@ -822,6 +822,34 @@ rbrp_status rbrp_id_batched(const rbrp_batch_desc* descs, const int32_t* order,
   return RBRP_OK;
 }
 
+// ---- sketchy pivoting and the oversampled sketchy ID ----
+
+static bool sketchy_args_ok(rbrp_dtype dtype, int64_t m, int64_t n, int32_t k, int32_t l) {
+  if (dtype != RBRP_F32 && dtype != RBRP_F64) return false;
+  if (m < 1 || n < 1 || m > kMaxRows || l < 1 || l > 65536) return false;
+  return k >= 1 && k <= l && (int64_t)k <= m;
+}
+
+size_t rbrp_sketchy_workspace_size(rbrp_dtype dtype, int64_t m, int64_t n, int32_t k,
+                                   int32_t l) {
+  if (!sketchy_args_ok(dtype, m, n, k, l)) return 0;
+  return rbrp::sketchy_workspace_bytes(m, k, l);
+}
+
+rbrp_status rbrp_sketchy_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64_t ldx,
+                            int32_t k, int32_t l, const double* Omega, int64_t ldo,
+                            int64_t* S, double* W, int64_t ldw, void* workspace,
+                            size_t ws_bytes, void* stream) {
+  if (!X || !Omega || !S || !workspace) return RBRP_E_INVALID;
+  if (!sketchy_args_ok(dtype, m, n, k, l) || ldx < n || ldo < l) return RBRP_E_INVALID;
+  if (W && ldw < k) return RBRP_E_INVALID;
+  if (ws_bytes < rbrp::sketchy_workspace_bytes(m, k, l)) return RBRP_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  RBRP_HIP(rbrp::launch_sketchy(X, dtype == RBRP_F32 ? 1 : 0, m, n, ldx, k, l, Omega, ldo, S, W,
+                                ldw, workspace, s));
+  return RBRP_OK;
+}
+
 // ---- batched form on a static scratch array (no allocation) ----
 //
 // The array lives in the library's code object: each GPU that loads the

@@ -243,6 +243,13 @@ hipError_t launch_interp_pinv(const void* L, int l_f64, int64_t ldl, int64_t m, 
                               double* ws, int32_t* kept_host, hipStream_t s);
 size_t pinv_workspace_doubles(int64_t k);
 
+// Sketchy pivoting (LU with partial pivoting on Y = X Omega) and the
+// oversampled sketchy interpolation matrix (k_sketchy.hip).
+size_t sketchy_workspace_bytes(int64_t m, int64_t k, int64_t l);
+hipError_t launch_sketchy(const void* X, int x_f32, int64_t m, int64_t n, int64_t ldx,
+                          int64_t k, int64_t l, const double* Omega, int64_t ldo, int64_t* S,
+                          double* W, int64_t ldw, void* ws, hipStream_t s);
+
 // Deflation arithmetic modes.
 // Deflation modes: the products' arithmetic and, for BF16 products, the
 // residual's storage (W: FP32 in, BF16 out; R: BF16 in and out).

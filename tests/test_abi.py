@@ -239,3 +239,24 @@ def test_stats_layout():
     assert B.rbrp_stats.err_bound.offset == 16
     assert B.rbrp_stats.deflate_bytes.offset == 88
     assert B.rbrp_stats.bprime.offset == 104
+
+
+def test_sketchy_validation(L):
+    """rbrp_sketchy_id: sizes and pointers checked before any device work."""
+    assert L.rbrp_sketchy_workspace_size(0, 1000, 200, 50, 150) > 0
+    for args in [(0, 1000, 200, 0, 150), (0, 1000, 200, 151, 150), (0, 40, 200, 50, 150),
+                 (7, 1000, 200, 50, 150), (0, 1000, 200, 50, 70000), (0, 0, 200, 1, 3)]:
+        assert L.rbrp_sketchy_workspace_size(*args) == 0, args
+    ws = 1 << 40
+    def call(X=1, k=50, l=150, Om=1, ldo=150, S=1, W=0, ldw=50, ldx=200):
+        return L.rbrp_sketchy_id(ctypes.c_void_p(X) if X else None, 0, 1000, 200, ldx, k, l,
+                                 ctypes.c_void_p(Om) if Om else None, ldo,
+                                 ctypes.c_void_p(S) if S else None,
+                                 ctypes.c_void_p(W) if W else None, ldw,
+                                 ctypes.c_void_p(1), ws, None)
+    for kw in (dict(X=0), dict(Om=0), dict(S=0), dict(ldo=149), dict(ldx=199),
+               dict(W=1, ldw=49), dict(k=151)):
+        assert call(**kw) == B.RBRP_E_INVALID, kw
+    assert L.rbrp_sketchy_id(ctypes.c_void_p(1), 0, 1000, 200, 200, 50, 150, ctypes.c_void_p(1),
+                             150, ctypes.c_void_p(1), None, 50, ctypes.c_void_p(1), 16,
+                             None) == B.RBRP_E_WORKSPACE
