@@ -224,6 +224,69 @@ def bench_batched(args, cfg):
     print(json.dumps(line), flush=True)
 
 
+def bench_sketchy(args, cfg, X):
+    """Sketchy pivoting (LU with partial pivoting on Y = X Omega) and the
+    oversampled sketchy ID (Algorithm 4) at a fixed rank k, l = 3k: the
+    comparison method of the paper's Table 3.  A step is one rbrp_sketchy_id
+    call; Omega is drawn once (Gaussian, seeded) and stays resident."""
+    import numpy as np
+    import torch
+    import paper_2309_16002_amd as rb
+    dev = torch.device("cuda:0")
+    m, n = X.shape
+    k = args.sketchy
+    l = args.sketch_l or 3 * k
+    Xg = torch.from_numpy(X).to(dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    Omega = torch.randn((n, l), dtype=torch.float64, device=dev, generator=gen)
+    for _ in range(args.warmup):
+        S, W = rb.sketchy_id(Xg, Omega, k)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[2 * i].record()
+        S, W = rb.sketchy_id(Xg, Omega, k)
+        ev[2 * i + 1].record()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ms_call = statistics.mean(ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(args.steps))
+    X64 = Xg.double()
+    err = float(torch.linalg.norm(X64 - W @ X64[S]) / torch.linalg.norm(X64))
+    # executed FP64 flops: the sketch 2 m n l, the elimination about m k^2,
+    # the OSID product 2 m l k (the QR of the l x k skeleton sketch is small)
+    flops = 2.0 * m * n * l + 1.0 * m * k * k + 2.0 * m * l * k
+    tfl = flops / (ms_call * 1e-3) / 1e12
+    line = {
+        "metric": METRIC, "value": m * args.steps / total, "unit": "rows/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * total / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "m": m, "n": n, "method": "SkLUPP-OSID",
+                   "k": k, "l": l, "parallelism": "single-gpu"},
+        "roofline": {"bound": "mfma", "achieved": round(tfl, 3), "peak": PEAK_TFLOPS["f64"],
+                     "unit": "TFLOP/s", "frac": round(tfl / PEAK_TFLOPS["f64"], 4),
+                     "traffic": None,
+                     "kernel": "whole rbrp_sketchy_id call (FP64 sketch, elimination, OSID)"},
+        "rel_error_last_step": err,
+    }
+    if not args.no_cpu_baseline:
+        from oracle.sketchy import sketchy_id as oracle_sketchy
+        Om = Omega.cpu().numpy()
+        X64h = np.asarray(X, dtype=np.float64)
+        times = []
+        while len(times) < args.cpu_repeats and sum(times) < args.cpu_budget:
+            t1 = time.perf_counter()
+            oracle_sketchy(X64h, Om, k)
+            times.append(time.perf_counter() - t1)
+        t = statistics.median(times)
+        line["cpu_baseline"] = {"value": m / t, "unit": "rows/s", "cores": os.cpu_count(),
+                                "kind": "oracle",
+                                "sample": f"full workload, {len(times)} runs, median {t:.3f} s"}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,6 +308,14 @@ def main():
     ap.add_argument("--trim", action="store_true",
                     help="rank trimming: cut k to the shortest prefix of the selection "
                          "that meets eps (an option of rbrp_id; off in the default line)")
+    ap.add_argument("--fixed-rank", type=int, default=0, metavar="K",
+                    help="run to exactly K skeletons (Alg. 2's 'or k' rule; the protocol of the "
+                         "paper's Table 3) instead of to eps")
+    ap.add_argument("--sketchy", type=int, default=0, metavar="K",
+                    help="time sketchy pivoting with LU + the oversampled sketchy ID (Alg. 4) "
+                         "at rank K instead of RBRP")
+    ap.add_argument("--sketch-l", type=int, default=0, metavar="L",
+                    help="sketch size for --sketchy (default 3K)")
     ap.add_argument("--w-method", default="substitution", choices=["substitution", "svd"],
                     help="interpolation matrix: blocked substitution with one refinement "
                          "step (Alg. 3, the default) or the truncated-SVD pseudo-inverse of "
@@ -282,6 +353,13 @@ def main():
         cfg["b"] = args.block
     if args.workload == "kernel_blocks_batched":
         bench_batched(args, cfg)
+        return
+    if args.fixed_rank:
+        cfg["k_max"] = args.fixed_rank
+        cfg["fixed_rank"] = True
+    if args.sketchy:
+        print(f"[bench] generating {args.workload}", file=sys.stderr, flush=True)
+        bench_sketchy(args, cfg, make_input(args.workload))
         return
     dev = torch.device("cuda:0")
     print(f"[bench] generating {args.workload}", file=sys.stderr, flush=True)
