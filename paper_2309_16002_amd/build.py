@@ -3,6 +3,7 @@ an object with hipcc, then linked into lib/librbrp.so (in-tree)."""
 
 import concurrent.futures
 import os
+import re
 import subprocess
 import sys
 
@@ -30,12 +31,38 @@ def _hipcc():
     return "hipcc"
 
 
+# Kernels whose register allocation is checked after compilation: the FP32
+# deflation at one wave per SIMD (512 registers) must not spill (a build of
+# it with spilled registers was measured to give wrong residuals).
+NO_SPILL = {"k_deflate.hip": re.compile(r"_ZN4rbrp9k_deflateILi1ELi2ELi32ELi\d+ELi4ELi2ELi0ELi1EEE")}
+
+
+def _check_no_spill(src, remarks, pattern):
+    name, seen = None, 0
+    for line in remarks.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            continue
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and name and pattern.match(name):
+            seen += 1
+            if int(m.group(1)) != 0:
+                raise RuntimeError(f"{src}: {name} spills {m.group(1)} bytes per lane")
+    if seen == 0:
+        raise RuntimeError(f"{src}: no kernel matched the register check {pattern.pattern}")
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
-    cmd = [_hipcc(), *FLAGS, "-c", src, "-o", obj]
+    check = NO_SPILL.get(os.path.basename(src))
+    extra = ["-Rpass-analysis=kernel-resource-usage"] if check else []
+    cmd = [_hipcc(), *FLAGS, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
+    if check:
+        _check_no_spill(src, r.stderr, check)
     return obj
 
 
