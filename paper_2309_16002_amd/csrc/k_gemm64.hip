@@ -752,36 +752,85 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 // block by block in substitution order.  R and T live in Tws (TB_M x 64 per
 // strip: rows of the strip only); Bt holds D_J^{-1} on its diagonal blocks;
 // L_1 is lower triangular (zero above the diagonal).
+// The right side L may alias W (its columns then hold the right sides of
+// a sub-solve): block J's right side is read by the first tile, before the
+// barrier after which the block is overwritten.  L_1 and Bt have leading
+// dimension ldt (>= K: the sub-solve of a diagonal block of a larger L_1).
 template <typename TL, bool VA, int TB_K, int WPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_trsm_refine(
-    int64_t M, int64_t K, const TL* __restrict__ L, int64_t ldl, const double* __restrict__ L1,
-    const double* __restrict__ Bt, double* W, int64_t ldw, double* __restrict__ Tws) {
+    int64_t M, int64_t K, const TL* L, int64_t ldl, const double* __restrict__ L1,
+    const double* __restrict__ Bt, int64_t ldt, double* W, int64_t ldw,
+    double* __restrict__ Tws) {
   constexpr int TBJ = 64;
   __shared__ double As[2][TB_K][TA_LD];
   __shared__ double Bs[2][TB_K][TBJ + 16];
   const int64_t i0 = (int64_t)blockIdx.x * TB_M;
   for (int64_t J = ceil_div(K, (int64_t)TBJ) - 1; J >= 0; --J) {
     const int64_t j0 = TBJ * J, nb = min((int64_t)TBJ, K - j0);
-    const double* Dinv = Bt + j0 * K + j0;
-    const double* Dj = L1 + j0 * K + j0;
+    const double* Dinv = Bt + j0 * ldt + j0;
+    const double* Dj = L1 + j0 * ldt + j0;
     // R (no K steps for the last block: the tile is then L_2(:, J) itself)
-    tall_tile<double, VA, TL, TB_K, TBJ>(i0, j0, j0 + TBJ, M, K, K, -1.0, W, ldw, L1, K, 1.0,
+    tall_tile<double, VA, TL, TB_K, TBJ>(i0, j0, j0 + TBJ, M, K, K, -1.0, W, ldw, L1, ldt, 1.0,
                                          Tws, TBJ, L, ldl, As, Bs, (const double*)nullptr, 0,
                                          0, j0);
     __syncthreads();
-    tall_tile<double, true, double, TB_K, TBJ>(i0, 0, 0, M, nb, nb, 1.0, Tws, TBJ, Dinv, K,
+    tall_tile<double, true, double, TB_K, TBJ>(i0, 0, 0, M, nb, nb, 1.0, Tws, TBJ, Dinv, ldt,
                                                0.0, W + j0, ldw, (const double*)nullptr, 0,
                                                As, Bs, (const double*)nullptr, 0, 0, 0, 0);
     __syncthreads();
-    tall_tile<double, VA, double, TB_K, TBJ>(i0, 0, 0, M, nb, nb, -1.0, W + j0, ldw, Dj, K,
+    tall_tile<double, VA, double, TB_K, TBJ>(i0, 0, 0, M, nb, nb, -1.0, W + j0, ldw, Dj, ldt,
                                              1.0, Tws, TBJ, Tws, TBJ, As, Bs,
                                              (const double*)nullptr, 0, 0, 0, 0);
     __syncthreads();
-    tall_tile<double, true, double, TB_K, TBJ>(i0, 0, 0, M, nb, nb, 1.0, Tws, TBJ, Dinv, K,
+    tall_tile<double, true, double, TB_K, TBJ>(i0, 0, 0, M, nb, nb, 1.0, Tws, TBJ, Dinv, ldt,
                                                1.0, W + j0, ldw, W + j0, ldw, As, Bs,
                                                (const double*)nullptr, 0, 0, 0, 0);
     __syncthreads();
   }
+}
+
+// C = Cin - A B for tall A (M x K, FP64, row-major) and B (K x N): the
+// contribution of the later column blocks of W to the right sides of a
+// block of columns (the super-block update of the W solve).  One 128 x 64
+// tile per workgroup; the tiles of one 128-row strip run on the same XCD
+// (workgroups are dealt to the eight XCDs in turn), so the strip of A is
+// read from HBM once and from that XCD's L2 by its other tiles.
+template <typename TC, bool VA>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_gemm_tall(
+    int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* __restrict__ B,
+    int64_t ldb, const TC* __restrict__ Cin, int64_t ldcin, double* C, int64_t ldc,
+    int64_t ntn, int64_t nstrips) {
+  constexpr int TB_N = 64, TB_K = 8;
+  __shared__ double As[2][TB_K][TA_LD];
+  __shared__ double Bs[2][TB_K][TB_N + 16];
+  const int64_t b = blockIdx.x;
+  const int64_t xcd = b % 8, slot = b / 8;
+  const int64_t strip = (slot / ntn) * 8 + xcd, tile = slot % ntn;
+  if (strip >= nstrips) return;
+  tall_tile<double, VA, TC, TB_K, TB_N>(strip * TB_M, tile * TB_N, 0, M, N, K, -1.0, A, lda, B,
+                                        ldb, 1.0, C, ldc, Cin, ldcin, As, Bs,
+                                        (const double*)nullptr, 0, 0, 0, -1);
+}
+
+hipError_t launch_gemm_tall(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                            bool a_vec, const double* B, int64_t ldb, const void* Cin,
+                            int cin_f32, int64_t ldcin, double* C, int64_t ldc, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int64_t ntn = ceil_div(N, (int64_t)64), nstrips = ceil_div(M, (int64_t)TB_M);
+  // whole groups of eight strips per XCD round (surplus workgroups exit)
+  const int64_t nwg = ceil_div(nstrips, (int64_t)8) * 8 * ntn;
+  const bool vec = a_vec && (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (lda % 2 == 0);
+  const dim3 g((unsigned)nwg);
+#define RBRP_TALL(TCV, VAV)                                                                   \
+  hipLaunchKernelGGL((k_gemm_tall<TCV, VAV>), g, dim3(256), 0, s, M, N, K, A, lda, B, ldb,   \
+                     (const TCV*)Cin, ldcin, C, ldc, ntn, nstrips)
+  if (cin_f32) {
+    if (vec) RBRP_TALL(float, true); else RBRP_TALL(float, false);
+  } else {
+    if (vec) RBRP_TALL(double, true); else RBRP_TALL(double, false);
+  }
+#undef RBRP_TALL
+  return hipGetLastError();
 }
 
 template <typename TL, bool VA>
@@ -828,13 +877,13 @@ static int device_cus() {
 
 template <typename TL, bool VA>
 static void refine_typed(int64_t M, int64_t K, const TL* L, int64_t ldl, const double* L1,
-                         const double* Bt, double* W, int64_t ldw, double* Tws, int step,
-                         hipStream_t s) {
+                         const double* Bt, int64_t ldt, double* W, int64_t ldw, double* Tws,
+                         int step, hipStream_t s) {
   const int64_t strips = ceil_div(M, TB_M);
   const dim3 g((unsigned)strips);
   if (step) {
     hipLaunchKernelGGL((k_trsm_refine_step<TL, VA, 8, 3>), g, dim3(256), 0, s, M, K, L, ldl, L1,
-                       Bt, W, ldw, Tws);
+                       Bt, W, ldw, Tws);   // whole solve: ldt = K
     return;
   }
   // Every strip is one long dependent chain of tiles, so each round of
@@ -846,24 +895,29 @@ static void refine_typed(int64_t M, int64_t K, const TL* L, int64_t ldl, const d
   const int64_t r3 = ceil_div(strips, 3 * cus), r4 = ceil_div(strips, 4 * cus);
   if (109 * r4 < 100 * r3)
     hipLaunchKernelGGL((k_trsm_refine<TL, VA, 8, 4>), g, dim3(256), 0, s, M, K, L, ldl, L1, Bt,
-                       W, ldw, Tws);
+                       ldt, W, ldw, Tws);
   else
     hipLaunchKernelGGL((k_trsm_refine<TL, VA, 8, 3>), g, dim3(256), 0, s, M, K, L, ldl, L1, Bt,
-                       W, ldw, Tws);
+                       ldt, W, ldw, Tws);
 }
 
 hipError_t launch_trsm_refine(int64_t M, int64_t K, const void* L, int l_f32, int64_t ldl,
-                              const double* L1, const double* Bt, double* W, int64_t ldw,
-                              double* Tws, int step, hipStream_t s) {
+                              const double* L1, const double* Bt, int64_t ldt, double* W,
+                              int64_t ldw, int64_t col_off, double* Tws, int step,
+                              hipStream_t s) {
   if (M <= 0 || K <= 0) return hipSuccess;
+  if (step && ldt != K) return hipErrorInvalidValue;   // a further step runs on the whole W
+  // vector loads of W's rows: the row (from W's column col_off of the
+  // caller's matrix) must extend to whole K steps
   const int64_t kr = round_up(K, (int64_t)8);
-  const bool vec = (reinterpret_cast<uintptr_t>(W) % 16 == 0) && (ldw % 2 == 0) && ldw >= kr;
+  const bool vec = (reinterpret_cast<uintptr_t>(W) % 16 == 0) && (ldw % 2 == 0) &&
+                   ldw >= col_off + kr;
   if (l_f32) {
-    if (vec) refine_typed<float, true>(M, K, (const float*)L, ldl, L1, Bt, W, ldw, Tws, step, s);
-    else refine_typed<float, false>(M, K, (const float*)L, ldl, L1, Bt, W, ldw, Tws, step, s);
+    if (vec) refine_typed<float, true>(M, K, (const float*)L, ldl, L1, Bt, ldt, W, ldw, Tws, step, s);
+    else refine_typed<float, false>(M, K, (const float*)L, ldl, L1, Bt, ldt, W, ldw, Tws, step, s);
   } else {
-    if (vec) refine_typed<double, true>(M, K, (const double*)L, ldl, L1, Bt, W, ldw, Tws, step, s);
-    else refine_typed<double, false>(M, K, (const double*)L, ldl, L1, Bt, W, ldw, Tws, step, s);
+    if (vec) refine_typed<double, true>(M, K, (const double*)L, ldl, L1, Bt, ldt, W, ldw, Tws, step, s);
+    else refine_typed<double, false>(M, K, (const double*)L, ldl, L1, Bt, ldt, W, ldw, Tws, step, s);
   }
   return hipGetLastError();
 }

@@ -16,9 +16,12 @@
 //   4. W(S(j),:) = e_j exactly.
 #include "rbrp_internal.h"
 
+#include <algorithm>
+
 namespace rbrp {
 
 constexpr int kDiag = 64;
+constexpr int64_t kSuper = 256;   // columns of a super-block of the W solve
 
 template <typename TL>
 __global__ __launch_bounds__(256) void k_gather_l1(const TL* __restrict__ L, int64_t ldl,
@@ -67,22 +70,45 @@ hipError_t launch_interp(const void* L, int l_f64, int64_t ldl, int64_t m, int64
   const int64_t nblk = ceil_div(k, kDiag);
   e = launch_lower_diag_inv(L1, k, k, kDiag, Bt, k, s);
   if (e != hipSuccess) return e;
-  // Bt(I, J) = -L_1(I, J) D_J^{-1} for the block rows I > J
-  for (int64_t J = 0; J + 1 < nblk; ++J) {
-    const int64_t j0 = J * kDiag, j1 = j0 + kDiag;
-    e = launch_gemm_f64(0, 0, k - j1, kDiag, kDiag, -1.0, L1 + j1 * k + j0, 0, k,
-                        Bt + j0 * k + j0, k, 0.0, Bt + j1 * k + j0, k, nullptr, nullptr, 0, s);
-    if (e != hipSuccess) return e;
-  }
   const int lf32 = l_f64 ? 0 : 1;
   if (refine <= 0) {
+    // Bt(I, J) = -L_1(I, J) D_J^{-1} for the block rows I > J
+    for (int64_t J = 0; J + 1 < nblk; ++J) {
+      const int64_t j0 = J * kDiag, j1 = j0 + kDiag;
+      e = launch_gemm_f64(0, 0, k - j1, kDiag, kDiag, -1.0, L1 + j1 * k + j0, 0, k,
+                          Bt + j0 * k + j0, k, 0.0, Bt + j1 * k + j0, k, nullptr, nullptr, 0, s);
+      if (e != hipSuccess) return e;
+    }
     e = launch_trsm_tall(m, k, L, lf32, ldl, Bt, W, ldw, s);
   } else {
-    // substitution with the first refinement step in the same pass, then
-    // any further steps on the result
-    e = launch_trsm_refine(m, k, L, lf32, ldl, L1, Bt, W, ldw, Tws, 0, s);
+    // Substitution with the first refinement step in the same pass, by
+    // super-blocks of kSuper columns from the last to the first: the later
+    // super-blocks' contribution to a super-block's right sides is one tall
+    // GEMM into W's own columns, R_s = L_2(:, s) - W(:, >s) L_1(>s, s), and
+    // the super-block is then solved strip by strip from R_s as before.
+    // Each strip re-reads its finished 64-column blocks only within its
+    // super-block, instead of across all of W.  Further refinement steps
+    // run on the whole result.
+    const bool a_vec = ldw >= round_up(k, (int64_t)8);
+    for (int64_t a = (ceil_div(k, kSuper) - 1) * kSuper; a >= 0 && e == hipSuccess; a -= kSuper) {
+      const int64_t nbk = std::min<int64_t>(kSuper, k - a);
+      if (a + nbk < k) {
+        e = launch_gemm_tall(m, nbk, k - a - nbk, W + a + nbk, ldw, a_vec, L1 + (a + nbk) * k + a,
+                             k, l_f64 ? (const void*)((const double*)L + a)
+                                      : (const void*)((const float*)L + a),
+                             lf32, ldl, W + a, ldw, s);
+        if (e != hipSuccess) return e;
+        e = launch_trsm_refine(m, nbk, W + a, 0, ldw, L1 + a * k + a, Bt + a * k + a, k, W + a,
+                               ldw, a, Tws, 0, s);
+      } else {
+        e = launch_trsm_refine(m, nbk, l_f64 ? (const void*)((const double*)L + a)
+                                             : (const void*)((const float*)L + a),
+                               lf32, ldl, L1 + a * k + a, Bt + a * k + a, k, W + a, ldw, a, Tws,
+                               0, s);
+      }
+    }
     for (int it = 1; it < refine && e == hipSuccess; ++it)
-      e = launch_trsm_refine(m, k, L, lf32, ldl, L1, Bt, W, ldw, Tws, 1, s);
+      e = launch_trsm_refine(m, k, L, lf32, ldl, L1, Bt, k, W, ldw, 0, Tws, 1, s);
   }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_identity_rows, dim3((unsigned)k), dim3(256), 0, s, S, k, W, ldw);

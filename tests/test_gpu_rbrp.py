@@ -128,6 +128,23 @@ def test_fp64_w_solve_block_boundaries(rb, k):
     assert np.array_equal(W[S], np.eye(k))
 
 
+@pytest.mark.parametrize("k", [256, 257, 320, 513, 259])
+def test_fp64_w_solve_super_blocks(rb, k):
+    """Fixed rank k around the 256-column super-blocks of the solve (one
+    whole super-block; one plus one column; a ragged second; three; an odd
+    k = k_max = 259, whose rows of W are loaded element by element): the later
+    super-blocks' contribution goes through the tall GEMM into W's columns,
+    and W still matches X X_S^+ with W(S,:) = I."""
+    X = svd_matrix(2500, 600, geometric_spectrum(600, 0.99), seed=81)
+    res = _run(rb, X, 1e-12, 32, 5, k_max=k, fixed_rank=True)
+    assert res.k == k
+    S = res.S.cpu().tolist()
+    W = res.W.cpu().numpy()
+    Wref = w_lstsq(X, S)
+    assert np.linalg.norm(W - Wref) <= 1e-10 * np.linalg.norm(Wref)
+    assert np.array_equal(W[S], np.eye(k))
+
+
 def test_fp64_w_solve_odd_leading_dimension(rb):
     """k = k_max = 131 (an odd leading dimension of W: the element-wise load
     path of the substitution) at fixed rank."""
