@@ -147,8 +147,9 @@ def bench_batched(args, cfg):
     t0 = time.perf_counter()
     bcls = rb.batch_autotune(plan, eps, 0)
     tune_s = time.perf_counter() - t0
-    print(f"[bench] autotuned b per class {bcls}, {plan.shape.num_wg} workgroups "
-          f"({tune_s:.1f} s)", file=sys.stderr, flush=True)
+    depth = [(plan.shape.row_depth >> (4 * c)) & 15 for c in range(3)]
+    print(f"[bench] autotuned b per class {bcls}, row-load depth per class {depth}, "
+          f"{plan.shape.num_wg} workgroups ({tune_s:.1f} s)", file=sys.stderr, flush=True)
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     g = torch.cuda.CUDAGraph()
@@ -188,6 +189,7 @@ def bench_batched(args, cfg):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "kernel_blocks_batched", "count": plan.count,
                    "rows_total": rows, "eps": eps, "b_per_class": bcls,
+                   "row_depth_per_class": depth,
                    "num_wg": plan.shape.num_wg, "launch": "one persistent kernel in a HIP graph",
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_GBS,
@@ -311,6 +313,9 @@ def main():
     ap.add_argument("--fixed-rank", type=int, default=0, metavar="K",
                     help="run to exactly K skeletons (Alg. 2's 'or k' rule; the protocol of the "
                          "paper's Table 3) instead of to eps")
+    ap.add_argument("--to-eps", action="store_true",
+                    help="run to the workload's eps with k_max = min(m, n) even where the "
+                         "workload is defined at a fixed rank (random_features_large)")
     ap.add_argument("--sketchy", type=int, default=0, metavar="K",
                     help="time sketchy pivoting with LU + the oversampled sketchy ID (Alg. 4) "
                          "at rank K instead of RBRP")
@@ -357,6 +362,9 @@ def main():
     if args.fixed_rank:
         cfg["k_max"] = args.fixed_rank
         cfg["fixed_rank"] = True
+    if args.to_eps:
+        cfg.pop("k_max", None)
+        cfg["fixed_rank"] = False
     if args.sketchy:
         print(f"[bench] generating {args.workload}", file=sys.stderr, flush=True)
         bench_sketchy(args, cfg, make_input(args.workload))

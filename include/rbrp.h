@@ -353,7 +353,10 @@ typedef struct {
   int32_t b_max;      /* largest b, <= 32                                      */
   int32_t k_cap_max;  /* largest k_cap, <= 256                                 */
   int32_t num_wg;     /* persistent workgroups; 0 -> 512 (two per CU)          */
-  int32_t reserved;
+  int32_t row_depth;  /* deflation: 8-value chunks of a row whose loads are
+                         issued together (1, 2 or 4) per size class, 4 bits
+                         each: bits 0-3 n <= 64, 4-7 n <= 128, 8-11 larger;
+                         a field of 0 -> 2 (rbrp_batch_autotune sets it)  */
 } rbrp_batch_shape;
 
 /* Workspace bytes of rbrp_id_batched for this shape (per-workgroup scratch
@@ -406,11 +409,12 @@ rbrp_status rbrp_id_batched_noalloc(const rbrp_batch_desc* descs,
  * Autotuner of the batched form.  descs_host [count] is the host copy of the
  * descriptors, descs [count] their device copy.  Size classes by n
  * (<= 64, <= 128, > 128); for each class the block sizes 8, 16 and 32
- * (<= shape->b_max) are timed on that class's IDs, then the number of
- * persistent workgroups (256, 512, 768, those the workspace fits).  On
- * return the device descriptors carry the chosen b, order [count] (device)
- * holds the largest-first queue order, shape->num_wg the chosen count and
- * b_class_host [3] the block size per class.  Synchronises the stream; runs
+ * (<= shape->b_max) are timed on that class's IDs, then, with that b, the
+ * deflation's row-load depths 1, 2 and 4; then the number of persistent
+ * workgroups (256, 512, 768, those the workspace fits).  On return the
+ * device descriptors carry the chosen b, order [count] (device) holds the
+ * largest-first queue order, shape->num_wg and shape->row_depth the chosen
+ * count and depths, and b_class_host [3] the block size per class.  Synchronises the stream; runs
  * the batch several times (outputs are overwritten).
  */
 rbrp_status rbrp_batch_autotune(const rbrp_batch_desc* descs_host,

@@ -86,7 +86,7 @@ class rbrp_batch_shape(ctypes.Structure):
         ("b_max", ctypes.c_int32),
         ("k_cap_max", ctypes.c_int32),
         ("num_wg", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("row_depth", ctypes.c_int32),
     ]
 
 

@@ -92,7 +92,7 @@ static BatchGeom batch_geom(rbrp_dtype dt, const rbrp_batch_shape& sh) {
 struct BatchParams {
   double eps, tau_b;
   uint64_t seed;
-  int32_t fixed_rank, refine, count, pad;
+  int32_t fixed_rank, refine, count, row_depth;
 };
 
 // Workgroup reduction of (sum, max) over one value per thread, fixed order.
@@ -225,7 +225,9 @@ __device__ __forceinline__ void lds_gram(const double* __restrict__ As, int na, 
 // P = R Q' (b' <= NBT values in registers), L(i, kS:kS+b') = P (zero on rows
 // of earlier skeletons), R <- R - P Q'^T, d_i = ||R_i||^2 (FP64), 0 on
 // skeletons.  QfT (LDS) is n8 x bq, zero outside b' columns and n rows.
-template <int NBT, typename T>
+// CIF: chunks of the row whose loads are issued together in the first pass
+// (the depth the autotuner chooses per size class).
+template <int NBT, typename T, int CIF>
 __device__ __forceinline__ void deflate_rows(T* __restrict__ RT, int64_t mpad, int64_t m,
                                              int64_t n8, const T* __restrict__ QfT,
                                              int64_t bq, T* __restrict__ L, int64_t ldl,
@@ -236,15 +238,15 @@ __device__ __forceinline__ void deflate_rows(T* __restrict__ RT, int64_t mpad, i
     T acc[NBT];
 #pragma unroll
     for (int j = 0; j < NBT; ++j) acc[j] = (T)0;
-    // two chunks of the row in flight per group (the loop is bound by the
-    // latency of its loads), then the remaining chunk
+    // CIF chunks of the row in flight per group (the loop is bound by the
+    // latency of its loads), then the remaining chunks one at a time
     int64_t c0 = 0;
-    for (; c0 + 2 * kChunk <= n8; c0 += 2 * kChunk) {
-      T r[2 * kChunk];
+    for (; c0 + CIF * kChunk <= n8; c0 += CIF * kChunk) {
+      T r[CIF * kChunk];
 #pragma unroll
-      for (int u = 0; u < 2 * kChunk; ++u) r[u] = RT[(c0 + u) * mpad + i];
+      for (int u = 0; u < CIF * kChunk; ++u) r[u] = RT[(c0 + u) * mpad + i];
 #pragma unroll
-      for (int u = 0; u < 2 * kChunk; ++u) {
+      for (int u = 0; u < CIF * kChunk; ++u) {
         const T* qc = QfT + (c0 + u) * bq;
 #pragma unroll
         for (int j = 0; j < NBT; ++j) acc[j] += r[u] * qc[j];
@@ -368,6 +370,11 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
     }
     const T* X = reinterpret_cast<const T*>(ds.X);
     const double tau_b = prm.tau_b < 0.0 ? 1.0 / b : prm.tau_b;
+    // the deflation's row-load depth of the ID's size class (n <= 64, <= 128,
+    // larger), 4-bit fields; 0 -> 2
+    const int cls = n <= 64 ? 0 : (n <= 128 ? 1 : 2);
+    int cif = (prm.row_depth >> (4 * cls)) & 15;
+    if (cif == 0) cif = 2;
     const double tau = prm.eps * prm.eps;
 
     // ---- initial norms, R^T <- X^T (zero columns n..n8), skeleton flags ----
@@ -534,14 +541,24 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
       __syncthreads();
       // ---- deflation: P = R Q', L(:, kS:kS+b') = P, R <- R - P Q'^T ----
       const int nbt = (bp + 7) & ~7;
+#define RBRP_DEFL(NBV)                                                                     \
+  do {                                                                                     \
+    if (cif == 1)                                                                          \
+      deflate_rows<NBV, T, 1>(RT, mpad, m, n8, QfT, bq, L, kcapw, kS, bp, sel, t, d);      \
+    else if (cif == 4)                                                                     \
+      deflate_rows<NBV, T, 4>(RT, mpad, m, n8, QfT, bq, L, kcapw, kS, bp, sel, t, d);      \
+    else                                                                                   \
+      deflate_rows<NBV, T, 2>(RT, mpad, m, n8, QfT, bq, L, kcapw, kS, bp, sel, t, d);      \
+  } while (0)
       if (nbt <= 8)
-        deflate_rows<8, T>(RT, mpad, m, n8, QfT, bq, L, kcapw, kS, bp, sel, t, d);
+        RBRP_DEFL(8);
       else if (nbt <= 16)
-        deflate_rows<16, T>(RT, mpad, m, n8, QfT, bq, L, kcapw, kS, bp, sel, t, d);
+        RBRP_DEFL(16);
       else if (nbt <= 24)
-        deflate_rows<24, T>(RT, mpad, m, n8, QfT, bq, L, kcapw, kS, bp, sel, t, d);
+        RBRP_DEFL(24);
       else
-        deflate_rows<32, T>(RT, mpad, m, n8, QfT, bq, L, kcapw, kS, bp, sel, t, d);
+        RBRP_DEFL(32);
+#undef RBRP_DEFL
       __syncthreads();
       kS += bp;
     }
@@ -722,8 +739,17 @@ int64_t batch_max_wg(rbrp_dtype dt, const rbrp_batch_shape* sh, size_t bytes) {
   return (int64_t)((bytes - 512) / (size_t)g.slice);
 }
 
+static bool row_depth_ok(int32_t code) {
+  if (code < 0 || code >= (1 << 12)) return false;
+  for (int c = 0; c < 3; ++c) {
+    const int v = (code >> (4 * c)) & 15;
+    if (v != 0 && v != 1 && v != 2 && v != 4) return false;
+  }
+  return true;
+}
+
 bool batch_shape_ok(const rbrp_batch_shape* sh) {
-  return sh && sh->m_max >= 1 && sh->m_max <= (int64_t)kBatchMaxTiles * kScanTile &&
+  return sh && row_depth_ok(sh->row_depth) && sh->m_max >= 1 && sh->m_max <= (int64_t)kBatchMaxTiles * kScanTile &&
          sh->n_max >= 1 && sh->n_max <= kBatchMaxN && sh->b_max >= 1 &&
          sh->b_max <= kBatchMaxB && sh->k_cap_max >= 1 && sh->k_cap_max <= kBatchMaxK &&
          sh->num_wg >= 0 && sh->num_wg <= 65536;
@@ -740,12 +766,12 @@ hipError_t launch_batched(const rbrp_batch_desc* descs, const int32_t* order, in
   char* scratch = ws + 256;
   BatchParams prm;
   prm.eps = eps;
+  prm.row_depth = sh.row_depth;
   prm.tau_b = o.tau_b;
   prm.seed = seed;
   prm.fixed_rank = o.fixed_rank;
   prm.refine = o.w_refine < 0 ? 1 : o.w_refine;
   prm.count = count;
-  prm.pad = 0;
   const size_t lds = batch_lds_bytes(dt, g);
   hipLaunchKernelGGL(k_batch_queue_reset, dim3(1), dim3(64), 0, s, queue);
   if (dt == RBRP_F64) {

@@ -993,6 +993,23 @@ rbrp_status rbrp_batch_autotune(const rbrp_batch_desc* descs_host, rbrp_batch_de
     }
     for (int32_t i : members) cur[i].b = best_b;
     b_class_host[c] = best_b;
+    // then the deflation's row-load depth of the class
+    const int32_t cand_depth[3] = {1, 2, 4};
+    best_ms = 1e30f;
+    int32_t best_depth = 2;
+    for (int32_t dep : cand_depth) {
+      if (st != RBRP_OK) break;
+      rbrp_batch_shape sh = *shape;
+      sh.row_depth = (sh.row_depth & ~(15 << (4 * c))) | (dep << (4 * c));
+      float ms = 0.f;
+      st = timed(members, sh, &ms);
+      if (st != RBRP_OK) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_depth = dep;
+      }
+    }
+    shape->row_depth = (shape->row_depth & ~(15 << (4 * c))) | (best_depth << (4 * c));
   }
   if (st == RBRP_OK) {
     const int32_t cand_wg[3] = {256, 512, 768};
