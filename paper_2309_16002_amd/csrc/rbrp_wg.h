@@ -475,6 +475,8 @@ constexpr int kPivKB = 16;   // pivot rows per delayed Schur-complement update
 constexpr int kPivLd = 18;   // row stride (doubles) of the transposed pivot rows
 constexpr int kPivThreads = 256;
 
+typedef double dmfma4 __attribute__((ext_vector_type(4)));
+
 template <int NBMAX>
 struct PivShared {
   alignas(16) double rblk[NBMAX][kPivLd];  // rblk[c][q]: entry c of pivot row q of the group
@@ -585,8 +587,12 @@ __device__ __forceinline__ void wg_piv_chol(
     if (wv == 0) {
       bool fin = false;
       int bp = 0;
+      // fully unrolled (qb a constant in each step): the steps after the
+      // last one are skipped rather than left by a break, which would keep
+      // the compiler from unrolling
 #pragma unroll
       for (int qb = 0; qb < kPivKB; ++qb) {
+        if (fin) continue;
         const int p = g * kPivKB + qb;
         // largest remaining diagonal entry (the wave maximum, then the lowest
         // column holding it: columns l + 64 j ascend with j, then with l)
@@ -648,7 +654,7 @@ __device__ __forceinline__ void wg_piv_chol(
         if (done) {
           bp = p;
           fin = true;
-          break;
+          continue;
         }
         const double r = sqrt(gv);
         const double rinv = 1.0 / r;
@@ -691,9 +697,38 @@ __device__ __forceinline__ void wg_piv_chol(
     }
     __syncthreads();
     if (sh.fin) break;
-    // delayed update of S by the group's pivot rows: thread (column c, part)
-    // takes rows part, part + TPC, ... (the same rows across a wave)
-    {
+    // delayed update of S by the group's pivot rows, S -= B B^T with
+    // B(c, q) = entry c of pivot row q.  In LDS for 64 or more columns: a
+    // rank-16 product on FP64 MFMA over 16 x 16 tiles of S, wave w taking
+    // tiles w, w + 4, ...; a tile is skipped when its rows or its columns
+    // are all chosen (entries of chosen rows and columns are never read
+    // again, so the others may be updated too).  Not needed after the group
+    // that reaches nb pivots.
+    if constexpr (!GS && NBMAX >= 64) {
+      if ((g + 1) * kPivKB < nb) {
+        const int nt = (nb + 15) >> 4;
+        const int l16 = lane & 15, lq = lane >> 4;
+        for (int tile = wv; tile < nt * nt; tile += kPivThreads / 64) {
+          const int ti = tile / nt, tj = tile - ti * nt;
+          const int ra = 16 * ti + l16, rb = 16 * tj + l16;
+          const bool rlive = ra < nb && !sh.chosen[ra];
+          const bool clive = rb < nb && !sh.chosen[rb];
+          if (__ballot(rlive) == 0ull || __ballot(clive) == 0ull) continue;
+          dmfma4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int s4 = 0; s4 < kPivKB / 4; ++s4)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sh.rblk[ra][4 * s4 + lq],
+                                                       sh.rblk[rb][4 * s4 + lq], acc, 0, 0, 0);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int i = 16 * ti + lq + 4 * q;
+            if (i < nb && rb < nb) S[(int64_t)i * ld + rb] -= acc[q];
+          }
+        }
+      }
+    } else {
+      // thread (column c, part) takes rows part, part + TPC, ... (the same
+      // rows across a wave)
       const int c = tid % NCOLS, part = tid / NCOLS;
       if (c < nb && !sh.chosen[c]) {
         double rc[kPivKB];
