@@ -2,13 +2,15 @@
 plain BRP (tau_b = 0: no robust filter, the paper's blockwise random
 pivoting), blockwise greedy pivoting (RBGP, Remark 4.3) with b > 1, and an
 explicit tau_b equal to the default 1/b.  FP64 inputs of full numerical rank
-per block: skeletons and b' identical, W within 1e-10 of least squares."""
+per block: skeletons and b' identical, W within 1e-10 of least squares;
+plain BRP on numerically rank-deficient blocks: the pivots up to the rank
+identical, both IDs exact to rounding."""
 
 import numpy as np
 import pytest
 
 from oracle import rbrp as oracle_rbrp, w_lstsq, relative_id_error
-from workloads import svd_matrix, geometric_spectrum, adversarial_gmm
+from workloads import svd_matrix, geometric_spectrum, adversarial_gmm, exact_rank
 
 pytestmark = pytest.mark.gpu
 
@@ -50,6 +52,34 @@ def test_plain_brp_matches_oracle(rb, m, n, b, eps, seed):
     _check(res, ref, X, eps)
     # no filter: every block but a final short one keeps all b rows
     assert all(bp == b for bp in res.bprime[:-1])
+
+
+@pytest.mark.parametrize("m,n,r,b,seed", [(2000, 300, 10, 16, 1), (2000, 300, 20, 32, 2),
+                                          (3000, 200, 40, 64, 3), (2000, 300, 10, 16, 4)])
+def test_plain_brp_rank_deficient_blocks(rb, m, n, r, b, seed):
+    """Plain BRP on a matrix of exact rank r < b, so the first block is
+    numerically rank-deficient.  The oracle's Householder CPQR keeps all b
+    columns (the last b - r on rounding noise); the GPU's pivoted Cholesky of
+    the Gram matrix keeps pivoting while the remaining diagonal is positive,
+    so it keeps the r columns and at most the few noise columns before the
+    first non-positive diagonal.  Both give an exact ID: the first r pivots
+    agree, W(S,:) = I and the error is at the rounding level."""
+    X = exact_rank(m, n, r, seed=700 + seed)
+    eps = 1e-8
+    ref = oracle_rbrp(X, eps, b, seed, tau_b=0.0)
+    res = _run(rb, X, eps, b, seed, tau_b=0.0)
+    assert res.status == 0
+    assert ref.k == b and len(res.bprime) == 1
+    S = res.S.cpu().tolist()
+    assert S[:r] == ref.S[:r]
+    assert r <= res.k <= b
+    W = res.W.cpu().numpy()
+    assert np.array_equal(W[S], np.eye(res.k))
+    e = relative_id_error(X, W, S)
+    print(f"  b'={res.k} (oracle {ref.k}), error {e:.2e}, max|W| {np.abs(W).max():.2e}",
+          flush=True)
+    assert e <= 1e-13
+    assert np.abs(W).max() <= 1e3
 
 
 @pytest.mark.parametrize("m,n,b,eps", [
