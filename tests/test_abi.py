@@ -114,9 +114,10 @@ def test_no_cpu_fallback_in_binding():
     assert "oracle" not in src and "numpy" not in src
 
 
-def _shape(m=1024, n=256, b=32, k=256, nwg=0):
+def _shape(m=1024, n=256, b=32, k=256, nwg=0, depth=0):
     sh = B.rbrp_batch_shape()
     sh.m_max, sh.n_max, sh.b_max, sh.k_cap_max, sh.num_wg = m, n, b, k, nwg
+    sh.row_depth = depth
     return sh
 
 
@@ -130,6 +131,11 @@ def test_batch_workspace_size_validates(L):
     assert L.rbrp_batch_workspace_size(0, ctypes.byref(_shape(m=16385))) == 0
     assert L.rbrp_batch_workspace_size(2, ctypes.byref(_shape())) == 0
     assert L.rbrp_batch_workspace_size(0, None) == 0
+    # row-load depth per size class: 4-bit fields of 0 (default), 1, 2 or 4
+    for ok in (0x000, 0x111, 0x224, 0x421, 0x040):
+        assert L.rbrp_batch_workspace_size(0, ctypes.byref(_shape(depth=ok))) > 0
+    for bad in (0x003, 0x500, 0x080, 0x1000, -1):
+        assert L.rbrp_batch_workspace_size(0, ctypes.byref(_shape(depth=bad))) == 0
     # scratch grows with the number of persistent workgroups
     assert (L.rbrp_batch_workspace_size(0, ctypes.byref(_shape(nwg=768)))
             > L.rbrp_batch_workspace_size(0, ctypes.byref(_shape(nwg=256))))
