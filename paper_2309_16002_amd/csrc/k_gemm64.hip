@@ -275,6 +275,103 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_nt16(int64_t M, int64_t N, int
   }
 }
 
+// The same product with 32 x 32 output blocks (four MFMA tiles) per
+// workgroup of NW waves: every A or B fragment a wave loads feeds two MFMA
+// tiles instead of one, which halves the operand traffic from L2 per flop.
+// Used when there are at least 128 such blocks (the projections against a
+// basis of a thousand rows and more, where the 16 x 16 form is bound by
+// that traffic; splitting their K into slices summed by the consumer was
+// measured slower, since the consumer then reads every slice).
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_gemm_nt32(int64_t M, int64_t N, int64_t K,
+                                                      double alpha,
+                                                      const double* __restrict__ A, int64_t lda,
+                                                      const double* __restrict__ B, int64_t ldb,
+                                                      double beta, double* __restrict__ C,
+                                                      int64_t ldc, const int32_t* m_dev,
+                                                      const int32_t* n_dev) {
+  __shared__ double part[NW][4][256];
+  if (m_dev) M = min(M, (int64_t)*m_dev);
+  if (n_dev) N = min(N, (int64_t)*n_dev);
+  const int64_t i0 = (int64_t)blockIdx.y * 32, j0 = (int64_t)blockIdx.x * 32;
+  if (i0 >= M || j0 >= N) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double* ap[2];
+  const double* bp[2];
+  bool va[2], vb[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t ia = i0 + 16 * h + (lane & 15), jb = j0 + 16 * h + (lane & 15);
+    va[h] = ia < M;
+    vb[h] = jb < N;
+    ap[h] = A + (va[h] ? ia : 0) * lda;
+    bp[h] = B + (vb[h] ? jb : 0) * ldb;
+  }
+  d4v acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = (d4v){0.0, 0.0, 0.0, 0.0};
+  // groups of two 16-wide chunks per wave, every load of a group before its
+  // MFMAs; chunk bases past K are clamped to the last chunk and masked
+  const int64_t kstep = 16 * NW;
+  const int64_t klast = K - 16;
+  const int koff = 4 * (lane >> 4);
+  for (int64_t k0 = 16 * w; k0 < K; k0 += 2 * kstep) {
+    d2v a[2][2][2], b[2][2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t kb = min(k0 + u * kstep, klast) + koff;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        a[u][h][0] = *reinterpret_cast<const d2v*>(ap[h] + kb);
+        a[u][h][1] = *reinterpret_cast<const d2v*>(ap[h] + kb + 2);
+        b[u][h][0] = *reinterpret_cast<const d2v*>(bp[h] + kb);
+        b[u][h][1] = *reinterpret_cast<const d2v*>(bp[h] + kb + 2);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const bool live = k0 + u * kstep < K;
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        double xa[2], yb[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          xa[h] = (live && va[h]) ? a[u][h][st >> 1][st & 1] : 0.0;
+          yb[h] = (live && vb[h]) ? b[u][h][st >> 1][st & 1] : 0.0;
+        }
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+            acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[x], yb[y], acc[x][y], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) part[w][2 * x + y][lane * 4 + q] = acc[x][y][q];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 1024; e += 64 * NW) {
+    const int t = e >> 8, idx = e & 255;
+    double sm = part[0][t][idx];
+#pragma unroll
+    for (int v = 1; v < NW; ++v) sm += part[v][t][idx];
+    const int ln = idx >> 2, q = idx & 3;
+    const int64_t row = i0 + 16 * (t >> 1) + (ln >> 4) + 4 * q;
+    const int64_t col = j0 + 16 * (t & 1) + (ln & 15);
+    if (row < M && col < N) {
+      double v = alpha * sm;
+      if (beta != 0.0) v += beta * C[row * ldc + col];
+      C[row * ldc + col] = v;
+    }
+  }
+}
+
 // Any K (rows of A and B need no padding): per-element loads with the K
 // tail masked, four waves.
 __global__ __launch_bounds__(256) void k_gemm_nt16_any(int64_t M, int64_t N, int64_t K,
@@ -324,6 +421,12 @@ __global__ __launch_bounds__(256) void k_gemm_nt16_any(int64_t M, int64_t N, int
 // K a multiple of 16 (the padded row length) with 16-byte aligned rows: the
 // batched-load kernel, sixteen waves splitting K when K >= 512; otherwise the
 // per-element kernel.  Partial tiles are summed in wave order (deterministic).
+// the 32 x 32 form: at least 128 output blocks and a long aligned K
+static bool nt32_shape(int64_t M, int64_t N, int64_t K) {
+  return K >= 512 && K % 16 == 0 && M >= 32 && N >= 32 &&
+         ceil_div(M, (int64_t)32) * ceil_div(N, (int64_t)32) >= 128;
+}
+
 int nt_slice_count(int64_t M, int64_t N, int64_t K) {
   const int64_t tiles = ceil_div(N, (int64_t)16) * ceil_div(M, (int64_t)16);
   if (tiles > 64 || K < 256 || K % 16) return 1;
@@ -349,6 +452,10 @@ hipError_t launch_gemm_nt_small(int64_t M, int64_t N, int64_t K, double alpha,
     g.z = (unsigned)nsl;
     hipLaunchKernelGGL(k_gemm_nt16<4>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb,
                        beta, C, ldc, m_dev, n_dev, kslice, cstride);
+  } else if (nt32_shape(M, N, K)) {
+    const dim3 g32((unsigned)ceil_div(N, 32), (unsigned)ceil_div(M, 32));
+    hipLaunchKernelGGL(k_gemm_nt32<8>, g32, dim3(512), 0, s, M, N, K, alpha, A, lda, B, ldb,
+                       beta, C, ldc, m_dev, n_dev);
   } else if (K >= 512) {
     hipLaunchKernelGGL(k_gemm_nt16<16>, g, dim3(1024), 0, s, M, N, K, alpha, A, lda, B, ldb,
                        beta, C, ldc, m_dev, n_dev, K, (int64_t)0);
@@ -435,6 +542,99 @@ __global__ __launch_bounds__(256) void k_gemm_tn16(int64_t M, int64_t N, int64_t
   }
 }
 
+// The same product with 32 x 32 output blocks (four MFMA tiles) per
+// workgroup: each loaded element of A or B feeds two MFMA tiles.  Used for
+// the basis projections when there are at least 128 such blocks.
+__global__ __launch_bounds__(256) void k_gemm_tn32(int64_t M, int64_t N, int64_t K,
+                                                   double alpha, const double* __restrict__ A,
+                                                   int64_t lda, const double* __restrict__ B,
+                                                   int64_t ldb, double beta,
+                                                   double* __restrict__ C, int64_t ldc, int nsl,
+                                                   int64_t astride) {
+  __shared__ double part[4][4][256];
+  const int64_t i0 = (int64_t)blockIdx.y * 32, j0 = (int64_t)blockIdx.x * 32;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int kq = lane >> 4;
+  int64_t iac[2], jbc[2];
+  bool va[2], vb[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t ia = i0 + 16 * h + (lane & 15), jb = j0 + 16 * h + (lane & 15);
+    va[h] = ia < M;
+    vb[h] = jb < N;
+    iac[h] = va[h] ? ia : 0;
+    jbc[h] = vb[h] ? jb : 0;
+  }
+  d4v acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = (d4v){0.0, 0.0, 0.0, 0.0};
+  // one 16-deep chunk per wave and step (k past K clamped to K - 1 and
+  // masked), every load of a step issued before its MFMAs
+  for (int64_t k0 = 16 * w; k0 < K; k0 += 64) {
+    double a[4][2], b[4][2];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int64_t k = min(k0 + 4 * st + kq, K - 1);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        a[st][h] = A[k * lda + iac[h]];
+        b[st][h] = B[k * ldb + jbc[h]];
+      }
+    }
+    // A given as K slices of partial sums: added in slice order
+    if (nsl > 1) {
+      double az[kNtMaxSlices - 1][4][2];
+#pragma unroll
+      for (int z = 1; z < kNtMaxSlices; ++z)
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int64_t k = min(k0 + 4 * st + kq, K - 1);
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            az[z - 1][st][h] = A[min(z, nsl - 1) * astride + k * lda + iac[h]];
+        }
+#pragma unroll
+      for (int z = 1; z < kNtMaxSlices; ++z)
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) a[st][h] += z < nsl ? az[z - 1][st][h] : 0.0;
+    }
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const bool kin = k0 + 4 * st + kq < K;
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64((va[x] && kin) ? a[st][x] : 0.0,
+                                                           (vb[y] && kin) ? b[st][y] : 0.0,
+                                                           acc[x][y], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) part[w][2 * x + y][lane * 4 + q] = acc[x][y][q];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 1024; e += 256) {
+    const int t = e >> 8, idx = e & 255;
+    const double sm = ((part[0][t][idx] + part[1][t][idx]) + part[2][t][idx]) + part[3][t][idx];
+    const int ln = idx >> 2, q = idx & 3;
+    const int64_t row = i0 + 16 * (t >> 1) + (ln >> 4) + 4 * q;
+    const int64_t col = j0 + 16 * (t & 1) + (ln & 15);
+    if (row < M && col < N) {
+      double v = alpha * sm;
+      if (beta != 0.0) v += beta * C[row * ldc + col];
+      C[row * ldc + col] = v;
+    }
+  }
+}
+
 hipError_t launch_gemm_tn_small(int64_t M, int64_t N, int64_t K, double alpha,
                                 const double* A, int64_t lda, const double* B, int64_t ldb,
                                 double beta, double* C, int64_t ldc, hipStream_t s,
@@ -443,7 +643,12 @@ hipError_t launch_gemm_tn_small(int64_t M, int64_t N, int64_t K, double alpha,
   if (M <= 0 || N <= 0) return hipSuccess;
   if (nsl < 1) return hipErrorInvalidValue;
   dim3 g((unsigned)ceil_div(N, 16), (unsigned)ceil_div(M, 16));
-  if (brow)
+  if (!brow && !k_dev && M >= 32 && N >= 32 &&
+      ceil_div(M, (int64_t)32) * ceil_div(N, (int64_t)32) >= 128) {
+    const dim3 g32((unsigned)ceil_div(N, 32), (unsigned)ceil_div(M, 32));
+    hipLaunchKernelGGL(k_gemm_tn32, g32, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta,
+                       C, ldc, nsl, astride);
+  } else if (brow)
     hipLaunchKernelGGL(k_gemm_tn16<true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb,
                        brow, k_dev, beta, C, ldc, nsl, astride);
   else
