@@ -148,8 +148,14 @@ __device__ __forceinline__ void sched_fence() {
 // spilled the eight-tile bodies and was slower.)
 constexpr int kRFDepth = 4;
 
-template <int MODE, int RT, int CT, int BT, int NB, int DEPTH0, int RIO = 0, int REGS = 256>
+// LOADR: phase 1 reads the panel's residual from memory (otherwise it is
+// already in Rreg: the second half of a block wider than 128 columns);
+// STORER: phase 2 writes it back and forms the row norms (otherwise it stays
+// in Rreg for the second half).
+template <int MODE, int RT, int CT, int BT, int NB, int DEPTH0, int RIO = 0, int REGS = 256,
+          bool LOADR = true, bool STORER = true>
 __device__ __forceinline__ void deflate_body(
+    typename DT<MODE>::V (&Rreg)[RT][CT],
     typename DT<MODE>::T* __restrict__ Rw, uint16_t* __restrict__ R16w, uint32_t ldr32,
     int64_t m, int nw, int w, int lane,
     const void* __restrict__ fragB1, const void* __restrict__ fragA2, int64_t frag_stride,
@@ -172,9 +178,8 @@ __device__ __forceinline__ void deflate_body(
   constexpr int DEPTH = WIDE ? 2 : DEPTH0;
   constexpr bool FENCE = WIDE || fence_fits<MODE, RT, CT, NB, DEPTH0, REGS>();
   const int l16 = lane & 15, lhi = lane >> 4;
-  constexpr bool RF = BF && RIO == 2;
+  constexpr bool RF = BF && RIO == 2 && LOADR;
 
-  V Rreg[RT][CT];
   // packed BF16 residual of the residual-first BF16-stored body
   uint4 raw[RT][RF ? CT / 2 : 1];
   V Pacc[RT][NB];
@@ -204,7 +209,7 @@ __device__ __forceinline__ void deflate_body(
 #pragma unroll
     for (int k = 0; k < DEPTH; ++k) {
       if (k < CT) {
-        load_r(k);
+        if constexpr (LOADR) load_r(k);
 #pragma unroll
         for (int bt = 0; bt < NB; ++bt) fr[k][bt] = fb[(uint32_t)((k * BT + bt) * 64) + lane];
       }
@@ -221,7 +226,7 @@ __device__ __forceinline__ void deflate_body(
           for (int rt = 0; rt < RT; ++rt)
             Pacc[rt][bt] = mfma4<MODE>(Rreg[rt][ct][i], fr[sl][bt][i], Pacc[rt][bt]);
       if (ct + DEPTH < CT) {
-        load_r(ct + DEPTH);
+        if constexpr (LOADR) load_r(ct + DEPTH);
 #pragma unroll
         for (int bt = 0; bt < NB; ++bt)
           fr[sl][bt] = fb[(uint32_t)(((ct + DEPTH) * BT + bt) * 64) + lane];
@@ -294,7 +299,7 @@ __device__ __forceinline__ void deflate_body(
 #pragma unroll
     for (int k = 0; k < DEPTH; ++k) {
       if (k < C2) {
-        load_pair(k);
+        if constexpr (LOADR) load_pair(k);
 #pragma unroll
         for (int bt = 0; bt < NB; ++bt) {
           const uint32_t o = (uint32_t)((k * BT + bt) * 64) + lane;
@@ -331,7 +336,7 @@ __device__ __forceinline__ void deflate_body(
         }
       }
       if (c2 + DEPTH < C2) {
-        load_pair(c2 + DEPTH);
+        if constexpr (LOADR) load_pair(c2 + DEPTH);
 #pragma unroll
         for (int bt = 0; bt < NB; ++bt) {
           const uint32_t o = (uint32_t)(((c2 + DEPTH) * BT + bt) * 64) + lane;
@@ -463,7 +468,8 @@ __device__ __forceinline__ void deflate_body(
         }
       sched_fence<FENCE>();
 #pragma unroll
-      for (int p = 0; p < PW; ++p) finish_chunk(c0 + p);
+      for (int p = 0; p < PW; ++p)
+        if constexpr (STORER) finish_chunk(c0 + p);
     }
   } else {
     constexpr int KS = BT / 2;               // fragment chunks of 32 in the buffer
@@ -533,12 +539,15 @@ __device__ __forceinline__ void deflate_body(
         }
       }
       sched_fence<FENCE>();
-      if constexpr (RIO == 0) finish_chunk(ct);
-      else if (ct & 1) finish_pair16(ct >> 1);
+      if constexpr (STORER) {
+        if constexpr (RIO == 0) finish_chunk(ct);
+        else if (ct & 1) finish_pair16(ct >> 1);
+      }
     }
   }
 
   // ---- squared row norms: lanes of one row, then waves in order ----
+  if constexpr (!STORER) return;
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
     double s = nrm[rt];
@@ -574,6 +583,20 @@ __device__ __forceinline__ void deflate_body(
   }
 }
 
+// Blocks wider than 128 kept columns come as two halves (bprime_p and
+// bprime2_p, with their own fragments): the second half's products run on
+// the residual still in registers (since Q2 is orthogonal to Q1, the
+// updated residual times Q2 equals R Q2), so R is read and written once per
+// block.  The kernels of 128-column blocks (BT = 8) with one BF16 product
+// carry that path, the memory-bound ones where the second pass over R
+// costs most; with FP32 or split products (bound by their MFMA work at 128
+// columns) the longer kernel spilled registers, so they take one launch per
+// half.
+template <int MODE, int BT>
+constexpr bool deflate_fuses() {
+  return BT == 8 && MODE == kModeBF16;
+}
+
 template <int MODE, int RT, int CT, int BT, int NWMAX, int DEPTH = kDepth, int RIO = 0,
           int WPE = 2>
 __global__ __launch_bounds__(64 * NWMAX) __attribute__((amdgpu_waves_per_eu(WPE))) void k_deflate(
@@ -581,12 +604,15 @@ __global__ __launch_bounds__(64 * NWMAX) __attribute__((amdgpu_waves_per_eu(WPE)
     int nw,
     const void* __restrict__ fragB1, const void* __restrict__ fragA2,
     int64_t frag_stride, const int32_t* __restrict__ bprime_p,
+    const void* __restrict__ fragB1b, const void* __restrict__ fragA2b,
+    const int32_t* __restrict__ bprime2_p,
     typename DT<MODE>::T* __restrict__ L, int64_t ldl, int64_t kS,
     const int32_t* __restrict__ sel_block, int32_t t, double* __restrict__ d,
     double* __restrict__ part_sum, double* __restrict__ part_max) {
   typedef typename DT<MODE>::T T;
   constexpr int MP = 16 * RT;
   constexpr int SLOT = RT * BT * kTileElems;
+  constexpr int REGS = WPE == 1 ? 512 : 256;
   extern __shared__ __align__(16) unsigned char smem[];
   T* Ps = reinterpret_cast<T*>(smem);                                            // nw * SLOT
   double* Ns = reinterpret_cast<double*>(smem + (size_t)nw * SLOT * sizeof(T));  // nw * MP
@@ -608,27 +634,45 @@ __global__ __launch_bounds__(64 * NWMAX) __attribute__((amdgpu_waves_per_eu(WPE)
   }
   const int bp = *bprime_p;
   if (bp <= 0) return;
-  const int nbt = (bp + 15) >> 4;          // active 16-wide tiles of b'
-#define RBRP_BODY(NBV)                                                                   \
-  deflate_body<MODE, RT, CT, BT, NBV, DEPTH, RIO, (WPE == 1 ? 512 : 256)>(                       \
-      Rw, R16w, (uint32_t)ldr, m, nw, w, lane,                                              \
-                                      fragB1, fragA2,                                      \
-                                      frag_stride, g0, bp, Lp, (uint32_t)ldl, t, sb_s, Ps, \
-                                      Ns, r0, d, part_sum, part_max)
-  if constexpr (MODE == kModeBF16x3 || MODE == kModeBF16) {
-    // BF16 phase 2 works in chunks of 32 b'-columns: round the tile count up
-    const int nb2 = (nbt + 1) & ~1;
-    if constexpr (BT >= 8) { if (nb2 > 4) { RBRP_BODY(8); return; } }
-    if constexpr (BT >= 4) { if (nb2 > 2) { RBRP_BODY(4); return; } }
-    RBRP_BODY(2);
-  } else {
-    if constexpr (BT >= 8) { if (nbt > 6) { RBRP_BODY(8); return; } }
-    if constexpr (BT >= 8) { if (nbt > 4) { RBRP_BODY(6); return; } }
-    if constexpr (BT >= 4) { if (nbt > 3) { RBRP_BODY(4); return; } }
-    if constexpr (BT >= 4) { if (nbt > 2) { RBRP_BODY(3); return; } }
-    if constexpr (BT >= 2) { if (nbt > 1) { RBRP_BODY(2); return; } }
-    RBRP_BODY(1);
+  typename DT<MODE>::V Rreg[RT][CT];
+  // the body for NBV active b' tiles of one half (fragments FB, FA; bpv
+  // kept columns at column offset LO of L)
+#define RBRP_BODY(NBV, LD, ST, FB, FA, BPV, LO)                                             \
+  deflate_body<MODE, RT, CT, BT, NBV, DEPTH, RIO, REGS, LD, ST>(                             \
+      Rreg, Rw, R16w, (uint32_t)ldr, m, nw, w, lane, FB, FA, frag_stride, g0, BPV, Lp + (LO), \
+      (uint32_t)ldl, t, sb_s, Ps, Ns, r0, d, part_sum, part_max)
+  // the ladder of active tile counts (BF16 phase 2 works in chunks of 32
+  // b'-columns: the tile count is rounded up to even)
+#define RBRP_LADDER(LD, ST, FB, FA, BPV, LO)                                                \
+  {                                                                                         \
+    const int nbt = ((BPV) + 15) >> 4;                                                      \
+    if constexpr (MODE == kModeBF16x3 || MODE == kModeBF16) {                               \
+      const int nb2 = (nbt + 1) & ~1;                                                       \
+      if constexpr (BT >= 8) { if (nb2 > 4) { RBRP_BODY(8, LD, ST, FB, FA, BPV, LO); return; } } \
+      if constexpr (BT >= 4) { if (nb2 > 2) { RBRP_BODY(4, LD, ST, FB, FA, BPV, LO); return; } } \
+      RBRP_BODY(2, LD, ST, FB, FA, BPV, LO);                                                \
+    } else {                                                                                \
+      if constexpr (BT >= 8) { if (nbt > 6) { RBRP_BODY(8, LD, ST, FB, FA, BPV, LO); return; } } \
+      if constexpr (BT >= 8) { if (nbt > 4) { RBRP_BODY(6, LD, ST, FB, FA, BPV, LO); return; } } \
+      if constexpr (BT >= 4) { if (nbt > 3) { RBRP_BODY(4, LD, ST, FB, FA, BPV, LO); return; } } \
+      if constexpr (BT >= 4) { if (nbt > 2) { RBRP_BODY(3, LD, ST, FB, FA, BPV, LO); return; } } \
+      if constexpr (BT >= 2) { if (nbt > 1) { RBRP_BODY(2, LD, ST, FB, FA, BPV, LO); return; } } \
+      RBRP_BODY(1, LD, ST, FB, FA, BPV, LO);                                                \
+    }                                                                                       \
+    return;                                                                                 \
   }
+  if constexpr (deflate_fuses<MODE, BT>()) {
+    const int bp2 = bprime2_p ? *bprime2_p : 0;
+    if (bp2 > 0) {
+      // first half: all 128 columns, the residual kept in registers
+      RBRP_BODY(8, true, false, fragB1, fragA2, bp, 0);
+      __syncthreads();
+      // second half on the updated residual, then stored with its norms
+      RBRP_LADDER(false, true, fragB1b, fragA2b, bp2, 16 * BT)
+    }
+  }
+  RBRP_LADDER(true, true, fragB1, fragA2, bp, 0)
+#undef RBRP_LADDER
 #undef RBRP_BODY
 }
 
@@ -773,6 +817,10 @@ int deflate_supported(int mode, int64_t ldr, int bmax) {
   return bmax >= 1 && bmax <= kMaxB;
 }
 
+bool deflate_fuses_halves(int mode) {
+  return mode == kModeBF16 || mode == kModeBF16W || mode == kModeBF16R;
+}
+
 int deflate_rows_per_wg(int mode, int64_t ldr) {
   DeflateCfg c;
   if (!pick_cfg(mode, ldr, &c)) return 0;
@@ -787,11 +835,19 @@ int64_t frag_elems(int mode, int64_t ldr, int bmax) {
   return G * bt * 64 * 4;
 }
 
+// The second half of a block wider than 128 kept columns (null bp: none).
+struct Half2 {
+  const void* fB;
+  const void* fA;
+  const int32_t* bp;
+};
+
 template <int MODE, int RT, int CT, int BT, int NWMAX, int RIO, int WPEV = 2, int DPO = 0>
 static hipError_t run_deflate(const DeflateCfg& c, int64_t grid, hipStream_t s,
                               void* R, void* R16, int64_t ldr, int64_t m, const void* fB,
                               const void* fA, int64_t fstride, const int32_t* bp,
-                              void* L, int64_t ldl, int64_t kS, const int32_t* sel,
+                              Half2 h2, void* L, int64_t ldl, int64_t kS,
+                              const int32_t* sel,
                               int32_t t, double* d, double* ps, double* pm) {
   typedef typename DT<MODE>::T T;
   // FP32 panels of 16 column tiles keep four chunks in flight (with the
@@ -811,20 +867,20 @@ static hipError_t run_deflate(const DeflateCfg& c, int64_t grid, hipStream_t s,
   if (lds > 160 * 1024 - 1024) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((k_deflate<MODE, RT, CT, BT, NWMAX, DP, RIO, WPEV>), dim3((unsigned)grid),
                      dim3(64 * c.nw), lds, s, (T*)R, (uint16_t*)R16, ldr, m, c.nw, fB, fA,
-                     fstride, bp, (T*)L, ldl, kS, sel, t, d, ps, pm);
+                     fstride, bp, h2.fB, h2.fA, h2.bp, (T*)L, ldl, kS, sel, t, d, ps, pm);
   return hipGetLastError();
 }
 
 template <int MODE, int BT, int RIO>
 static hipError_t dispatch_ct(const DeflateCfg& c, int64_t mr, hipStream_t s, void* R,
                               void* R16, int64_t ldr, int64_t m, const void* fB,
-                              const void* fA, int64_t fstride, const int32_t* bp, void* L,
-                              int64_t ldl, int64_t kS, const int32_t* sel, int32_t t,
+                              const void* fA, int64_t fstride, const int32_t* bp, Half2 h2,
+                              void* L, int64_t ldl, int64_t kS, const int32_t* sel, int32_t t,
                               double* d, double* ps, double* pm) {
 #define RBRP_DEF_CASE(CTV, RTV, NWV)                                                   \
   if (c.ct == CTV && c.rt == RTV && c.nwmax == NWV)                                   \
     return run_deflate<MODE, RTV, CTV, BT, NWV, RIO>(c, mr / (16 * RTV), s, R, R16, ldr, \
-                                                     m, fB, fA, fstride, bp, L, ldl, kS, \
+                                                     m, fB, fA, fstride, bp, h2, L, ldl, kS, \
                                                      sel, t, d, ps, pm);
   if constexpr (MODE == kModeF64) {
     RBRP_DEF_CASE(4, 2, 4)
@@ -845,7 +901,7 @@ static hipError_t dispatch_ct(const DeflateCfg& c, int64_t mr, hipStream_t s, vo
     if constexpr (MODE == kModeF32 && RIO == 0)
       if (c.ct == 32 && c.rt == 2 && c.nwmax == 4)
         return run_deflate<MODE, 2, 32, BT, 4, RIO, 1, 2>(c, mr / 32, s, R, R16, ldr, m, fB, fA,
-                                                          fstride, bp, L, ldl, kS, sel, t, d, ps,
+                                                          fstride, bp, h2, L, ldl, kS, sel, t, d, ps,
                                                           pm);
   }
 #undef RBRP_DEF_CASE
@@ -856,22 +912,23 @@ template <int MODE, int RIO>
 static hipError_t dispatch_bt(int bt, const DeflateCfg& c, int64_t mr, hipStream_t s,
                               void* R, void* R16, int64_t ldr, int64_t m, const void* fB,
                               const void* fA, int64_t fstride, const int32_t* bp,
-                              void* L, int64_t ldl, int64_t kS, const int32_t* sel,
+                              Half2 h2, void* L, int64_t ldl, int64_t kS,
+                              const int32_t* sel,
                               int32_t t, double* d, double* ps, double* pm) {
   switch (bt) {
     case 1:
       if constexpr (MODE == kModeF64 || MODE == kModeF32)
-        return dispatch_ct<MODE, 1, RIO>(c, mr, s, R, R16, ldr, m, fB, fA, fstride, bp, L,
+        return dispatch_ct<MODE, 1, RIO>(c, mr, s, R, R16, ldr, m, fB, fA, fstride, bp, h2, L,
                                          ldl, kS, sel, t, d, ps, pm);
       break;
     case 2:
-      return dispatch_ct<MODE, 2, RIO>(c, mr, s, R, R16, ldr, m, fB, fA, fstride, bp, L, ldl,
+      return dispatch_ct<MODE, 2, RIO>(c, mr, s, R, R16, ldr, m, fB, fA, fstride, bp, h2, L, ldl,
                                        kS, sel, t, d, ps, pm);
     case 4:
-      return dispatch_ct<MODE, 4, RIO>(c, mr, s, R, R16, ldr, m, fB, fA, fstride, bp, L, ldl,
+      return dispatch_ct<MODE, 4, RIO>(c, mr, s, R, R16, ldr, m, fB, fA, fstride, bp, h2, L, ldl,
                                        kS, sel, t, d, ps, pm);
     case 8:
-      return dispatch_ct<MODE, 8, RIO>(c, mr, s, R, R16, ldr, m, fB, fA, fstride, bp, L, ldl,
+      return dispatch_ct<MODE, 8, RIO>(c, mr, s, R, R16, ldr, m, fB, fA, fstride, bp, h2, L, ldl,
                                        kS, sel, t, d, ps, pm);
   }
   return hipErrorInvalidConfiguration;
@@ -879,7 +936,8 @@ static hipError_t dispatch_bt(int bt, const DeflateCfg& c, int64_t mr, hipStream
 
 hipError_t launch_deflate(int mode, void* R, void* R16, int64_t mr, int64_t ldr, int64_t m,
                           const void* fragB1, const void* fragA2,
-                          const int32_t* bprime, int bmax, void* L, int64_t ldl,
+                          const int32_t* bprime, int bmax, const void* fragB1b,
+                          const void* fragA2b, const int32_t* bprime2, void* L, int64_t ldl,
                           int64_t kS, const int32_t* sel_block, int32_t t, double* d,
                           double* part_sum, double* part_max, hipStream_t s) {
   DeflateCfg c;
@@ -888,7 +946,12 @@ hipError_t launch_deflate(int mode, void* R, void* R16, int64_t mr, int64_t ldr,
   if (mode_stores_bf16(mode) && (!R16 || ldr % 32)) return hipErrorInvalidValue;
   const int bt = bt_for(mode, bmax);
   const int64_t fstride = frag_elems(mode, ldr, bmax) / (is_bf16_mode(mode) ? 8 : 4);
-#define RBRP_ARGS bt, c, mr, s, R, R16, ldr, m, fragB1, fragA2, fstride, bprime, L, ldl, kS, \
+  // a second half only in one launch with the first (kernels of 128-column
+  // blocks with one BF16 product)
+  if (bprime2 && (bt != 8 || !deflate_fuses_halves(mode) || !fragB1b || !fragA2b))
+    return hipErrorInvalidValue;
+  const Half2 h2{fragB1b, fragA2b, bprime2};
+#define RBRP_ARGS bt, c, mr, s, R, R16, ldr, m, fragB1, fragA2, fstride, bprime, h2, L, ldl, kS, \
                   sel_block, t, d, part_sum, part_max
   switch (mode) {
     case kModeF64: return dispatch_bt<kModeF64, 0>(RBRP_ARGS);

@@ -69,6 +69,8 @@ struct Work {
   double* Qt;
   void* fragB1;
   void* fragA2;
+  void* fragB1b;   // the second half of blocks wider than kDeflateMaxB
+  void* fragA2b;
   void* L;
   double* interp;
 };
@@ -148,6 +150,9 @@ size_t layout(const Plan& p, char* base, Work* w) {
   w->Qt = cv.take<double>((size_t)p.k_max * p.ldr);
   w->fragB1 = cv.take<char>(frag_bytes(mode, p.ldr, p.bdef));
   w->fragA2 = cv.take<char>(frag_bytes(mode, p.ldr, p.bdef));
+  const bool halves = p.b > kDeflateMaxB;
+  w->fragB1b = halves ? cv.take<char>(frag_bytes(mode, p.ldr, p.bdef)) : nullptr;
+  w->fragA2b = halves ? cv.take<char>(frag_bytes(mode, p.ldr, p.bdef)) : nullptr;
   w->L = cv.take<char>((size_t)p.m * p.ldl * rs);
   const size_t nint = p.w_pinv ? pinv_workspace_doubles(p.k_max)
                                : interp_workspace_doubles(p.m, p.k_max, p.refine);
@@ -534,8 +539,12 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
       if (mode == p.native_mode) st.blocks_native++;
       if (mode_stores_bf16(mode)) st.blocks_bf16_stored++;
     }
+    // blocks wider than kDeflateMaxB columns: both halves in one launch
+    // where the mode allows it (the count of the second half stays on the
+    // device), else one launch per half
+    const bool fuse = b > kDeflateMaxB && deflate_fuses_halves(mode);
     int nchunk = 1;
-    if (b > kDeflateMaxB) {
+    if (b > kDeflateMaxB && !fuse) {
       rs = fetch(h, w.sc, s);
       if (rs != RBRP_OK) return rs;
       nchunk = h->bprime > kDeflateMaxB ? 2 : 1;
@@ -546,7 +555,23 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     }
     prof.end();
     const double s_in = mode_reads_bf16(mode) ? 2.0 : (p.r_f64 ? 8.0 : 4.0);
-    for (int c = 0; c < nchunk; ++c) {
+    if (fuse) {
+      prof.begin(2);
+      RBRP_HIP(launch_make_frags(Qn, ldr, &w.sc->bchunk[0], ldr, p.bdef, mode, w.fragB1,
+                                 w.fragA2, s));
+      RBRP_HIP(launch_make_frags(Qn + (int64_t)kDeflateMaxB * ldr, ldr, &w.sc->bchunk[1], ldr,
+                                 p.bdef, mode, w.fragB1b, w.fragA2b, s));
+      prof.end();
+      prof.begin(3);
+      RBRP_HIP(launch_deflate(mode, w.R, w.R16, p.mr, ldr, m, w.fragB1, w.fragA2,
+                              &w.sc->bchunk[0], p.bdef, w.fragB1b, w.fragA2b,
+                              &w.sc->bchunk[1], w.L, p.ldl, kS, w.sel_block, t, w.d,
+                              w.part_sum, w.part_max, s));
+      prof.end();
+      const double sw = mode_stores_bf16(mode) ? 2.0 : (p.r_f64 ? 8.0 : 4.0);
+      dbytes += (double)m * (double)n * (s_in + sw) + 8.0 * (double)m;
+    }
+    for (int c = 0; c < (fuse ? 0 : nchunk); ++c) {
       const int32_t* bcnt = b > kDeflateMaxB ? &w.sc->bchunk[c] : &w.sc->bprime;
       // the first launch of a block that switches to BF16 storage writes the
       // BF16 residual, a second one reads it
@@ -557,7 +582,8 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
       prof.end();
       prof.begin(3);
       RBRP_HIP(launch_deflate(cm, w.R, w.R16, p.mr, ldr, m, w.fragB1, w.fragA2, bcnt, p.bdef,
-                              w.L, p.ldl, kS + (int64_t)c * kDeflateMaxB, w.sel_block, t, w.d,
+                              nullptr, nullptr, nullptr, w.L, p.ldl,
+                              kS + (int64_t)c * kDeflateMaxB, w.sel_block, t, w.d,
                               w.part_sum, w.part_max, s));
       prof.end();
       // algorithmic bytes: R read and written, d written (L below)
@@ -591,10 +617,12 @@ rbrp_status rbrp_id(const void* X, rbrp_dtype dtype, int64_t m, int64_t n, int64
     sum_last = sum_d;
     kS += bp;
     {
-      // a second deflation launch rounds the accumulator once more per row,
-      // and with BF16 storage rounds the (larger) intermediate residual too
-      double v = err_var_increment(mode, bp + 32 * (nchunk - 1), sum_d / D0, h->sum_d / D0);
-      if (v > 0.0 && nchunk > 1 && mode_stores_bf16(mode))
+      // a second half rounds the accumulator once more per row; in its own
+      // launch with BF16 storage it also rounds the (larger) intermediate
+      // residual to BF16
+      const int halves = bp > kDeflateMaxB ? 2 : 1;
+      double v = err_var_increment(mode, bp + 32 * (halves - 1), sum_d / D0, h->sum_d / D0);
+      if (v > 0.0 && !fuse && nchunk > 1 && mode_stores_bf16(mode))
         v += (nchunk - 1) * err_var_increment(mode, 0, 0.0, sum_d / D0);
       if (v > 0.0) err_var += v;
     }

@@ -220,9 +220,14 @@ hipError_t launch_make_frags(const double* Qt_new, int64_t ldq,
 // R <- R - P Q'^T, d_i = ||R_i||^2 (0 on skeletons), partial sums / maxima.
 // R16: the BF16 residual (mr x ldr, permuted 32-column groups) that modes
 // kModeBF16W write and kModeBF16R read and write; may be NULL otherwise.
+// bprime2 (with fragB1b, fragA2b): the second half of a block wider than
+// kDeflateMaxB columns (its count, possibly 0, on the device), deflated in
+// the same launch on the residual still in registers; only where
+// deflate_fuses_halves says so, otherwise NULL and one launch per half.
 hipError_t launch_deflate(int mode, void* R, void* R16, int64_t mr, int64_t ldr,
                           int64_t m, const void* fragB1, const void* fragA2,
-                          const int32_t* bprime, int bmax, void* L,
+                          const int32_t* bprime, int bmax, const void* fragB1b,
+                          const void* fragA2b, const int32_t* bprime2, void* L,
                           int64_t ldl, int64_t kS, const int32_t* sel_block,
                           int32_t t, double* d, double* part_sum,
                           double* part_max, hipStream_t s);
@@ -231,6 +236,9 @@ int64_t deflate_num_partials(int64_t mr);
 hipError_t launch_r16_to_r32(const void* R16, void* R, int64_t mr, int64_t ldr,
                              hipStream_t s);
 int deflate_supported(int mode, int64_t ldr, int bmax);
+// whether one launch deflates both halves of a block wider than
+// kDeflateMaxB columns in this mode (the one-BF16-product modes)
+bool deflate_fuses_halves(int mode);
 int deflate_rows_per_wg(int mode, int64_t ldr);
 int64_t deflate_pad_cols(int64_t n);
 size_t frag_bytes(int mode, int64_t ldr, int bmax);
