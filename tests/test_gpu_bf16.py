@@ -94,6 +94,32 @@ def test_bf16_power_spectrum(rb, eps):
     assert abs(res.k - ref32.k) <= max(b, 0.15 * ref32.k)
 
 
+@pytest.mark.parametrize("theta", [0.5, 0.0])
+def test_bf16_wide_blocks_one_launch(rb, theta):
+    """b = 256 with blocks of more than 128 kept columns: with one BF16
+    product both halves are deflated in one launch on the residual held in
+    registers (theta = 0.5: split while the relative residual exceeds 0.5,
+    one product on the FP32 residual below; theta = 0: the controller, down
+    to the BF16-stored residual).  Same bounds as the other BF16 runs."""
+    eps, b = 1e-3, 256
+    X = svd_matrix(20000, 1024, power_spectrum(1024, 1.5), seed=8).astype(np.float32)
+    res = _run(rb, X, eps, b, 2, precision="bf16", theta=theta)
+    assert max(res.bprime) > 128
+    assert res.blocks_split < res.blocks
+    oracle = oracle_rbrp(X.astype(np.float64), eps, b, 2)
+    assert res.bprime[0] == oracle.blocks[0][1]
+    e_true, e_opt = _errors(X, res)
+    print(f"  k={res.k} bprime={res.bprime} split={res.blocks_split} e_true={e_true:.3e} "
+          f"rho={res.resid_tracked:.3e} E={res.err_bound:.3e}", flush=True)
+    assert e_true <= eps
+    # the fixed rule's stated floor (one product from a relative residual of
+    # theta on), the controller's otherwise
+    assert e_true <= e_opt + W_FLOOR + 4e-3 * theta
+    assert abs(res.resid_tracked - e_true) <= res.err_bound
+    ref32 = _run(rb, X, eps, b, 2)
+    assert abs(res.k - ref32.k) <= max(b, 0.15 * ref32.k)
+
+
 def test_bf16_split_everywhere(rb):
     # theta -> 0: every block uses the three-product split form
     eps, b = 1e-3, 64
