@@ -333,7 +333,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not "
-              "supported by this build: every decomposition runs on a single MI355X.",
+              "supported: every decomposition runs on a single MI355X.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -45,7 +45,7 @@ typedef enum {
   RBRP_E_NONFINITE = 4,   /* X holds a NaN or an infinity                     */
   RBRP_E_CAPACITY = 5,    /* the tolerance was not met within k_max skeletons;
                              S, k and W describe the k_max skeletons chosen   */
-  RBRP_E_UNSUPPORTED = 6  /* a valid combination this build does not provide  */
+  RBRP_E_UNSUPPORTED = 6  /* a valid combination the library does not provide */
 } rbrp_status;
 
 typedef enum { RBRP_F32 = 0, RBRP_F64 = 1 } rbrp_dtype;
