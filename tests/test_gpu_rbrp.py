@@ -77,6 +77,34 @@ def test_fp64_matches_oracle(rb, m, n, b, eps, seed):
         assert max(res.bprime) > 128
 
 
+@pytest.mark.parametrize("m,n,b,eps,seed", [
+    (1, 7, 16, 1e-12, 1),     # one row
+    (7, 1, 4, 1e-12, 2),      # one column
+    (10, 40, 16, 1e-12, 3),   # fewer rows than b: the whole matrix in one block
+    (40, 10, 64, 1e-12, 4),   # b > m and b > n
+    (16, 16, 16, 1e-3, 5),    # m = n = b
+    (65, 17, 8, 1e-12, 6),    # ragged rows and columns, run to full rank
+    (129, 33, 32, 1e-3, 7),
+    (3, 300, 2, 1e-12, 8),    # the filter keeps one of two columns per block
+])
+def test_fp64_tiny_and_degenerate_shapes(rb, m, n, b, eps, seed):
+    """Gaussian matrices of tiny and degenerate shapes against the oracle:
+    the same skeletons and block sizes, W = X X_S^+ to 1e-10 (with an
+    absolute floor: several runs end at full rank, where W(rest,:) is exact
+    up to rounding), W(S,:) = I."""
+    X = np.random.default_rng(seed).standard_normal((m, n))
+    res = _run(rb, X, eps, b, seed)
+    ref = oracle_rbrp(X, eps, b, seed)
+    assert res.status == 0
+    assert res.S.cpu().tolist() == ref.S
+    assert res.bprime == [bp for _, bp in ref.blocks]
+    W = res.W.cpu().numpy()
+    Wref = w_lstsq(X, ref.S)
+    assert np.array_equal(W[ref.S], np.eye(res.k))
+    assert np.linalg.norm(W - Wref) <= 1e-10 * np.linalg.norm(Wref) + 1e-12
+    assert abs(res.resid_tracked - ref.rho) <= 1e-10 * ref.rho + 1e-14
+
+
 @pytest.mark.parametrize("r,b", [(5, 16), (40, 16), (12, 8), (70, 32)])
 def test_fp64_exact_rank_recovery(rb, r, b):
     X = exact_rank(600, 150, r, seed=40 + r)
