@@ -120,6 +120,25 @@ def test_bf16_wide_blocks_one_launch(rb, theta):
     assert abs(res.k - ref32.k) <= max(b, 0.15 * ref32.k)
 
 
+@pytest.mark.parametrize("precision", ["native", "bf16"])
+@pytest.mark.parametrize("m,n,b", [(1, 7, 16), (7, 1, 4), (10, 40, 16), (40, 10, 64),
+                                   (65, 17, 8), (129, 33, 32), (3, 300, 2)])
+def test_fp32_tiny_and_degenerate_shapes(rb, m, n, b, precision):
+    """FP32 input of tiny and degenerate shapes in both forms: a valid ID at
+    eps (W(S,:) = I, error recomputed in FP64), the first block equal to the
+    oracle's (its probabilities come from X alone)."""
+    eps, seed = 1e-3, m + n
+    X = np.random.default_rng(seed).standard_normal((m, n)).astype(np.float32)
+    res = _run(rb, X, eps, b, seed, precision=precision)
+    assert res.status == 0
+    oracle = oracle_rbrp(X.astype(np.float64), eps, b, seed)
+    bp0 = oracle.blocks[0][1]
+    assert res.bprime[0] == bp0
+    assert res.S.cpu().tolist()[:bp0] == oracle.S[:bp0]
+    e_true, _ = _errors(X, res)
+    assert e_true <= eps
+
+
 def test_bf16_split_everywhere(rb):
     # theta -> 0: every block uses the three-product split form
     eps, b = 1e-3, 64
