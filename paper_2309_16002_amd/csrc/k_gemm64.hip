@@ -913,7 +913,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
   }
 }
 
-// A further refinement step on an existing W (after the pass below), fused
+// A further refinement step on an existing W (after the first pass), fused
 // per 128-row strip: with the residual E = L_2 - W L_1 the
 // correction F of F L_1 = E is formed block by block from the last column
 // block to the first as F(:, J) = (E(:, J) - sum_{I > J} F(:, I) L_1(I, J))
@@ -944,55 +944,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
   }
 }
 
-
-// Substitution with one step of iterative refinement, per 128-row strip in
-// a single pass.  For column block J (last to first), with the blocks I > J
-// already final:
-//   R = L_2(:, J) - sum_{I > J} W(:, I) L_1(I, J)          (the right side)
-//   W(:, J) = R D_J^{-1}
-//   T = R - W(:, J) D_J    (= (L_2 - W L_1)(:, J), the residual of the block)
-//   W(:, J) += T D_J^{-1}
-// The residual of block J is exact for the current W (the later blocks are
-// final), so this is the refinement step W += F, F L_1 = L_2 - W L_1, taken
-// block by block in substitution order.  R and T live in Tws (TB_M x 64 per
-// strip: rows of the strip only); Bt holds D_J^{-1} on its diagonal blocks;
-// L_1 is lower triangular (zero above the diagonal).
-// The right side L may alias W (its columns then hold the right sides of
-// a sub-solve): block J's right side is read by the first tile, before the
-// barrier after which the block is overwritten.  L_1 and Bt have leading
-// dimension ldt (>= K: the sub-solve of a diagonal block of a larger L_1).
-template <typename TL, bool VA, int TB_K, int WPE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_trsm_refine(
-    int64_t M, int64_t K, const TL* L, int64_t ldl, const double* __restrict__ L1,
-    const double* __restrict__ Bt, int64_t ldt, double* W, int64_t ldw,
-    double* __restrict__ Tws) {
-  constexpr int TBJ = 64;
-  __shared__ double As[2][TB_K][TA_LD];
-  __shared__ double Bs[2][TB_K][TBJ + 16];
-  const int64_t i0 = (int64_t)blockIdx.x * TB_M;
-  for (int64_t J = ceil_div(K, (int64_t)TBJ) - 1; J >= 0; --J) {
-    const int64_t j0 = TBJ * J, nb = min((int64_t)TBJ, K - j0);
-    const double* Dinv = Bt + j0 * ldt + j0;
-    const double* Dj = L1 + j0 * ldt + j0;
-    // R (no K steps for the last block: the tile is then L_2(:, J) itself)
-    tall_tile<double, VA, TL, TB_K, TBJ>(i0, j0, j0 + TBJ, M, K, K, -1.0, W, ldw, L1, ldt, 1.0,
-                                         Tws, TBJ, L, ldl, As, Bs, (const double*)nullptr, 0,
-                                         0, j0);
-    __syncthreads();
-    tall_tile<double, true, double, TB_K, TBJ>(i0, 0, 0, M, nb, nb, 1.0, Tws, TBJ, Dinv, ldt,
-                                               0.0, W + j0, ldw, (const double*)nullptr, 0,
-                                               As, Bs, (const double*)nullptr, 0, 0, 0, 0);
-    __syncthreads();
-    tall_tile<double, VA, double, TB_K, TBJ>(i0, 0, 0, M, nb, nb, -1.0, W + j0, ldw, Dj, ldt,
-                                             1.0, Tws, TBJ, Tws, TBJ, As, Bs,
-                                             (const double*)nullptr, 0, 0, 0, 0);
-    __syncthreads();
-    tall_tile<double, true, double, TB_K, TBJ>(i0, 0, 0, M, nb, nb, 1.0, Tws, TBJ, Dinv, ldt,
-                                               1.0, W + j0, ldw, W + j0, ldw, As, Bs,
-                                               (const double*)nullptr, 0, 0, 0, 0);
-    __syncthreads();
-  }
-}
 
 // C = Cin - A B for tall A (M x K, FP64, row-major) and B (K x N): the
 // contribution of the later column blocks of W to the right sides of a
@@ -1066,63 +1017,27 @@ hipError_t launch_trsm_tall(int64_t M, int64_t K, const void* L, int l_f32, int6
   return hipGetLastError();
 }
 
-// Compute units of the current device (cached per host thread).
-static int device_cus() {
-  static thread_local int dev = -1, cus = 0;
-  int d = 0;
-  if (hipGetDevice(&d) != hipSuccess) return 256;
-  if (d != dev) {
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess ||
-        cus <= 0)
-      cus = 256;
-    dev = d;
-  }
-  return cus;
-}
-
 template <typename TL, bool VA>
-static void refine_typed(int64_t M, int64_t K, const TL* L, int64_t ldl, const double* L1,
-                         const double* Bt, int64_t ldt, double* W, int64_t ldw, double* Tws,
-                         int step, hipStream_t s) {
-  const int64_t strips = ceil_div(M, TB_M);
-  const dim3 g((unsigned)strips);
-  if (step) {
-    hipLaunchKernelGGL((k_trsm_refine_step<TL, VA, 8, 3>), g, dim3(256), 0, s, M, K, L, ldl, L1,
-                       Bt, W, ldw, Tws);   // whole solve: ldt = K
-    return;
-  }
-  // Every strip is one long dependent chain of tiles, so each round of
-  // resident workgroups costs a whole chain.  The four-per-CU build (fewer
-  // registers, a few spilled) runs a chain about 9 % slower than the
-  // three-per-CU build (measured at k = 202), so it is used when it needs
-  // fewer rounds by more than that (100000 x 202: 0.53 -> 0.49 ms).
-  const int64_t cus = device_cus();
-  const int64_t r3 = ceil_div(strips, 3 * cus), r4 = ceil_div(strips, 4 * cus);
-  if (109 * r4 < 100 * r3)
-    hipLaunchKernelGGL((k_trsm_refine<TL, VA, 8, 4>), g, dim3(256), 0, s, M, K, L, ldl, L1, Bt,
-                       ldt, W, ldw, Tws);
-  else
-    hipLaunchKernelGGL((k_trsm_refine<TL, VA, 8, 3>), g, dim3(256), 0, s, M, K, L, ldl, L1, Bt,
-                       ldt, W, ldw, Tws);
+static void refine_step_typed(int64_t M, int64_t K, const TL* L, int64_t ldl, const double* L1,
+                              const double* Bt, double* W, int64_t ldw, double* Tws,
+                              hipStream_t s) {
+  hipLaunchKernelGGL((k_trsm_refine_step<TL, VA, 8, 3>), dim3((unsigned)ceil_div(M, TB_M)),
+                     dim3(256), 0, s, M, K, L, ldl, L1, Bt, W, ldw, Tws);
 }
 
-hipError_t launch_trsm_refine(int64_t M, int64_t K, const void* L, int l_f32, int64_t ldl,
-                              const double* L1, const double* Bt, int64_t ldt, double* W,
-                              int64_t ldw, int64_t col_off, double* Tws, int step,
-                              hipStream_t s) {
+hipError_t launch_trsm_refine_step(int64_t M, int64_t K, const void* L, int l_f32,
+                                   int64_t ldl, const double* L1, const double* Bt, double* W,
+                                   int64_t ldw, double* Tws, hipStream_t s) {
   if (M <= 0 || K <= 0) return hipSuccess;
-  if (step && ldt != K) return hipErrorInvalidValue;   // a further step runs on the whole W
-  // vector loads of W's rows: the row (from W's column col_off of the
-  // caller's matrix) must extend to whole K steps
+  // vector loads of W's rows: the rows must extend to whole K steps
   const int64_t kr = round_up(K, (int64_t)8);
-  const bool vec = (reinterpret_cast<uintptr_t>(W) % 16 == 0) && (ldw % 2 == 0) &&
-                   ldw >= col_off + kr;
+  const bool vec = (reinterpret_cast<uintptr_t>(W) % 16 == 0) && (ldw % 2 == 0) && ldw >= kr;
   if (l_f32) {
-    if (vec) refine_typed<float, true>(M, K, (const float*)L, ldl, L1, Bt, ldt, W, ldw, Tws, step, s);
-    else refine_typed<float, false>(M, K, (const float*)L, ldl, L1, Bt, ldt, W, ldw, Tws, step, s);
+    if (vec) refine_step_typed<float, true>(M, K, (const float*)L, ldl, L1, Bt, W, ldw, Tws, s);
+    else refine_step_typed<float, false>(M, K, (const float*)L, ldl, L1, Bt, W, ldw, Tws, s);
   } else {
-    if (vec) refine_typed<double, true>(M, K, (const double*)L, ldl, L1, Bt, ldt, W, ldw, Tws, step, s);
-    else refine_typed<double, false>(M, K, (const double*)L, ldl, L1, Bt, ldt, W, ldw, Tws, step, s);
+    if (vec) refine_step_typed<double, true>(M, K, (const double*)L, ldl, L1, Bt, W, ldw, Tws, s);
+    else refine_step_typed<double, false>(M, K, (const double*)L, ldl, L1, Bt, W, ldw, Tws, s);
   }
   return hipGetLastError();
 }

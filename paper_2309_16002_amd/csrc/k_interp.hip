@@ -9,7 +9,7 @@
 //      by 16 x 16 blocks on FP64 MFMA) and the sub-diagonal blocks scaled,
 //      Bt(I, J) = -L_1(I, J) D_J^{-1} (one small MFMA GEMM per block column);
 //   3. W L_1 = L solved in place in W by blocked substitution over the block
-//      columns, from the last to the first (super-blocks of 128 columns: the
+//      columns, from the last to the first (super-blocks of 256 columns: the
 //      later super-blocks' part by one tall MFMA GEMM, then each row's
 //      substitution with W in registers), with the first refinement step
 //      (the residual E = L - W L_1, F L_1 = E, W += F) taken block by block
@@ -22,7 +22,7 @@
 namespace rbrp {
 
 constexpr int kDiag = 64;
-constexpr int kRegsNJ = 2;   // column blocks of 64 per super-block of the W solve
+constexpr int kRegsNJ = 4;   // column blocks of 64 per super-block of the W solve
 constexpr int kRegsNB = 1;   // 16-row column blocks of W^T per wave
 constexpr int64_t kSuper = 64 * kRegsNJ;   // columns of a super-block
 
@@ -127,9 +127,11 @@ __global__ __launch_bounds__(256) void k_trsm_regs_frags(const double* __restric
 // (the later super-blocks' contribution is already in the right sides).
 // No LDS, no barriers: each wave runs its own chain.  L may alias W (the
 // right sides of a super-block are then W's own columns): a wave reads its
-// rows of block J before it stores them.
+// rows of block J before it stores them.  With NJ = 4 the registers are
+// capped at two waves per SIMD (236 without spills): the compiler's own
+// choice, one wave per SIMD, ran the solve about 4 % slower on 200000 rows.
 template <typename TL, int NJ, int NB>
-__global__ __launch_bounds__(256) void k_trsm_regs(int64_t M, int64_t K,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_trsm_regs(int64_t M, int64_t K,
                                                    const TL* L, int64_t ldl,
                                                    const double* __restrict__ F,
                                                    double* W, int64_t ldw) {
@@ -339,7 +341,7 @@ hipError_t launch_interp(const void* L, int l_f64, int64_t ldl, int64_t m, int64
       }
     }
     for (int it = 1; it < refine && e == hipSuccess; ++it)
-      e = launch_trsm_refine(m, k, L, lf32, ldl, L1, Bt, k, W, ldw, 0, Tws, 1, s);
+      e = launch_trsm_refine_step(m, k, L, lf32, ldl, L1, Bt, W, ldw, Tws, s);
   }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_identity_rows, dim3((unsigned)k), dim3(256), 0, s, S, k, W, ldw);

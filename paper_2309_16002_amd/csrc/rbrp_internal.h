@@ -122,17 +122,13 @@ hipError_t launch_gemm_f64(int transA, int transB, int64_t M, int64_t N,
 // -L_1(I, J) D_J^{-1} below them (K x K, ld K).
 hipError_t launch_trsm_tall(int64_t M, int64_t K, const void* L, int l_f32, int64_t ldl,
                             const double* Bt, double* W, int64_t ldw, hipStream_t s);
-// The same solve with one refinement step, in one pass per strip (step = 0:
-// W is written from scratch), or a further refinement step of an existing W
-// (step = 1).  Tws: round_up(M, 128) x 64 doubles of scratch; L1 the
-// lower-triangular k x k factor, Bt as above.
-// ldt: leading dimension of L1 and Bt (K for a whole solve; the caller's k
-// for the diagonal block of a super-block, whose first column is col_off of
-// W's rows); step = 1 needs ldt = K.
-hipError_t launch_trsm_refine(int64_t M, int64_t K, const void* L, int l_f32, int64_t ldl,
-                              const double* L1, const double* Bt, int64_t ldt, double* W,
-                              int64_t ldw, int64_t col_off, double* Tws, int step,
-                              hipStream_t s);
+// A further refinement step of an existing W (W += F, F L_1 = L_2 - W L_1),
+// in one pass per 128-row strip.  Tws: round_up(M, 128) x 64 doubles of
+// scratch; L1 the lower-triangular K x K factor (ld K), Bt with D_J^{-1} on
+// its diagonal blocks (ld K).
+hipError_t launch_trsm_refine_step(int64_t M, int64_t K, const void* L, int l_f32,
+                                   int64_t ldl, const double* L1, const double* Bt, double* W,
+                                   int64_t ldw, double* Tws, hipStream_t s);
 // C = Cin - A B (A: M x K FP64; B: K x N; Cin FP32 or FP64), tall A.
 // a_vec: the rows of A extend to whole 8-column K steps (vector loads).
 hipError_t launch_gemm_tall(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,

@@ -156,14 +156,15 @@ def test_fp64_w_solve_block_boundaries(rb, k):
     assert np.array_equal(W[S], np.eye(k))
 
 
-@pytest.mark.parametrize("k", [128, 129, 200, 256, 257, 513, 259])
+@pytest.mark.parametrize("k", [129, 200, 256, 257, 320, 513, 259])
 def test_fp64_w_solve_super_blocks(rb, k):
-    """Fixed rank k around the 128-column super-blocks of the solve (one
-    whole super-block; one plus one column; a ragged second; two; two plus
-    one column; five; an odd k = k_max = 259, whose rows of W are loaded
-    element by element by the tall GEMM): the later super-blocks'
-    contribution goes through the tall GEMM into W's columns, and W still
-    matches X X_S^+ with W(S,:) = I."""
+    """Fixed rank k within and around the 256-column super-blocks of the
+    solve (two and a ragged third and fourth column block of one
+    super-block; one whole super-block; one plus one column; a ragged second;
+    three; an odd k = k_max = 259, whose rows of W are loaded element by
+    element by the tall GEMM): the later super-blocks' contribution goes
+    through the tall GEMM into W's columns, and W still matches X X_S^+ with
+    W(S,:) = I."""
     X = svd_matrix(2500, 600, geometric_spectrum(600, 0.99), seed=81)
     res = _run(rb, X, 1e-12, 32, 5, k_max=k, fixed_rank=True)
     assert res.k == k
