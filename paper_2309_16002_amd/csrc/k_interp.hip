@@ -60,14 +60,15 @@ typedef double d4w __attribute__((ext_vector_type(4)));
 //     (0,0..3), (1,1..3), (2,2..3), (3,3), four steps each).
 // Indices past the super-block's K columns are zero, so the solve needs no
 // masks and every fragment load is one contiguous, unconditional load.
+// (jb, kb >= jb) -> index 0..9 of a block of an upper triangular operand
+constexpr int regs_tri(int jb, int kb) { return jb * 4 - jb * (jb - 1) / 2 + (kb - jb); }
+
 template <int NJ>
 struct RegsFrags {
   static constexpr int kPairs = NJ * (NJ - 1) / 2;
   static constexpr int kPerSb = 64 * kPairs + 80 * NJ;
   static constexpr int pair(int I, int J) { return 64 * (I * (I - 1) / 2 + J); }
   static constexpr int diag(int J) { return 64 * kPairs + 80 * J; }
-  // (jb, kb >= jb) -> index 0..9
-  static constexpr int tri(int jb, int kb) { return jb * 4 - jb * (jb - 1) / 2 + (kb - jb); }
 };
 
 template <int NJ>
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(256) void k_trsm_regs_frags(const double* __restric
     const int t = (g % 40) / 4;
     s = g % 4;
     jb = t < 4 ? 0 : t < 7 ? 1 : t < 9 ? 2 : 3;
-    kb = jb + t - RF::tri(jb, jb);
+    kb = jb + t - regs_tri(jb, jb);
     X = g < 40 ? Bt : L1;
     neg = g >= 40;
     r0 = a + 64 * J; c0 = r0;
@@ -110,6 +111,75 @@ __global__ __launch_bounds__(256) void k_trsm_regs_frags(const double* __restric
   double v = 0.0;
   if (i < ni && j < nj) v = X[(r0 + i) * k + c0 + j];
   F[((int64_t)sb * RF::kPerSb + f) * 64 + lane] = neg ? -v : v;
+}
+
+// Ra -= L_1(I, J)^T W^T(I) for the later block I of the super-block: the K
+// steps over the KI live 16-row tiles of block I (past them both operands
+// are zero).  Fp: the pair's fragments.
+template <int KI, int NB>
+__device__ __forceinline__ void regs_pair(d4w (&Ra)[4][NB], const d4w (&Wi)[4][NB],
+                                          const double* Fp) {
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+    for (int kb = 0; kb < KI; ++kb)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double a = Fp[64 * (16 * jb + 4 * kb + s)];
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+          Ra[jb][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Wi[kb][n][s], Ra[jb][n], 0, 0, 0);
+      }
+}
+
+// The three products against the diagonal block D_J with KJ live 16-column
+// tiles (Fdi: the fragments of D_J^{-T}, then those of -D_J^T):
+//   W^T(J) = D_J^{-T} R^T,  T^T = R^T - D_J^T W^T(J) (in place of R^T),
+//   W^T(J) += D_J^{-T} T^T.
+// Both operands are upper triangular by 16 x 16 blocks (block row jb takes
+// the blocks kb >= jb) and zero at tiles >= KJ, so those rows of W^T(J) are
+// zero and those of T^T are not needed.
+template <int KJ, int NB>
+__device__ __forceinline__ void regs_diag(d4w (&Ra)[4][NB], d4w (&Wj)[4][NB],
+                                          const double* Fdi) {
+  const double* Fd = Fdi + 64 * 40;
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+    for (int n = 0; n < NB; ++n) Wj[jb][n] = (d4w){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int jb = 0; jb < KJ; ++jb)
+#pragma unroll
+    for (int kb = jb; kb < KJ; ++kb)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double a = Fdi[64 * (4 * regs_tri(jb, kb) + s)];
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+          Wj[jb][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Ra[kb][n][s], Wj[jb][n], 0, 0, 0);
+      }
+#pragma unroll
+  for (int jb = 0; jb < KJ; ++jb)
+#pragma unroll
+    for (int kb = jb; kb < KJ; ++kb)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double a = Fd[64 * (4 * regs_tri(jb, kb) + s)];
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+          Ra[jb][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Wj[kb][n][s], Ra[jb][n], 0, 0, 0);
+      }
+#pragma unroll
+  for (int jb = 0; jb < KJ; ++jb)
+#pragma unroll
+    for (int kb = jb; kb < KJ; ++kb)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double a = Fdi[64 * (4 * regs_tri(jb, kb) + s)];
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+          Wj[jb][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Ra[kb][n][s], Wj[jb][n], 0, 0, 0);
+      }
 }
 
 // Substitution with one refinement step for a super-block of at most 64 NJ
@@ -149,6 +219,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
   F += lane;
   const int nblk = (int)((K + 63) >> 6);  // <= NJ
+  // live 16-column tiles of the last block (every other block has four);
+  // the products of that block run in a form specialised to them
+  const int klast = (int)((K - 64 * (nblk - 1) + 15) >> 4);
   d4w Wt[NJ][4][NB];
   d4w Ra[4][NB];
 #pragma unroll
@@ -172,63 +245,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     for (int I = JB + 1; I < NJ; ++I) {
       if (I >= nblk) continue;
       const double* Fp = F + 64 * RF::pair(I, JB);
-#pragma unroll
-      for (int jb = 0; jb < 4; ++jb)
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb)
-#pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            const double a = Fp[64 * (16 * jb + 4 * kb + s)];
-#pragma unroll
-            for (int n = 0; n < NB; ++n)
-              Ra[jb][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Wt[I][kb][n][s], Ra[jb][n],
-                                                               0, 0, 0);
-          }
+      if (I < nblk - 1) {
+        regs_pair<4, NB>(Ra, Wt[I], Fp);
+      } else {
+        switch (klast) {
+          case 1: regs_pair<1, NB>(Ra, Wt[I], Fp); break;
+          case 2: regs_pair<2, NB>(Ra, Wt[I], Fp); break;
+          case 3: regs_pair<3, NB>(Ra, Wt[I], Fp); break;
+          default: regs_pair<4, NB>(Ra, Wt[I], Fp); break;
+        }
+      }
     }
-    const double* Fdi = F + 64 * RF::diag(JB);   // D_J^{-T}
-    const double* Fd = Fdi + 64 * 40;            // -D_J^T
-    // W^T(J) = D_J^{-T} R^T (block rows jb take the blocks kb >= jb)
-#pragma unroll
-    for (int jb = 0; jb < 4; ++jb) {
-#pragma unroll
-      for (int n = 0; n < NB; ++n) Wt[JB][jb][n] = (d4w){0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int kb = jb; kb < 4; ++kb)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const double a = Fdi[64 * (4 * RF::tri(jb, kb) + s)];
-#pragma unroll
-          for (int n = 0; n < NB; ++n)
-            Wt[JB][jb][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Ra[kb][n][s], Wt[JB][jb][n],
-                                                                 0, 0, 0);
-        }
+    const double* Fdi = F + 64 * RF::diag(JB);
+    if (JB < nblk - 1) {
+      regs_diag<4, NB>(Ra, Wt[JB], Fdi);
+    } else {
+      switch (klast) {
+        case 1: regs_diag<1, NB>(Ra, Wt[JB], Fdi); break;
+        case 2: regs_diag<2, NB>(Ra, Wt[JB], Fdi); break;
+        case 3: regs_diag<3, NB>(Ra, Wt[JB], Fdi); break;
+        default: regs_diag<4, NB>(Ra, Wt[JB], Fdi); break;
+      }
     }
-    // T^T = R^T - D_J^T W^T(J), in place of R^T
-#pragma unroll
-    for (int jb = 0; jb < 4; ++jb)
-#pragma unroll
-      for (int kb = jb; kb < 4; ++kb)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const double a = Fd[64 * (4 * RF::tri(jb, kb) + s)];
-#pragma unroll
-          for (int n = 0; n < NB; ++n)
-            Ra[jb][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Wt[JB][kb][n][s], Ra[jb][n], 0,
-                                                             0, 0);
-        }
-    // W^T(J) += D_J^{-T} T^T
-#pragma unroll
-    for (int jb = 0; jb < 4; ++jb)
-#pragma unroll
-      for (int kb = jb; kb < 4; ++kb)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const double a = Fdi[64 * (4 * RF::tri(jb, kb) + s)];
-#pragma unroll
-          for (int n = 0; n < NB; ++n)
-            Wt[JB][jb][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Ra[kb][n][s], Wt[JB][jb][n],
-                                                                 0, 0, 0);
-        }
     // W(r, j0 + j) = W^T(j, r)
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb)
