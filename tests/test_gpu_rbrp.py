@@ -175,6 +175,23 @@ def test_fp64_w_solve_super_blocks(rb, k):
     assert np.array_equal(W[S], np.eye(k))
 
 
+@pytest.mark.parametrize("k", [20, 40, 104, 148, 350])
+def test_fp64_w_solve_partial_last_block(rb, k):
+    """Fixed rank k whose last 64-column block holds two or three 16-column
+    tiles (20, 148: 20 columns; 40, 104: 40; 350: a second super-block of 94
+    columns whose last block has 30): the products of that block run in
+    their two- and three-tile forms, and W still matches X X_S^+ with
+    W(S,:) = I."""
+    X = svd_matrix(2500, 600, geometric_spectrum(600, 0.99), seed=83)
+    res = _run(rb, X, 1e-12, 32, 6, k_max=k, fixed_rank=True)
+    assert res.k == k
+    S = res.S.cpu().tolist()
+    W = res.W.cpu().numpy()
+    Wref = w_lstsq(X, S)
+    assert np.linalg.norm(W - Wref) <= 1e-10 * np.linalg.norm(Wref)
+    assert np.array_equal(W[S], np.eye(k))
+
+
 def test_fp64_w_solve_odd_leading_dimension(rb):
     """k = k_max = 131 (an odd leading dimension of W: the element-wise load
     path of the substitution) at fixed rank."""
