@@ -23,6 +23,8 @@
 // the filter, the small triangular factors of the W solve live in LDS when
 // they fit, and every loop over global data loads eight independent values
 // before using them.
+#include <type_traits>
+
 #include "rbrp_wg.h"
 
 namespace rbrp {
@@ -604,104 +606,114 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
         const int lane = tid & 63, wv = tid >> 6;
         double* wl_row = wrow + wv * 2 * kcapw;   // this wave's copy of the row of L
         double* wbuf = wl_row + kcapw;            // and of w, then of the residual e
-        constexpr int KS = kBatchMaxK / 64;
-        for (int64_t i = wv; i < m; i += kBT / 64) {
-          const T* lr = L + i * kcapw;
-  #pragma unroll
-          for (int s = 0; s < KS; ++s) {
-            const int64_t p = lane + 64 * s;
-            if (p < k) wl_row[p] = (double)lr[p];
-          }
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          double w[KS];
-  #pragma unroll
-          for (int s = 0; s < KS; ++s) w[s] = 0.0;
-          // w = l L_1^{-1}, four p per group: the group's loads are all
-          // issued before its FMAs (L_1^{-1} may be in global memory);
-          // each w[s] still sums over p in order
-          auto row_times_inv = [&](const double* lv) {
-            int64_t p = 0;
-            for (; p + 4 <= k; p += 4) {
-              double a4[4], iv[4][KS];
-  #pragma unroll
-              for (int u = 0; u < 4; ++u) {
-                a4[u] = lv[p + u];
-  #pragma unroll
+        // KS 64-column slots per lane, ceil(k / 64) of them: no slot's loads
+        // and FMAs issue fully masked (the sums and their order are the
+        // same for every KS that covers k)
+        auto rows_pass = [&](auto ks_tag) {
+          constexpr int KS = decltype(ks_tag)::value;
+          for (int64_t i = wv; i < m; i += kBT / 64) {
+            const T* lr = L + i * kcapw;
+    #pragma unroll
+            for (int s = 0; s < KS; ++s) {
+              const int64_t p = lane + 64 * s;
+              if (p < k) wl_row[p] = (double)lr[p];
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            double w[KS];
+    #pragma unroll
+            for (int s = 0; s < KS; ++s) w[s] = 0.0;
+            // w = l L_1^{-1}, four p per group: the group's loads are all
+            // issued before its FMAs (L_1^{-1} may be in global memory);
+            // each w[s] still sums over p in order
+            auto row_times_inv = [&](const double* lv) {
+              int64_t p = 0;
+              for (; p + 4 <= k; p += 4) {
+                double a4[4], iv[4][KS];
+    #pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                  a4[u] = lv[p + u];
+    #pragma unroll
+                  for (int s = 0; s < KS; ++s) {
+                    const int64_t j = lane + 64 * s;
+                    iv[u][s] = 0.0;
+                    if (j < k) iv[u][s] = Linv[(p + u) * k + j];
+                  }
+                }
+    #pragma unroll
+                for (int u = 0; u < 4; ++u)
+    #pragma unroll
+                  for (int s = 0; s < KS; ++s) w[s] += a4[u] * iv[u][s];
+              }
+              for (; p < k; ++p) {
+                const double a = lv[p];
+    #pragma unroll
                 for (int s = 0; s < KS; ++s) {
                   const int64_t j = lane + 64 * s;
-                  iv[u][s] = 0.0;
-                  if (j < k) iv[u][s] = Linv[(p + u) * k + j];
+                  if (j < k) w[s] += a * Linv[p * k + j];
                 }
               }
-  #pragma unroll
-              for (int u = 0; u < 4; ++u)
-  #pragma unroll
-                for (int s = 0; s < KS; ++s) w[s] += a4[u] * iv[u][s];
-            }
-            for (; p < k; ++p) {
-              const double a = lv[p];
-  #pragma unroll
+            };
+            row_times_inv(wl_row);
+            for (int it = 0; it < prm.refine; ++it) {
+              // e = l - w L_1
+    #pragma unroll
               for (int s = 0; s < KS; ++s) {
                 const int64_t j = lane + 64 * s;
-                if (j < k) w[s] += a * Linv[p * k + j];
+                if (j < k) wbuf[j] = w[s];
               }
+              __builtin_amdgcn_wave_barrier();
+              __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+              double ev[KS];
+    #pragma unroll
+              for (int s = 0; s < KS; ++s) {
+                const int64_t p = lane + 64 * s;
+                double v = 0.0;
+                if (p < k) {
+                  v = wl_row[p];
+                  int64_t j = p;
+                  for (; j + 4 <= k; j += 4) {
+                    double wv4[4], l4[4];
+    #pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                      wv4[u] = wbuf[j + u];
+                      l4[u] = L1[(j + u) * k + p];
+                    }
+    #pragma unroll
+                    for (int u = 0; u < 4; ++u) v -= wv4[u] * l4[u];
+                  }
+                  for (; j < k; ++j) v -= wbuf[j] * L1[j * k + p];
+                }
+                ev[s] = v;
+              }
+              __builtin_amdgcn_wave_barrier();
+              __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    #pragma unroll
+              for (int s = 0; s < KS; ++s) {
+                const int64_t p = lane + 64 * s;
+                if (p < k) wbuf[p] = ev[s];
+              }
+              __builtin_amdgcn_wave_barrier();
+              __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+              // w += e L_1^{-1}
+              row_times_inv(wbuf);
+              __builtin_amdgcn_wave_barrier();
+              __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             }
-          };
-          row_times_inv(wl_row);
-          for (int it = 0; it < prm.refine; ++it) {
-            // e = l - w L_1
-  #pragma unroll
+    #pragma unroll
             for (int s = 0; s < KS; ++s) {
               const int64_t j = lane + 64 * s;
-              if (j < k) wbuf[j] = w[s];
+              if (j < k) ds.W[i * ds.ldw + j] = w[s];
             }
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            double ev[KS];
-  #pragma unroll
-            for (int s = 0; s < KS; ++s) {
-              const int64_t p = lane + 64 * s;
-              double v = 0.0;
-              if (p < k) {
-                v = wl_row[p];
-                int64_t j = p;
-                for (; j + 4 <= k; j += 4) {
-                  double wv4[4], l4[4];
-  #pragma unroll
-                  for (int u = 0; u < 4; ++u) {
-                    wv4[u] = wbuf[j + u];
-                    l4[u] = L1[(j + u) * k + p];
-                  }
-  #pragma unroll
-                  for (int u = 0; u < 4; ++u) v -= wv4[u] * l4[u];
-                }
-                for (; j < k; ++j) v -= wbuf[j] * L1[j * k + p];
-              }
-              ev[s] = v;
-            }
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  #pragma unroll
-            for (int s = 0; s < KS; ++s) {
-              const int64_t p = lane + 64 * s;
-              if (p < k) wbuf[p] = ev[s];
-            }
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            // w += e L_1^{-1}
-            row_times_inv(wbuf);
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
           }
-  #pragma unroll
-          for (int s = 0; s < KS; ++s) {
-            const int64_t j = lane + 64 * s;
-            if (j < k) ds.W[i * ds.ldw + j] = w[s];
-          }
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        }
+        };
+        const int ksn = (int)((k + 63) >> 6);
+        if (ksn <= 1) rows_pass(std::integral_constant<int, 1>());
+        else if (ksn == 2) rows_pass(std::integral_constant<int, 2>());
+        else if (ksn == 3) rows_pass(std::integral_constant<int, 3>());
+        else rows_pass(std::integral_constant<int, 4>());
       }
     };
     if (wl) w_solve(As, As + k * k);
