@@ -611,13 +611,25 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
         // same for every KS that covers k)
         auto rows_pass = [&](auto ks_tag) {
           constexpr int KS = decltype(ks_tag)::value;
-          for (int64_t i = wv; i < m; i += kBT / 64) {
-            const T* lr = L + i * kcapw;
+          // the row of L is loaded one row ahead (clamped to row m - 1 past
+          // the end), so that its load overlaps the previous row's products
+          T lnext[KS];
+          auto load_row = [&](int64_t r) {
+            const T* lr = L + (r < m ? r : m - 1) * kcapw;
     #pragma unroll
             for (int s = 0; s < KS; ++s) {
               const int64_t p = lane + 64 * s;
-              if (p < k) wl_row[p] = (double)lr[p];
+              lnext[s] = lr[p < k ? p : k - 1];
             }
+          };
+          load_row(wv);
+          for (int64_t i = wv; i < m; i += kBT / 64) {
+    #pragma unroll
+            for (int s = 0; s < KS; ++s) {
+              const int64_t p = lane + 64 * s;
+              if (p < k) wl_row[p] = (double)lnext[s];
+            }
+            load_row(i + kBT / 64);
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             double w[KS];
