@@ -171,35 +171,51 @@ __device__ __forceinline__ void lds_project(double* __restrict__ As, int na, int
                                             double* __restrict__ C, double* __restrict__ Cs,
                                             int64_t cs_cap) {
   const int tid = threadIdx.x;
-  for (int64_t e = tid; e < k * na; e += kBT) {
-    const int64_t p = e / na, j = e - p * na;
+  // thread (p, g) forms C[p][jg .. jg + JG - 1], jg = JG g: one pass over
+  // row p of Qt serves JG rows of As (rows past na are clamped and unused)
+  constexpr int JG = 4;
+  const int ngj = (na + JG - 1) / JG;
+  for (int64_t e = tid; e < k * ngj; e += kBT) {
+    const int64_t p = e / ngj;
+    const int jg = (int)(e - p * ngj) * JG;
     const double* q = Qt + p * n8;
-    const double* a = As + j * n8;
-    double s0 = 0.0, s1 = 0.0;
+    const double* a[JG];
+#pragma unroll
+    for (int g = 0; g < JG; ++g) a[g] = As + (int64_t)min(jg + g, na - 1) * n8;
+    double s0[JG], s1[JG];
+#pragma unroll
+    for (int g = 0; g < JG; ++g) s0[g] = s1[g] = 0.0;
     // four chunks of Qt in flight per group (the loop is latency-bound:
-    // one workgroup per CU), then the remaining chunks one at a time
+    // one workgroup per CU), then the remaining chunks one at a time; each
+    // entry sums its even and its odd columns in order, then adds the two
     int64_t c0 = 0;
     for (; c0 + 4 * kChunk <= n8; c0 += 4 * kChunk) {
       double qv[4 * kChunk];
 #pragma unroll
       for (int u = 0; u < 4 * kChunk; ++u) qv[u] = q[c0 + u];
 #pragma unroll
-      for (int u = 0; u < 4 * kChunk; u += 2) {
-        s0 += qv[u] * a[c0 + u];
-        s1 += qv[u + 1] * a[c0 + u + 1];
-      }
+      for (int u = 0; u < 4 * kChunk; u += 2)
+#pragma unroll
+        for (int g = 0; g < JG; ++g) {
+          s0[g] += qv[u] * a[g][c0 + u];
+          s1[g] += qv[u + 1] * a[g][c0 + u + 1];
+        }
     }
     for (; c0 < n8; c0 += kChunk) {
       double qv[kChunk];
 #pragma unroll
       for (int u = 0; u < kChunk; ++u) qv[u] = q[c0 + u];
 #pragma unroll
-      for (int u = 0; u < kChunk; u += 2) {
-        s0 += qv[u] * a[c0 + u];
-        s1 += qv[u + 1] * a[c0 + u + 1];
-      }
+      for (int u = 0; u < kChunk; u += 2)
+#pragma unroll
+        for (int g = 0; g < JG; ++g) {
+          s0[g] += qv[u] * a[g][c0 + u];
+          s1[g] += qv[u + 1] * a[g][c0 + u + 1];
+        }
     }
-    C[p * na + j] = s0 + s1;
+#pragma unroll
+    for (int g = 0; g < JG; ++g)
+      if (jg + g < na) C[p * na + jg + g] = s0[g] + s1[g];
   }
   __syncthreads();
   if (na <= 16) lds_project_update<16>(As, na, n8, Qt, k, C, Cs, cs_cap);
