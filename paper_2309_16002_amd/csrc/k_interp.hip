@@ -6,8 +6,9 @@
 // All in FP64, by substitution as in Alg. 3:
 //   1. L_1 gathered from the rows S of L (strict upper part set to zero);
 //   2. the 64 x 64 diagonal blocks D_J of L_1 inverted (one workgroup each,
-//      by 16 x 16 blocks on FP64 MFMA) and the sub-diagonal blocks scaled,
-//      Bt(I, J) = -L_1(I, J) D_J^{-1} (one small MFMA GEMM per block column);
+//      by 16 x 16 blocks on FP64 MFMA); without refinement also the
+//      sub-diagonal blocks scaled, Bt(I, J) = -L_1(I, J) D_J^{-1} (one small
+//      MFMA GEMM per block column);
 //   3. W L_1 = L solved in place in W by blocked substitution over the block
 //      columns, from the last to the first (super-blocks of 256 columns: the
 //      later super-blocks' part by one tall MFMA GEMM, then each row's
@@ -60,6 +61,7 @@ typedef double d4w __attribute__((ext_vector_type(4)));
 //     (0,0..3), (1,1..3), (2,2..3), (3,3), four steps each).
 // Indices past the super-block's K columns are zero, so the solve needs no
 // masks and every fragment load is one contiguous, unconditional load.
+
 // (jb, kb >= jb) -> index 0..9 of a block of an upper triangular operand
 constexpr int regs_tri(int jb, int kb) { return jb * 4 - jb * (jb - 1) / 2 + (kb - jb); }
 
@@ -198,13 +200,13 @@ __device__ __forceinline__ void regs_diag(d4w (&Ra)[4][NB], d4w (&Wj)[4][NB],
 // No LDS, no barriers: each wave runs its own chain.  L may alias W (the
 // right sides of a super-block are then W's own columns): a wave reads its
 // rows of block J before it stores them.  With NJ = 4 the registers are
-// capped at two waves per SIMD (236 without spills): the compiler's own
-// choice, one wave per SIMD, ran the solve about 4 % slower on 200000 rows.
+// capped at two waves per SIMD (256 per lane, no spills): the compiler's
+// own choice, one wave per SIMD, ran the solve about 4 % slower on 200000
+// rows.
 template <typename TL, int NJ, int NB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_trsm_regs(int64_t M, int64_t K,
-                                                   const TL* L, int64_t ldl,
-                                                   const double* __restrict__ F,
-                                                   double* W, int64_t ldw) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_trsm_regs(
+    int64_t M, int64_t K, const TL* L, int64_t ldl, const double* __restrict__ F, double* W,
+    int64_t ldw) {
   typedef RegsFrags<NJ> RF;
   const int lane = threadIdx.x & 63, l16 = lane & 15, lhi = lane >> 4;
   const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * (16 * NB);
