@@ -460,9 +460,25 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
       const int nt = s_nt;
       if (nt <= 0) break;
       // ---- V^T: sampled rows of X in FP64 (LDS), projected twice against Q ----
-      for (int64_t e = tid; e < nt * n8; e += kBT) {
-        const int64_t j = e / n8, c = e - j * n8;
-        As[j * n8 + c] = c < n ? (double)X[idx[j] * ldx + c] : 0.0;
+      // kChunk elements per thread loaded before any is stored (clamped
+      // past the end: the load of a column >= n or an entry past the block
+      // reads an element of the block that is in range, and is not used)
+      for (int64_t e0 = tid; e0 < nt * n8; e0 += kChunk * kBT) {
+        double xv[kChunk];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+          const int64_t e = min(e0 + u * kBT, (int64_t)nt * n8 - 1);
+          const int64_t j = e / n8, c = e - j * n8;
+          xv[u] = (double)X[idx[j] * ldx + (c < n ? c : n - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+          const int64_t e = e0 + u * kBT;
+          if (e < nt * n8) {
+            const int64_t c = e % n8;
+            As[e] = c < n ? xv[u] : 0.0;
+          }
+        }
       }
       __syncthreads();
       if (tid < nt) {
