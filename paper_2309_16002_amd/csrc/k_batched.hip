@@ -230,9 +230,13 @@ __device__ __forceinline__ void lds_gram(const double* __restrict__ As, int na, 
     const double* a = As + (int64_t)i * n8;
     const double* b = As + (int64_t)j * n8;
     double s0 = 0.0, s1 = 0.0;
-    for (int64_t c = 0; c < n8; c += 2) {
-      s0 += a[c] * b[c];
-      s1 += a[c + 1] * b[c + 1];
+    // n8 is a multiple of kChunk: a chunk's LDS loads are issued together
+    for (int64_t c0 = 0; c0 < n8; c0 += kChunk) {
+#pragma unroll
+      for (int u = 0; u < kChunk; u += 2) {
+        s0 += a[c0 + u] * b[c0 + u];
+        s1 += a[c0 + u + 1] * b[c0 + u + 1];
+      }
     }
     G[(int64_t)i * ldg + j] = s0 + s1;
   }
@@ -483,7 +487,10 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
       __syncthreads();
       if (tid < nt) {
         double s = 0.0;
-        for (int64_t c = 0; c < n8; ++c) s += As[tid * n8 + c] * As[tid * n8 + c];
+        for (int64_t c0 = 0; c0 < n8; c0 += kChunk) {
+#pragma unroll
+          for (int u = 0; u < kChunk; ++u) s += As[tid * n8 + c0 + u] * As[tid * n8 + c0 + u];
+        }
         xs2[tid] = s;
       }
       __syncthreads();
