@@ -53,6 +53,19 @@ def test_workspace_size_is_host_only_and_validates(L):
     assert rb.workspace_size(100, 100, 16, k_max=101) == 0
 
 
+def test_workspace_grows_with_w_refinement_steps(L):
+    """The W solve's scratch in the workspace: one refinement step (the
+    default) adds the A operands of the register-resident substitution to
+    the plain solve's; further steps add a 64-column FP64 scratch per row
+    (rows rounded up to 128)."""
+    m, n, b = 50000, 600, 32
+    w0, w1, w2, w3 = (rb.workspace_size(m, n, b, "f32", w_refine=r) for r in range(4))
+    assert 0 < w0 < w1 < w2
+    assert w2 - w1 >= 8 * 64 * m
+    assert w3 == w2                                   # the scratch is reused per step
+    assert rb.workspace_size(m, n, b, "f32") == w1    # one step is the default
+
+
 def _call_id(L, X=1, dt=0, m=100, n=50, ldx=50, eps=0.1, b=8, S=1, k=True, W=None, ldw=0,
              ws=1, wsb=1 << 40, opt=None):
     kk = ctypes.c_int64(-7)
