@@ -591,7 +591,9 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
     else                                                                                   \
       deflate_rows<NBV, T, 2>(RT, mpad, m, n8, QfT, bq, L, kcapw, kS, bp, sel, t, d);      \
   } while (0)
-      if (nbt <= 8)
+      if (bp <= 4)
+        RBRP_DEFL(4);
+      else if (nbt <= 8)
         RBRP_DEFL(8);
       else if (nbt <= 16)
         RBRP_DEFL(16);
