@@ -591,7 +591,11 @@ __global__ __launch_bounds__(kBT) void k_rbrp_batched(
     else                                                                                   \
       deflate_rows<NBV, T, 2>(RT, mpad, m, n8, QfT, bq, L, kcapw, kS, bp, sel, t, d);      \
   } while (0)
-      if (bp <= 4)
+      if (bp <= 1)
+        RBRP_DEFL(1);
+      else if (bp <= 2)
+        RBRP_DEFL(2);
+      else if (bp <= 4)
         RBRP_DEFL(4);
       else if (nbt <= 8)
         RBRP_DEFL(8);
