@@ -218,7 +218,9 @@ __device__ __forceinline__ void lds_project(double* __restrict__ As, int na, int
       if (jg + g < na) C[p * na + jg + g] = s0[g] + s1[g];
   }
   __syncthreads();
-  if (na <= 16) lds_project_update<16>(As, na, n8, Qt, k, C, Cs, cs_cap);
+  if (na <= 4) lds_project_update<4>(As, na, n8, Qt, k, C, Cs, cs_cap);
+  else if (na <= 8) lds_project_update<8>(As, na, n8, Qt, k, C, Cs, cs_cap);
+  else if (na <= 16) lds_project_update<16>(As, na, n8, Qt, k, C, Cs, cs_cap);
   else lds_project_update<kBatchMaxB>(As, na, n8, Qt, k, C, Cs, cs_cap);
 }
 
